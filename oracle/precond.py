@@ -1,0 +1,116 @@
+"""Oracle preconditioners.  TEST INFRASTRUCTURE ONLY.
+
+* ``ML``  the inexact block lower-triangular preconditioner M_L of eq. (8),
+  applied exactly as Algorithm 1: solve on the host domain with Q_OO
+  (V-cycles on S~ of eq. (7)), update the fracture residual with A_GO, solve
+  on the fracture block with Q_GG (V-cycles on A_GG), concatenate.
+* ``exact_block_lower_dense``  B_L = (D L)^{-1} of Section 3.2 (exact Schur
+  complement, exact inverses), and ``approx_block_lower_dense`` B~_L (S~
+  with exact inverses), both dense, for the spectral checks of Section 3.2.
+* ``block_diag_dense`` / ``block_upper_dense``  B_D = D^{-1} and
+  B_U = (U D)^{-1} of Section 3.2, dense.
+
+Pins: M_L equals the dense block lower-triangular solve with the same Q's;
+with exact blocks, GMRES converges in at most two iterations because
+A B_L = U is unipotent with (U - I)^2 = 0 (Section 3.2 states its
+eigenvalues are all one); with a diagonal fracture block the same holds for
+B~_L (tests/test_oracle_precond.py).
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import amg, blocks
+
+
+class ML:
+    """M_L of eq. (8) with Q_OO, Q_GG = ``cycles`` SA-AMG V-cycles."""
+
+    def __init__(self, A, part, cycles: int = 1, amg_opts: Optional[amg.AMGOptions] = None):
+        self.n = A.shape[0]
+        (self.omega, self.gamma, self.Aoo, self.Aog,
+         self.Ago, self.Agg) = blocks.split(A, part)
+        self.S = blocks.approx_schur(self.Aoo, self.Aog, self.Ago, self.Agg)
+        self.cycles = cycles
+        self.H_omega = amg.setup(self.S, amg_opts)
+        self.H_gamma = amg.setup(self.Agg, amg_opts) if self.gamma.size else None
+
+    def q_omega(self, r):
+        return amg.apply_cycles(self.H_omega, r, self.cycles)
+
+    def q_gamma(self, r):
+        return amg.apply_cycles(self.H_gamma, r, self.cycles)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        """Algorithm 1."""
+        r_o = r[self.omega]
+        z_o = self.q_omega(r_o)                      # solve in the domain
+        z = np.empty_like(r)
+        z[self.omega] = z_o
+        if self.gamma.size:
+            r_g = r[self.gamma] - self.Ago @ z_o     # update the interface residual
+            z[self.gamma] = self.q_gamma(r_g)        # solve on the interface
+        return z
+
+
+def _dense(M):
+    return np.asarray(sp.csr_matrix(M).todense())
+
+
+def exact_block_lower_dense(A, part):
+    """B_L = [[S, 0], [A_GO, A_GG]]^{-1} in the original unknown order."""
+    omega, gamma, Aoo, Aog, Ago, Agg = blocks.split(A, part)
+    S = blocks.exact_schur_dense(Aoo, Aog, Ago, Agg)
+    return _lower_inverse(omega, gamma, S, _dense(Ago), _dense(Agg))
+
+
+def approx_block_lower_dense(A, part):
+    """B~_L = [[S~, 0], [A_GO, A_GG]]^{-1} in the original unknown order."""
+    omega, gamma, Aoo, Aog, Ago, Agg = blocks.split(A, part)
+    S = _dense(blocks.approx_schur(Aoo, Aog, Ago, Agg))
+    return _lower_inverse(omega, gamma, S, _dense(Ago), _dense(Agg))
+
+
+def _lower_inverse(omega, gamma, S, Ago, Agg):
+    n = omega.size + gamma.size
+    T = np.zeros((n, n))
+    perm = np.concatenate([omega, gamma])
+    no = omega.size
+    T[:no, :no] = S
+    T[no:, :no] = Ago
+    T[no:, no:] = Agg
+    Tinv = np.linalg.inv(T)
+    B = np.zeros((n, n))
+    B[np.ix_(perm, perm)] = Tinv
+    return B
+
+
+def block_diag_dense(A, part):
+    """B_D = D^{-1} = blockdiag(S, A_GG)^{-1}."""
+    omega, gamma, Aoo, Aog, Ago, Agg = blocks.split(A, part)
+    S = blocks.exact_schur_dense(Aoo, Aog, Ago, Agg)
+    n = omega.size + gamma.size
+    B = np.zeros((n, n))
+    B[np.ix_(omega, omega)] = np.linalg.inv(S)
+    B[np.ix_(gamma, gamma)] = np.linalg.inv(_dense(Agg))
+    return B
+
+
+def block_upper_dense(A, part):
+    """B_U = (U D)^{-1} with U D = [[S, A_OG], [0, A_GG]]."""
+    omega, gamma, Aoo, Aog, Ago, Agg = blocks.split(A, part)
+    S = blocks.exact_schur_dense(Aoo, Aog, Ago, Agg)
+    n = omega.size + gamma.size
+    no = omega.size
+    T = np.zeros((n, n))
+    T[:no, :no] = S
+    T[:no, no:] = _dense(Aog)
+    T[no:, no:] = _dense(Agg)
+    perm = np.concatenate([omega, gamma])
+    B = np.zeros((n, n))
+    B[np.ix_(perm, perm)] = np.linalg.inv(T)
+    return B

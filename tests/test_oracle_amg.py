@@ -1,0 +1,194 @@
+"""Pins of the oracle smoothed-aggregation AMG (Section 3.3 reading)."""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import amg
+from oracle import assembly as oa
+from oracle import blocks as ob
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    data = np.loadtxt(os.path.join(GOLDEN, name), comments="#", dtype=np.int64)
+    return data[:, 1]
+
+
+def _chain(n):
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tolil()
+    A[0, 0] = A[n - 1, n - 1] = 1.0
+    return A.tocsr()
+
+
+def _grid(m):
+    T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+    I = sp.identity(m)
+    return sp.csr_matrix(sp.kron(I, T) + sp.kron(T, I))
+
+
+def _weak_star():
+    A = 10.0 * np.eye(5)
+    for i, j, v in [(0, 1, -5.0), (1, 2, -0.5), (2, 3, -5.0), (3, 4, -5.0)]:
+        A[i, j] = A[j, i] = v
+    return sp.csr_matrix(A)
+
+
+def _pass2_graph():
+    edges = [(0, 1), (1, 2), (2, 5), (3, 4), (4, 5)]
+    A = np.zeros((6, 6))
+    for i, j in edges:
+        A[i, j] = A[j, i] = -1.0
+    A[np.diag_indices(6)] = -A.sum(axis=1) + 1.0
+    return sp.csr_matrix(A)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("aggregation_pass2_snapshot.txt", _pass2_graph),
+    ("aggregation_chain7.txt", lambda: _chain(7)),
+    ("aggregation_grid4x4.txt", lambda: _grid(4)),
+    ("aggregation_weak_star.txt", _weak_star),
+])
+def test_aggregates_match_hand_computation(name, make):
+    agg, n_agg = amg.aggregate(amg.strong_neighbours(make(), 0.08))
+    assert np.array_equal(agg, _golden(name))
+    assert n_agg == int(_golden(name).max()) + 1
+
+
+def test_node_without_strong_neighbours_stays_out():
+    A = np.array([[10.0, -0.1, 0.0], [-0.1, 2.0, -1.0], [0.0, -1.0, 2.0]])
+    agg, n_agg = amg.aggregate(amg.strong_neighbours(sp.csr_matrix(A), 0.08))
+    assert agg[0] == -1 and agg[1] == agg[2] == 0 and n_agg == 1
+
+
+def _system_blocks(sc):
+    A, b, part = oa.assemble(sc)
+    _, _, Aoo, Aog, Ago, Agg = ob.split(A, part)
+    return ob.approx_schur(Aoo, Aog, Ago, Agg), Agg
+
+
+@pytest.mark.parametrize("make", [
+    lambda: _system_blocks(synth.grid_2d_four_lines(32))[0],
+    lambda: _system_blocks(synth.regular_3d(n=10, seed=3))[0],
+    lambda: _system_blocks(synth.regular_3d(n=10, seed=3))[1],
+])
+def test_tentative_orthonormal_and_coarse_symmetric(make):
+    A = make()
+    H = amg.setup(A, amg.AMGOptions(max_coarse=20))
+    assert len(H.levels) >= 2
+    for lv in H.levels[:-1]:
+        Pt = amg.tentative(lv.agg, int(lv.agg.max()) + 1)
+        G = (Pt.T @ Pt).toarray()
+        assert np.allclose(G, np.eye(G.shape[0]), atol=1e-15)
+        assert (lv.R != lv.P.T).nnz == 0
+    for lv in H.levels[1:]:
+        D = (lv.A - lv.A.T)
+        assert abs(D).max() <= 1e-13 * abs(lv.A).max()
+
+
+def test_near_nullspace_preserved_on_neumann_graph():
+    """Pure-Neumann graph Laplacian (A 1 = 0): with every node aggregated,
+    c_a = sqrt(|agg_a|) gives P_tent c = 1, hence P c = 1 and A_c c = 0."""
+    m = 9
+    A = _grid(m).tolil()
+    for i in range(m * m):  # turn the Dirichlet-like grid into a pure-Neumann one
+        A[i, i] = 0.0
+        A[i, i] = -A[i].sum()
+    A = sp.csr_matrix(A)
+    assert np.allclose(A @ np.ones(m * m), 0.0)
+    agg, n_agg = amg.aggregate(amg.strong_neighbours(A, 0.08))
+    assert np.all(agg >= 0)
+    c = np.sqrt(np.bincount(agg).astype(float))
+    Pt = amg.tentative(agg, n_agg)
+    P = amg.smoothed_prolongator(A, Pt)
+    assert np.allclose(Pt @ c, 1.0, atol=1e-14)
+    assert np.allclose(P @ c, 1.0, atol=1e-13)
+    Ac = P.T @ A @ P
+    assert np.allclose(Ac @ c, 0.0, atol=1e-12)
+
+
+def test_one_level_hierarchy_is_exact_solve():
+    S, Agg = _system_blocks(synth.tiny_2d(10))
+    H = amg.setup(S)
+    assert len(H.levels) == 1 and H.coarse_dense is not None
+    b = synth.random_vector(S.shape[0], 1)
+    x = amg.vcycle(H, b)
+    assert np.allclose(S @ x, b, rtol=0, atol=1e-12 * np.linalg.norm(b))
+
+
+def _operator(H, n):
+    return np.column_stack([amg.vcycle(H, e) for e in np.eye(n)])
+
+
+def test_two_level_cycle_is_textbook_two_grid():
+    """I - B A = (I - D^-1 A)(I - P A_c^-1 R A)(I - D^-1 A), with D the l1
+    diagonal, for a two-level hierarchy with an exact coarse solve."""
+    S, _ = _system_blocks(synth.grid_2d_four_lines(24))
+    n = S.shape[0]
+    H = amg.setup(S, amg.AMGOptions(max_levels=2))
+    assert len(H.levels) == 2 and H.coarse_dense is not None
+    A = S.toarray()
+    lv = H.levels[0]
+    P, R = lv.P.toarray(), lv.R.toarray()
+    Ac = H.levels[1].A.toarray()
+    I = np.eye(n)
+    Sm = I - A / lv.d_l1[:, None]
+    E = Sm @ (I - P @ np.linalg.solve(Ac, R @ A)) @ Sm
+    B = _operator(H, n)
+    assert np.allclose(I - B @ A, E, atol=1e-10)
+
+
+def test_vcycle_operator_symmetric_positive_definite():
+    S, _ = _system_blocks(synth.tiny_3d(6, seed=2))
+    n = S.shape[0]
+    H = amg.setup(S, amg.AMGOptions(max_coarse=10))
+    assert len(H.levels) >= 3
+    B = _operator(H, n)
+    assert np.allclose(B, B.T, atol=1e-12 * np.abs(B).max())
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0.0
+
+
+def test_coarsest_without_dense_uses_l1_jacobi():
+    S, _ = _system_blocks(synth.tiny_2d(12))
+    H = amg.setup(S, amg.AMGOptions(max_dense=10, max_levels=1))
+    assert H.coarse_dense is None
+    b = synth.random_vector(S.shape[0], 4)
+    x = amg.vcycle(H, b)
+    d = H.levels[0].d_l1
+    y = b / d
+    for _ in range(3):
+        y = y + (b - S @ y) / d
+    assert np.array_equal(x, y)
+
+
+def test_stopping_rules():
+    S, _ = _system_blocks(synth.regular_3d(n=12, seed=1))
+    H = amg.setup(S)
+    sizes = H.sizes()
+    assert sizes[-1] <= 400 or len(sizes) == 10
+    assert all(sizes[i + 1] <= 0.9 * sizes[i] for i in range(len(sizes) - 1))
+    assert all(s > 400 for s in sizes[:-1])
+
+
+def test_smoothed_prolongator_closed_form_chain():
+    """Chain of 7 with aggregates {0,1}, {2,3,4}, {5,6}: D = diag(A) =
+    (1,2,2,2,2,2,1), Gershgorin rho = 2, omega = 2/3.  Expanding
+    P = P_tent - omega D^-1 A P_tent by hand gives the columns below."""
+    A = _chain(7)
+    agg, n_agg = amg.aggregate(amg.strong_neighbours(A, 0.08))
+    P = amg.smoothed_prolongator(A, amg.tentative(agg, n_agg)).toarray()
+    s2, s3 = np.sqrt(2.0), np.sqrt(3.0)
+    expect = np.zeros((7, 3))
+    expect[:3, 0] = [1 / s2, 2 / (3 * s2), 1 / (3 * s2)]
+    expect[1:6, 1] = [1 / (3 * s3), 2 / (3 * s3), 1 / s3, 2 / (3 * s3), 1 / (3 * s3)]
+    expect[4:, 2] = [1 / (3 * s2), 2 / (3 * s2), 1 / s2]
+    assert np.allclose(P, expect, rtol=0, atol=1e-15)
+
+
+def test_l1_diagonal_definition():
+    A = sp.csr_matrix(np.array([[4.0, -1.5, 0.0], [-1.5, 3.0, 2.0], [0.0, 2.0, -5.0]]))
+    assert np.array_equal(amg.l1_diagonal(A), [5.5, 6.5, 7.0])
