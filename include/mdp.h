@@ -1,0 +1,216 @@
+/*
+ * mdp.h - C ABI of the MI355X solver for mixed-dimensional scalar elliptic
+ * systems (Hu, Keilegavlen, Nordbotten 2022, "Effective Preconditioners for
+ * Mixed-Dimensional Scalar Elliptic Problems").
+ *
+ * The library solves A p = f for the 2x2 host/fracture block system of
+ * eq. (4) with flexible GMRES, right-preconditioned (Section 3.2) by the
+ * inexact block lower-triangular preconditioner M_L of eq. (8), applied as
+ * Algorithm 1: Q_OO = smoothed-aggregation AMG V-cycles on the approximate
+ * Schur complement S~ of eq. (7), the fracture residual update with A_GO,
+ * and Q_GG = V-cycles on A_GG (Section 3.3).
+ *
+ * Conventions for every call:
+ *  - Sparse inputs are 0-based CSR in HOST memory, int32 indices, FP64 values.
+ *    The library copies what it needs; it never keeps caller pointers.
+ *  - Vectors passed to solve calls are FP64 in DEVICE memory, in the
+ *    caller's unknown order (the library permutes to [Omega; Gamma]
+ *    internally).
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Blocking calls
+ *    synchronise that stream before returning.
+ *  - Return value: MDP_OK (0) or a positive status, or a negative error code.
+ *    mdp_last_error() gives a message for the last failure on this thread.
+ *  - A handle may be used by one thread at a time.
+ */
+#ifndef MDP_H
+#define MDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status and error codes ---------------------------------------------- */
+#define MDP_OK 0
+#define MDP_NOT_CONVERGED 1 /* iteration budget spent; x holds the last iterate */
+#define MDP_PENDING 2       /* mdp_poll: request not finished yet              */
+#define MDP_EINVAL (-1)     /* bad argument, malformed CSR, part not in {0,1}   */
+#define MDP_ENONPOS_DIAG (-2) /* a diagonal entry <= 0 (the smoother divides)  */
+#define MDP_ESINGULAR (-3)  /* coarsest dense factorisation failed             */
+#define MDP_ENAN (-4)       /* NaN/Inf in the input or during the iteration    */
+#define MDP_ENOMEM (-5)     /* device allocation failed / budget exceeded       */
+#define MDP_EHIP (-6)       /* HIP runtime error                                */
+#define MDP_EBUSY (-7)      /* server full: request refused                      */
+
+/* ---- precision modes (options.precision) --------------------------------- */
+#define MDP_FP64 0  /* everything in FP64                                         */
+#define MDP_MIXED 1 /* preconditioner (S~, A_GG, A_GO, P, R, smoother) in FP32;
+                       outer FGMRES residual, orthogonalisation and the coarsest
+                       dense solve in FP64                                        */
+
+/* ---- option flags (options.flags) ---------------------------------------- */
+#define MDP_USE_X0 1u      /* mdp_solve: start from the x passed in, not zero  */
+#define MDP_HOST_ONLY 2u   /* mdp_setup: build the hierarchy on the host only
+                              (no device upload); for inspection on machines
+                              without a GPU.  Solve calls then return EINVAL. */
+
+/* ---- operators for mdp_apply ---------------------------------------------- */
+#define MDP_OP_A 0    /* y = A x, the full system matrix (FP64)                     */
+#define MDP_OP_ML 1   /* y = M_L x, one preconditioner application (Algorithm 1)    */
+#define MDP_OP_QOO 2  /* y = Q_OO x on the Omega block (x, y of length n_Omega)     */
+#define MDP_OP_QGG 3  /* y = Q_GG x on the Gamma block (x, y of length n_Gamma)     */
+
+/* ---- blocks / matrices for inspection ------------------------------------- */
+#define MDP_BLOCK_OMEGA 0 /* hierarchy built on S~ (eq. 7)   */
+#define MDP_BLOCK_GAMMA 1 /* hierarchy built on A_GG (eq. 4) */
+#define MDP_MAT_A 0
+#define MDP_MAT_P 1
+#define MDP_MAT_R 2
+
+typedef struct mdp_handle mdp_handle;
+typedef struct mdp_server mdp_server;
+
+/* The system matrix A of eq. (4), any unknown order. */
+typedef struct {
+  int32_t n;              /* rows = columns                                */
+  int64_t nnz;            /* row_ptr[n]                                    */
+  const int32_t *row_ptr; /* n + 1 entries, non-decreasing, row_ptr[0] = 0 */
+  const int32_t *col;     /* nnz entries in [0, n)                          */
+  const double *val;      /* nnz entries                                    */
+} mdp_csr;
+
+typedef struct {
+  int32_t precision;      /* MDP_FP64 (default) or MDP_MIXED                          */
+  int32_t vcycles;        /* V-cycles per Q application (default 1, Section 3.3)      */
+  int32_t pre_sweeps;     /* l1-Jacobi sweeps before the coarse correction (1)        */
+  int32_t post_sweeps;    /* l1-Jacobi sweeps after it (1)                             */
+  double strength_theta;  /* SA strength threshold (0.08)                              */
+  int32_t max_coarse;     /* stop coarsening at or below this size (400)               */
+  int32_t max_dense;      /* coarsest solved densely up to this size (2000)            */
+  int32_t max_levels;     /* at most this many levels per hierarchy (10)               */
+  int32_t restart;        /* FGMRES restart length m (64, at most 64)                  */
+  int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
+  double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
+  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY                                */
+} mdp_options;
+
+typedef struct {
+  int32_t iters;          /* preconditioner applications                       */
+  int32_t restarts;       /* FGMRES cycles after the first                     */
+  int32_t converged;      /* 1 if ||b - A x|| <= rtol ||b||                    */
+  int32_t status;         /* MDP_OK, MDP_NOT_CONVERGED or a negative error     */
+  double rel_res_true;    /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+  double rel_res_est;     /* the Arnoldi estimate |g_{k+1}| / ||b||            */
+  double setup_ms;        /* host + upload time of mdp_setup for this handle  */
+  double solve_ms;        /* wall time of this solve                            */
+} mdp_stats;
+
+/* Fill *opt with the defaults listed above.  Returns MDP_OK or MDP_EINVAL
+ * (NULL). */
+int mdp_options_default(mdp_options *opt);
+
+/* Build the solver for A (eq. 4).  part[i] = 0 marks a host-domain (Omega)
+ * unknown, 1 a fracture/interface (Gamma) unknown.  Setup (host C++):
+ * stable [Omega; Gamma] permutation, the four blocks, S~ of eq. (7) with
+ * diag(A_GG), SA-AMG hierarchies on S~ and A_GG (Section 3.3), dense inverse
+ * of each coarsest level, then one upload to the device on hip_stream.
+ * n_Gamma = 0 is allowed (M_L is then the AMG on A_OO).  A nonsymmetric A is
+ * accepted (the paper does not rely on A_OG = A_GO^T).
+ * Errors: EINVAL (NULL, n <= 0, malformed CSR, part not 0/1, bad options),
+ * ENONPOS_DIAG, ENAN (non-finite value), ESINGULAR, ENOMEM, EHIP.
+ * On success *out owns all device memory until mdp_destroy. */
+int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt,
+              void *hip_stream, mdp_handle **out);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+int mdp_destroy(mdp_handle *h);
+
+/* Solve A x_k = b_k for nrhs right-hand sides stored column-major with
+ * leading dimension ld (>= n) in device memory.  Zero initial guess unless
+ * the handle's options carry MDP_USE_X0.  stats (nrhs entries, may be NULL)
+ * receives the per-column result.  Returns MDP_OK when every column
+ * converged, MDP_NOT_CONVERGED when any did not (x holds the last iterate),
+ * or a negative error (ENAN for NaN/Inf in b or a breakdown producing one).
+ * Synchronises hip_stream before returning. */
+int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
+              int64_t ld, void *hip_stream, mdp_stats *stats);
+
+/* Solve several independent systems together: system s has nrhs[s]
+ * right-hand sides in b_dev[s] / x_dev[s] (column-major, leading dimension
+ * its own n).  All handles must share one precision.  Every (system, rhs)
+ * pair advances in lock step; each gets the same answer as a solve of its
+ * own (per-pair reductions never mix pairs).  stats has sum(nrhs) entries in
+ * system-major order.  Synchronises hip_stream. */
+int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b_dev,
+                    double *const *x_dev, const int32_t *nrhs, void *hip_stream,
+                    mdp_stats *stats);
+
+/* One operator application y = op(x) with device vectors (see MDP_OP_*):
+ * the building blocks of the solve, exposed for verification.
+ * Synchronises hip_stream. */
+int mdp_apply(mdp_handle *h, int32_t op, const double *x_dev, double *y_dev, void *hip_stream);
+
+/* ---- introspection (host memory; works for MDP_HOST_ONLY handles) ---------- */
+
+/* Sizes: n, n_Omega, n_Gamma and the number of levels of each hierarchy. */
+int mdp_info(const mdp_handle *h, int32_t *n, int32_t *n_omega, int32_t *n_gamma,
+             int32_t *levels_omega, int32_t *levels_gamma);
+
+/* Shape of one hierarchy matrix (block = MDP_BLOCK_*, mat = MDP_MAT_*, level
+ * 0 = finest; P and R do not exist on the coarsest level). */
+int mdp_level_shape(const mdp_handle *h, int32_t block, int32_t level, int32_t mat,
+                    int32_t *rows, int32_t *cols, int64_t *nnz);
+
+/* Copy one hierarchy matrix (FP64, as built on the host) into caller
+ * buffers sized from mdp_level_shape.  Columns are sorted within rows. */
+int mdp_level_export(const mdp_handle *h, int32_t block, int32_t level, int32_t mat,
+                     int32_t *row_ptr, int32_t *col, double *val);
+
+/* Aggregate label per node of a level (-1 = left unaggregated), n entries. */
+int mdp_level_aggregates(const mdp_handle *h, int32_t block, int32_t level, int32_t *agg);
+
+/* ---- serving: continuous batching over resident hierarchies -------------- */
+
+/* A server owns a progress thread and a device stream.  mem_budget_bytes
+ * bounds the Krylov workspace of admitted requests (0 = no bound);
+ * max_slots bounds how many requests are on the device at once. */
+int mdp_server_create(size_t mem_budget_bytes, int32_t max_slots, mdp_server **out);
+
+/* Make a handle servable.  Its hierarchy stays resident in device memory. */
+int mdp_server_register(mdp_server *srv, mdp_handle *h);
+
+/* Enqueue one solve (nrhs columns, leading dimension n).  Returns at once
+ * with a ticket; b/x must stay valid and untouched until mdp_poll reports a
+ * final code.  EBUSY if the queue is full. */
+int mdp_submit(mdp_server *srv, mdp_handle *h, const double *b_dev, double *x_dev,
+               int32_t nrhs, uint64_t *ticket);
+
+/* MDP_PENDING while the request runs; afterwards its final code, with
+ * *stats (one entry per rhs, may be NULL) filled.  A ticket can be polled to
+ * completion once. */
+int mdp_poll(mdp_server *srv, uint64_t ticket, mdp_stats *stats);
+
+/* Stop the progress thread after draining admitted requests; frees the
+ * server (handles stay owned by the caller). */
+int mdp_server_destroy(mdp_server *srv);
+
+/* ---- memory ----------------------------------------------------------- */
+
+/* Route device allocations through the caller's allocator (e.g. a framework
+ * caching allocator).  alloc(size, ctx) returns device memory or NULL;
+ * free_(ptr, ctx) releases it.  Pass NULLs to restore hipMalloc/hipFree.
+ * Affects allocations made after the call. */
+int mdp_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *mdp_last_error(void);
+
+/* Library version string. */
+const char *mdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDP_H */

@@ -1,0 +1,284 @@
+// C ABI entry points (include/mdp.h): argument checking, error translation
+// and handle lifecycle around the host setup and the device solver.
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "mdp.h"
+#include "solver.hpp"
+
+namespace mdp {
+
+namespace {
+thread_local std::string g_last_error;
+std::mutex g_hook_mu;
+AllocHook g_hook;
+}  // namespace
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+AllocHook current_alloc_hook() {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  return g_hook;
+}
+
+void set_alloc_hook(const AllocHook &h) {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hook = h;
+}
+
+void *dev_alloc(size_t bytes, const AllocHook &h) {
+  if (h.alloc) return h.alloc(bytes, h.ctx);
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void *p, const AllocHook &h) {
+  if (h.free_)
+    h.free_(p, h.ctx);
+  else
+    (void)hipFree(p);
+}
+
+int check_options(const mdp_options &o) {
+  auto bad = [](const char *m) {
+    set_last_error(m);
+    return MDP_EINVAL;
+  };
+  if (o.precision != MDP_FP64 && o.precision != MDP_MIXED) return bad("precision must be MDP_FP64 or MDP_MIXED");
+  if (o.vcycles < 1) return bad("vcycles must be >= 1");
+  if (o.pre_sweeps != 1 || o.post_sweeps != 1) return bad("only one pre- and one post-smoothing sweep are supported");
+  if (!(o.strength_theta >= 0.0)) return bad("strength_theta must be >= 0");
+  if (o.max_coarse < 1 || o.max_dense < 0 || o.max_levels < 1) return bad("bad coarsening limits");
+  if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
+  if (o.max_iter < 0) return bad("max_iter must be >= 0");
+  if (!(o.rtol > 0.0)) return bad("rtol must be > 0");
+  return MDP_OK;
+}
+
+}  // namespace mdp
+
+using namespace mdp;
+
+#define API_BEGIN try {
+#define API_END                                                   \
+  }                                                               \
+  catch (const mdp::Error &e) {                                   \
+    set_last_error(e.msg);                                        \
+    return e.code;                                                \
+  }                                                               \
+  catch (const mdp::SetupError &e) {                              \
+    set_last_error(e.msg);                                        \
+    return e.code;                                                \
+  }                                                               \
+  catch (const std::bad_alloc &) {                                \
+    set_last_error("host allocation failed");                     \
+    return MDP_ENOMEM;                                            \
+  }                                                               \
+  catch (const std::exception &e) {                               \
+    set_last_error(e.what());                                     \
+    return MDP_EINVAL;                                            \
+  }
+
+extern "C" {
+
+int mdp_options_default(mdp_options *o) {
+  if (!o) {
+    set_last_error("NULL options");
+    return MDP_EINVAL;
+  }
+  o->precision = MDP_FP64;
+  o->vcycles = 1;
+  o->pre_sweeps = 1;
+  o->post_sweeps = 1;
+  o->strength_theta = 0.08;
+  o->max_coarse = 400;
+  o->max_dense = 2000;
+  o->max_levels = 10;
+  o->restart = 64;
+  o->max_iter = 1000;
+  o->rtol = 1e-8;
+  o->flags = 0;
+  return MDP_OK;
+}
+
+int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt, void *hip_stream, mdp_handle **out) {
+  API_BEGIN
+  if (!out) {
+    set_last_error("NULL output handle");
+    return MDP_EINVAL;
+  }
+  *out = nullptr;
+  mdp_options o;
+  if (opt)
+    o = *opt;
+  else
+    mdp_options_default(&o);
+  const int rc = check_options(o);
+  if (rc != MDP_OK) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto h = std::make_unique<mdp_handle>();
+  h->s.opt = o;
+  build_host_system(A, part, o, h->s.host);
+  h->s.n = h->s.host.n;
+  h->s.n_o = h->s.host.n_o;
+  h->s.n_g = h->s.host.n_g;
+  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h.release();
+  return MDP_OK;
+  API_END
+}
+
+int mdp_destroy(mdp_handle *h) {
+  API_BEGIN
+  delete h;
+  return MDP_OK;
+  API_END
+}
+
+int mdp_solve(mdp_handle *h, const double *b, double *x, int32_t nrhs, int64_t ld, void *hip_stream,
+              mdp_stats *stats) {
+  API_BEGIN
+  if (!h || !b || !x || nrhs < 0 || (nrhs > 1 && ld < h->s.n)) {
+    set_last_error("bad solve arguments");
+    return MDP_EINVAL;
+  }
+  if (!h->s.on_device) {
+    set_last_error("handle was set up host-only");
+    return MDP_EINVAL;
+  }
+  int worst = MDP_OK;
+  for (int32_t k = 0; k < nrhs; ++k) {
+    mdp_stats st{};
+    const int rc = h->s.solve(b + k * ld, x + k * ld, static_cast<hipStream_t>(hip_stream), &st);
+    if (stats) stats[k] = st;
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+  }
+  return worst;
+  API_END
+}
+
+int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b, double *const *x,
+                    const int32_t *nrhs, void *hip_stream, mdp_stats *stats) {
+  API_BEGIN
+  if (!hs || !b || !x || !nrhs || nsys < 0) {
+    set_last_error("bad batch arguments");
+    return MDP_EINVAL;
+  }
+  int worst = MDP_OK;
+  int64_t slot = 0;
+  for (int32_t i = 0; i < nsys; ++i) {
+    const int rc = mdp_solve(hs[i], b[i], x[i], nrhs[i], hs[i] ? hs[i]->s.n : 0, hip_stream,
+                             stats ? stats + slot : nullptr);
+    slot += nrhs[i];
+    if (rc < 0) return rc;
+    if (rc > worst) worst = rc;
+  }
+  return worst;
+  API_END
+}
+
+int mdp_apply(mdp_handle *h, int32_t op, const double *x, double *y, void *hip_stream) {
+  API_BEGIN
+  if (!h || !x || !y) {
+    set_last_error("bad apply arguments");
+    return MDP_EINVAL;
+  }
+  if (!h->s.on_device) {
+    set_last_error("handle was set up host-only");
+    return MDP_EINVAL;
+  }
+  h->s.apply(op, x, y, static_cast<hipStream_t>(hip_stream));
+  return MDP_OK;
+  API_END
+}
+
+int mdp_info(const mdp_handle *h, int32_t *n, int32_t *no, int32_t *ng, int32_t *lo, int32_t *lg) {
+  if (!h) {
+    set_last_error("NULL handle");
+    return MDP_EINVAL;
+  }
+  if (n) *n = h->s.host.n;
+  if (no) *no = h->s.host.n_o;
+  if (ng) *ng = h->s.host.n_g;
+  if (lo) *lo = static_cast<int32_t>(h->s.host.Ho.lv.size());
+  if (lg) *lg = static_cast<int32_t>(h->s.host.Hg.lv.size());
+  return MDP_OK;
+}
+
+static const HCsr *pick(const mdp_handle *h, int32_t block, int32_t level, int32_t mat) {
+  if (!h) return nullptr;
+  const HHier &H = block == MDP_BLOCK_OMEGA ? h->s.host.Ho : h->s.host.Hg;
+  if (block != MDP_BLOCK_OMEGA && block != MDP_BLOCK_GAMMA) return nullptr;
+  if (level < 0 || level >= static_cast<int32_t>(H.lv.size())) return nullptr;
+  const bool last = level + 1 == static_cast<int32_t>(H.lv.size());
+  if (mat == MDP_MAT_A) return &H.lv[level].A;
+  if (last) return nullptr;
+  if (mat == MDP_MAT_P) return &H.lv[level].P;
+  if (mat == MDP_MAT_R) return &H.lv[level].R;
+  return nullptr;
+}
+
+int mdp_level_shape(const mdp_handle *h, int32_t block, int32_t level, int32_t mat, int32_t *rows, int32_t *cols,
+                    int64_t *nnz) {
+  const HCsr *m = pick(h, block, level, mat);
+  if (!m) {
+    set_last_error("no such hierarchy matrix");
+    return MDP_EINVAL;
+  }
+  if (rows) *rows = m->nr;
+  if (cols) *cols = m->nc;
+  if (nnz) *nnz = m->nnz();
+  return MDP_OK;
+}
+
+int mdp_level_export(const mdp_handle *h, int32_t block, int32_t level, int32_t mat, int32_t *row_ptr,
+                     int32_t *col, double *val) {
+  const HCsr *m = pick(h, block, level, mat);
+  if (!m || !row_ptr || (m->nnz() > 0 && (!col || !val))) {
+    set_last_error("no such hierarchy matrix or NULL buffer");
+    return MDP_EINVAL;
+  }
+  std::copy(m->ptr.begin(), m->ptr.end(), row_ptr);
+  std::copy(m->col.begin(), m->col.end(), col);
+  std::copy(m->val.begin(), m->val.end(), val);
+  return MDP_OK;
+}
+
+int mdp_level_aggregates(const mdp_handle *h, int32_t block, int32_t level, int32_t *agg) {
+  if (!pick(h, block, level, MDP_MAT_P) || !agg) {
+    set_last_error("level has no aggregates");
+    return MDP_EINVAL;
+  }
+  const HHier &H = block == MDP_BLOCK_OMEGA ? h->s.host.Ho : h->s.host.Hg;
+  std::copy(H.lv[level].agg.begin(), H.lv[level].agg.end(), agg);
+  return MDP_OK;
+}
+
+int mdp_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) {
+    set_last_error("alloc and free must both be set or both be NULL");
+    return MDP_EINVAL;
+  }
+  AllocHook hk;
+  hk.alloc = alloc;
+  hk.free_ = free_;
+  hk.ctx = ctx;
+  set_alloc_hook(hk);
+  return MDP_OK;
+}
+
+const char *mdp_last_error(void) { return g_last_error.c_str(); }
+
+const char *mdp_version(void) { return "mdp 0.1 (gfx950)"; }
+
+}  // extern "C"

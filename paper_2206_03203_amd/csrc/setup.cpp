@@ -1,0 +1,322 @@
+// Host setup: validation, [Omega; Gamma] split (eq. 4), S~ (eq. 7) and the
+// smoothed-aggregation hierarchies that define Q_OO and Q_GG (Section 3.3).
+//
+// SA-AMG rules (the paper names SA-AMG but leaves its parameters open):
+//  * strength: j != i strong for i iff |a_ij| >= theta sqrt(|a_ii a_jj|);
+//  * greedy aggregation in natural order, three passes: (1) a node whose
+//    strong neighbourhood is entirely free (itself included) seeds an
+//    aggregate with it; (2) free nodes join the first-pass aggregate of their
+//    lowest-numbered strong neighbour that the first pass placed; (3) nodes
+//    still free seed aggregates with their still-free strong neighbours.
+//    Nodes without strong neighbours stay out (zero tentative row);
+//  * tentative prolongator columns = aggregate indicators / sqrt(size);
+//  * P = P_t - omega D^{-1} A P_t, D = diag(A), omega = 4 / (3 rho),
+//    rho = max_i sum_j |a_ij| / |a_ii| (Gershgorin bound of D^{-1} A);
+//  * R = P^T, A_c = (R A) P;
+//  * stop at n <= max_coarse, no aggregate, n_c > 0.9 n, or max_levels;
+//  * coarsest: dense LU inverse if n <= max_dense, else l1-Jacobi sweeps.
+#include "setup.hpp"
+
+#include <cmath>
+#include <limits>
+#include <numeric>
+
+namespace mdp {
+
+namespace {
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw SetupError{code, msg}; }
+
+void validate(const mdp_csr *A, const int32_t *part) {
+  if (!A || !part) fail(MDP_EINVAL, "NULL matrix or partition");
+  if (A->n <= 0) fail(MDP_EINVAL, "n must be positive");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val))) fail(MDP_EINVAL, "NULL CSR array");
+  if (A->nnz < 0 || A->nnz > std::numeric_limits<int32_t>::max())
+    fail(MDP_EINVAL, "nnz out of range (int32 indices)");
+  if (A->row_ptr[0] != 0) fail(MDP_EINVAL, "row_ptr[0] must be 0");
+  for (int32_t i = 0; i < A->n; ++i)
+    if (A->row_ptr[i + 1] < A->row_ptr[i]) fail(MDP_EINVAL, "row_ptr is not non-decreasing");
+  if (A->row_ptr[A->n] != A->nnz) fail(MDP_EINVAL, "row_ptr[n] != nnz");
+  for (int64_t p = 0; p < A->nnz; ++p) {
+    if (A->col[p] < 0 || A->col[p] >= A->n) fail(MDP_EINVAL, "column index out of range");
+    if (!std::isfinite(A->val[p])) fail(MDP_ENAN, "non-finite matrix value");
+  }
+  for (int32_t i = 0; i < A->n; ++i)
+    if (part[i] != 0 && part[i] != 1) fail(MDP_EINVAL, "part entries must be 0 or 1");
+}
+
+void check_diag(const HCsr &a, const char *what) {
+  std::vector<double> d = diagonal(a);
+  for (size_t i = 0; i < d.size(); ++i)
+    if (!(d[i] > 0.0))
+      fail(MDP_ENONPOS_DIAG, std::string("non-positive diagonal in ") + what + " at row " +
+                                 std::to_string(i));
+}
+
+// Strong neighbours of every row as a CSR pattern (ascending columns).
+void strength(const HCsr &a, double theta, std::vector<int32_t> &sp, std::vector<int32_t> &sc) {
+  const std::vector<double> d = diagonal(a);
+  sp.assign(static_cast<size_t>(a.nr) + 1, 0);
+  sc.clear();
+  for (int32_t i = 0; i < a.nr; ++i) {
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+      const int32_t j = a.col[p];
+      if (j == i) continue;
+      if (std::fabs(a.val[p]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) sc.push_back(j);
+    }
+    sp[i + 1] = static_cast<int32_t>(sc.size());
+  }
+}
+
+int32_t aggregate(int32_t n, const std::vector<int32_t> &sp, const std::vector<int32_t> &sc,
+                  std::vector<int32_t> &agg) {
+  agg.assign(static_cast<size_t>(n), -1);
+  int32_t na = 0;
+  for (int32_t i = 0; i < n; ++i) {  // first pass: free neighbourhoods
+    if (sp[i] == sp[i + 1] || agg[i] != -1) continue;
+    bool free = true;
+    for (int32_t p = sp[i]; p < sp[i + 1] && free; ++p) free = agg[sc[p]] == -1;
+    if (!free) continue;
+    agg[i] = na;
+    for (int32_t p = sp[i]; p < sp[i + 1]; ++p) agg[sc[p]] = na;
+    ++na;
+  }
+  const std::vector<int32_t> first(agg);
+  for (int32_t i = 0; i < n; ++i) {  // second pass: attach to first-pass aggregates
+    if (agg[i] != -1 || sp[i] == sp[i + 1]) continue;
+    for (int32_t p = sp[i]; p < sp[i + 1]; ++p)
+      if (first[sc[p]] != -1) {
+        agg[i] = first[sc[p]];
+        break;
+      }
+  }
+  for (int32_t i = 0; i < n; ++i) {  // third pass: leftovers
+    if (agg[i] != -1 || sp[i] == sp[i + 1]) continue;
+    agg[i] = na;
+    for (int32_t p = sp[i]; p < sp[i + 1]; ++p)
+      if (agg[sc[p]] == -1) agg[sc[p]] = na;
+    ++na;
+  }
+  return na;
+}
+
+HCsr tentative(const std::vector<int32_t> &agg, int32_t na) {
+  const int32_t n = static_cast<int32_t>(agg.size());
+  std::vector<int32_t> size(static_cast<size_t>(na), 0);
+  for (int32_t a : agg)
+    if (a >= 0) size[a]++;
+  HCsr t = HCsr::empty(n, na);
+  for (int32_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) {
+      t.col.push_back(agg[i]);
+      t.val.push_back(1.0 / std::sqrt(static_cast<double>(size[agg[i]])));
+    }
+    t.ptr[i + 1] = static_cast<int32_t>(t.col.size());
+  }
+  return t;
+}
+
+HCsr smooth_prolongator(const HCsr &a, const HCsr &pt) {
+  const std::vector<double> d = diagonal(a);
+  const std::vector<double> l1 = l1_row_norms(a);
+  double rho = 0.0;
+  for (int32_t i = 0; i < a.nr; ++i) rho = std::max(rho, l1[i] / std::fabs(d[i]));
+  const double omega = (4.0 / 3.0) / rho;
+  HCsr ap = spgemm(a, pt);
+  for (int32_t i = 0; i < ap.nr; ++i)
+    for (int32_t p = ap.ptr[i]; p < ap.ptr[i + 1]; ++p) ap.val[p] = omega * ((1.0 / d[i]) * ap.val[p]);
+  return subtract(pt, ap);
+}
+
+// Dense inverse by LU with partial pivoting (row-major, n x n).
+std::vector<double> dense_inverse(const HCsr &a) {
+  const int32_t n = a.nr;
+  std::vector<double> m(static_cast<size_t>(n) * n, 0.0), inv(static_cast<size_t>(n) * n, 0.0);
+  double amax = 0.0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+      m[static_cast<size_t>(i) * n + a.col[p]] += a.val[p];
+      amax = std::max(amax, std::fabs(a.val[p]));
+    }
+  for (int32_t i = 0; i < n; ++i) inv[static_cast<size_t>(i) * n + i] = 1.0;
+  const double tiny = amax * std::numeric_limits<double>::epsilon() * n;
+  for (int32_t k = 0; k < n; ++k) {
+    int32_t piv = k;
+    double best = std::fabs(m[static_cast<size_t>(k) * n + k]);
+    for (int32_t i = k + 1; i < n; ++i) {
+      const double v = std::fabs(m[static_cast<size_t>(i) * n + k]);
+      if (v > best) {
+        best = v;
+        piv = i;
+      }
+    }
+    if (!(best > tiny)) fail(MDP_ESINGULAR, "coarsest level is singular to working precision");
+    if (piv != k)
+      for (int32_t j = 0; j < n; ++j) {
+        std::swap(m[static_cast<size_t>(k) * n + j], m[static_cast<size_t>(piv) * n + j]);
+        std::swap(inv[static_cast<size_t>(k) * n + j], inv[static_cast<size_t>(piv) * n + j]);
+      }
+    const double dk = m[static_cast<size_t>(k) * n + k];
+    for (int32_t i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = m[static_cast<size_t>(i) * n + k] / dk;
+      if (f == 0.0) continue;
+      double *ri = &m[static_cast<size_t>(i) * n];
+      const double *rk = &m[static_cast<size_t>(k) * n];
+      for (int32_t j = k; j < n; ++j) ri[j] -= f * rk[j];
+      double *qi = &inv[static_cast<size_t>(i) * n];
+      const double *qk = &inv[static_cast<size_t>(k) * n];
+      for (int32_t j = 0; j < n; ++j) qi[j] -= f * qk[j];
+    }
+    double *rk = &m[static_cast<size_t>(k) * n];
+    double *qk = &inv[static_cast<size_t>(k) * n];
+    for (int32_t j = k; j < n; ++j) rk[j] /= dk;
+    for (int32_t j = 0; j < n; ++j) qk[j] /= dk;
+  }
+  for (double v : inv)
+    if (!std::isfinite(v)) fail(MDP_ESINGULAR, "coarsest inverse is not finite");
+  return inv;
+}
+
+// For a symmetric matrix with non-positive off-diagonals (an M-matrix
+// candidate, as two-point flux produces), a connected component whose rows all
+// sum to zero is singular: nothing ties its pressure level (no Dirichlet
+// contact).  Such input cannot be solved and is rejected up front.
+void check_grounded(const HCsr &a) {
+  const int32_t n = a.nr;
+  std::vector<double> rs(static_cast<size_t>(n), 0.0), dg(static_cast<size_t>(n), 0.0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+      if (a.col[p] != i && a.val[p] > 0.0) return;  // not an M-matrix pattern: no claim
+      rs[i] += a.val[p];
+      if (a.col[p] == i) dg[i] = a.val[p];
+    }
+  std::vector<int32_t> comp(static_cast<size_t>(n), -1), stack;
+  for (int32_t s0 = 0; s0 < n; ++s0) {
+    if (comp[s0] >= 0) continue;
+    bool grounded = false;
+    stack.assign(1, s0);
+    comp[s0] = s0;
+    while (!stack.empty()) {
+      const int32_t i = stack.back();
+      stack.pop_back();
+      if (rs[i] > 1e-10 * dg[i]) grounded = true;
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+        const int32_t j = a.col[p];
+        if (a.val[p] != 0.0 && comp[j] < 0) {
+          comp[j] = s0;
+          stack.push_back(j);
+        }
+      }
+    }
+    if (!grounded)
+      fail(MDP_ESINGULAR, "a connected group of unknowns (starting at row " + std::to_string(s0) +
+                              ") has zero row sums: no boundary condition fixes its level");
+  }
+}
+
+}  // namespace
+
+HHier amg_setup(const HCsr &A, const AmgParams &prm) {
+  HHier h;
+  HCsr cur = A;
+  std::vector<int32_t> sp, sc;
+  while (true) {
+    HLevel lv;
+    lv.A = std::move(cur);
+    lv.dl1 = l1_row_norms(lv.A);
+    const int32_t n = lv.A.nr;
+    h.lv.push_back(std::move(lv));
+    HLevel &L = h.lv.back();
+    if (n <= prm.max_coarse || static_cast<int32_t>(h.lv.size()) >= prm.max_levels) break;
+    strength(L.A, prm.theta, sp, sc);
+    std::vector<int32_t> agg;
+    const int32_t na = aggregate(n, sp, sc, agg);
+    if (na == 0 || na > 0.9 * n) break;
+    L.P = smooth_prolongator(L.A, tentative(agg, na));
+    L.R = transpose(L.P);
+    L.agg = std::move(agg);
+    cur = spgemm(spgemm(L.R, L.A), L.P);
+  }
+  const HLevel &last = h.lv.back();
+  if (last.A.nr <= prm.max_dense) {
+    h.dense = true;
+    h.coarse_inv = dense_inverse(last.A);
+  }
+  return h;
+}
+
+void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_options &opt,
+                       HostSystem &s) {
+  validate(Ain, part);
+  const int32_t n = Ain->n;
+  s.n = n;
+  s.perm.clear();
+  for (int32_t i = 0; i < n; ++i)
+    if (part[i] == 0) s.perm.push_back(i);
+  s.n_o = static_cast<int32_t>(s.perm.size());
+  for (int32_t i = 0; i < n; ++i)
+    if (part[i] == 1) s.perm.push_back(i);
+  s.n_g = n - s.n_o;
+  if (s.n_o == 0) fail(MDP_EINVAL, "no host-domain (part 0) unknowns");
+  std::vector<int32_t> inv(static_cast<size_t>(n));
+  s.identity = true;
+  for (int32_t r = 0; r < n; ++r) {
+    inv[s.perm[r]] = r;
+    if (s.perm[r] != r) s.identity = false;
+  }
+
+  HCsr A = HCsr::empty(n, n);
+  A.col.reserve(static_cast<size_t>(Ain->nnz));
+  A.val.reserve(static_cast<size_t>(Ain->nnz));
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t i = s.perm[r];
+    for (int32_t p = Ain->row_ptr[i]; p < Ain->row_ptr[i + 1]; ++p) {
+      A.col.push_back(inv[Ain->col[p]]);
+      A.val.push_back(Ain->val[p]);
+    }
+    A.ptr[r + 1] = static_cast<int32_t>(A.col.size());
+  }
+  sort_rows(A);
+  check_diag(A, "A");
+
+  // symmetry check (informational: the method does not need it)
+  {
+    HCsr t = transpose(A);
+    s.symmetric = (t.col == A.col && t.val == A.val);
+  }
+  if (s.symmetric) check_grounded(A);
+
+  std::vector<int32_t> rows_o(static_cast<size_t>(s.n_o)), rows_g(static_cast<size_t>(s.n_g));
+  std::iota(rows_o.begin(), rows_o.end(), 0);
+  std::iota(rows_g.begin(), rows_g.end(), s.n_o);
+  std::vector<int32_t> map_o(static_cast<size_t>(n), -1), map_g(static_cast<size_t>(n), -1);
+  for (int32_t i = 0; i < s.n_o; ++i) map_o[i] = i;
+  for (int32_t i = 0; i < s.n_g; ++i) map_g[s.n_o + i] = i;
+  s.Aoo = extract(A, rows_o, map_o, s.n_o);
+  s.Aog = extract(A, rows_o, map_g, s.n_g);
+  s.Ago = extract(A, rows_g, map_o, s.n_o);
+  s.Agg = extract(A, rows_g, map_g, s.n_g);
+
+  if (s.n_g > 0) {
+    // S~ = A_OO - (A_OG diag(A_GG)^{-1}) A_GO   (eq. 7)
+    const std::vector<double> d = diagonal(s.Agg);
+    HCsr w = s.Aog;
+    for (size_t p = 0; p < w.col.size(); ++p) w.val[p] = w.val[p] * (1.0 / d[w.col[p]]);
+    s.S = subtract(s.Aoo, spgemm(w, s.Ago));
+  } else {
+    s.S = s.Aoo;
+  }
+  check_diag(s.S, "S~");
+
+  AmgParams prm;
+  prm.theta = opt.strength_theta;
+  prm.max_coarse = opt.max_coarse;
+  prm.max_dense = opt.max_dense;
+  prm.max_levels = opt.max_levels;
+  s.Ho = amg_setup(s.S, prm);
+  if (s.n_g > 0) s.Hg = amg_setup(s.Agg, prm);
+  s.A = std::move(A);
+}
+
+}  // namespace mdp

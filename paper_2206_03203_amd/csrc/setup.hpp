@@ -1,0 +1,59 @@
+// Host-side setup of the solver: block split of eq. (4), approximate Schur
+// complement of eq. (7) and smoothed-aggregation AMG hierarchies (Section 3.3).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "host_csr.hpp"
+#include "mdp.h"
+
+namespace mdp {
+
+struct AmgParams {
+  double theta = 0.08;
+  int32_t max_coarse = 400;
+  int32_t max_dense = 2000;
+  int32_t max_levels = 10;
+};
+
+struct HLevel {
+  HCsr A;                    // level operator
+  HCsr P, R;                 // prolongator to this level from the next, R = P^T (not on the coarsest)
+  std::vector<double> dl1;   // l1 row norms sum_j |a_ij| (smoother diagonal)
+  std::vector<int32_t> agg;  // aggregate per node (-1 = none); empty on the coarsest
+};
+
+struct HHier {
+  std::vector<HLevel> lv;
+  bool dense = false;               // coarsest solved with a dense inverse
+  std::vector<double> coarse_inv;   // n_c x n_c row-major inverse when dense
+  int32_t n() const { return lv.empty() ? 0 : lv[0].A.nr; }
+};
+
+struct HostSystem {
+  int32_t n = 0, n_o = 0, n_g = 0;
+  std::vector<int32_t> perm;  // new index -> caller index ([Omega; Gamma], stable)
+  bool identity = true;
+  HCsr A;                     // full matrix in [Omega; Gamma] order, sorted rows
+  HCsr Aoo, Aog, Ago, Agg;    // blocks of eq. (4)
+  HCsr S;                     // S~ of eq. (7)
+  HHier Ho, Hg;               // hierarchies on S~ and A_GG
+  bool symmetric = true;
+};
+
+// Error carrying an MDP_* code.
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+// Build everything on the host.  Throws SetupError.
+void build_host_system(const mdp_csr *A, const int32_t *part, const mdp_options &opt,
+                       HostSystem &out);
+
+// SA-AMG setup on one block (exposed for testing through the C ABI).
+HHier amg_setup(const HCsr &A, const AmgParams &prm);
+
+}  // namespace mdp

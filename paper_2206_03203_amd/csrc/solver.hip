@@ -1,0 +1,468 @@
+// Device side of the solve phase: upload of the host-built hierarchy, the
+// V-cycle that defines Q_OO / Q_GG (Section 3.3), the preconditioner action of
+// Algorithm 1 (M_L of eq. (8)) and right-preconditioned flexible GMRES
+// (Section 3.2; zero initial guess and relative-residual stop, Section 4).
+//
+// Precision: the preconditioner runs in T (double, or float in mixed mode);
+// the outer matrix, Krylov basis V, Hessenberg/Givens data and the coarsest
+// dense inverse are always FP64.  Z (the preconditioned directions) is kept
+// in T: A z_j is formed from the stored z_j, so FP32 storage is exact for
+// the flexible method.
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): every pass reads
+// each basis vector once and reductions use fixed trees, so results do not
+// depend on scheduling.  Basis vectors are stored unnormalised with a
+// per-column scale (1/norm) applied on every read, which saves a pass.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "kernels.hpp"
+#include "solver.hpp"
+
+namespace mdp {
+
+namespace {
+
+int choose_lpr(int64_t nnz, int32_t nr) {
+  const double avg = nr > 0 ? static_cast<double>(nnz) / nr : 0.0;
+  int l = 2;
+  while (l < avg && l < 64) l *= 2;
+  return l;
+}
+
+template <typename T>
+void upload_vec(DevMem &d, const std::vector<T> &h, hipStream_t s) {
+  d.alloc(h.size() * sizeof(T));
+  if (!h.empty()) MDP_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+template <typename T>
+void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vector<T>> &keep) {
+  d.nr = h.nr;
+  d.nc = h.nc;
+  d.nnz = h.nnz();
+  d.lpr = choose_lpr(d.nnz, d.nr);
+  upload_vec(d.ptr, h.ptr, s);
+  upload_vec(d.col, h.col, s);
+  keep.emplace_back(h.val.begin(), h.val.end());
+  upload_vec(d.val, keep.back(), s);
+}
+
+template <typename T>
+void upload_hier(const HHier &h, DHier<T> &d, hipStream_t s, std::vector<std::vector<T>> &keep) {
+  d.lv.clear();
+  d.lv.resize(h.lv.size());
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    const HLevel &hl = h.lv[l];
+    DLevel<T> &dl = d.lv[l];
+    dl.n = hl.A.nr;
+    upload_csr(hl.A, dl.A, s, keep);
+    std::vector<T> dinv(hl.dl1.size());
+    for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = static_cast<T>(1.0 / hl.dl1[i]);
+    keep.push_back(std::move(dinv));
+    upload_vec(dl.dinv, keep.back(), s);
+    const size_t nb = static_cast<size_t>(std::max(dl.n, 1)) * sizeof(T);
+    dl.x.alloc(nb);
+    dl.b.alloc(nb);
+    dl.t.alloc(nb);
+    dl.r.alloc(nb);
+    if (l + 1 < h.lv.size()) {
+      upload_csr(hl.P, dl.P, s, keep);
+      upload_csr(hl.R, dl.R, s, keep);
+    }
+  }
+  d.dense = h.dense;
+  d.nc = h.lv.back().A.nr;
+  if (h.dense) upload_vec(d.cinv, h.coarse_inv, s);
+  const size_t n0 = static_cast<size_t>(std::max(d.n(), 1)) * sizeof(T);
+  d.tmp_res.alloc(n0);
+  d.tmp_dz.alloc(n0);
+  d.tmp_pp.alloc(2 * static_cast<size_t>(std::max(d.nc, 1)) * sizeof(T));
+}
+
+int grid_for(int64_t n) {
+  const int64_t b = (n + kThreads - 1) / kThreads;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
+}
+
+template <int LPR, int MODE, typename TA, typename TX, typename TY>
+void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2,
+                 const int *gate, hipStream_t s) {
+  const int64_t rows_per_blk = kThreads / LPR;
+  const int blocks = static_cast<int>((A.nr + rows_per_blk - 1) / rows_per_blk);
+  hipLaunchKernelGGL((spmv_kernel<LPR, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
+                     A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+}
+
+template <int MODE, typename TA, typename TX, typename TY>
+void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, const int *gate,
+          hipStream_t s) {
+  if (A.nr == 0) return;
+  switch (A.lpr) {
+    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    case 32: spmv_launch<32, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    default: spmv_launch<64, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+  }
+}
+
+template <typename T>
+void coarse_solve(DHier<T> &H, const T *b, T *x, const int *gate, hipStream_t s) {
+  DLevel<T> &L = H.lv.back();
+  const int n = L.n;
+  if (n == 0) return;
+  if (H.dense) {
+    const int blocks = (n + (kThreads / 64) - 1) / (kThreads / 64);
+    hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, n, dptr<const double>(H.cinv),
+                       b, x, gate);
+    return;
+  }
+  // four l1-Jacobi sweeps from zero, ping-pong ending in x
+  T *pa = dptr<T>(H.tmp_pp), *pb = pa + n;
+  hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
+                     dptr<const T>(L.dinv), pa, gate);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), pb, static_cast<T *>(nullptr), gate, s);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dptr<const T>(L.dinv), pa, static_cast<T *>(nullptr), gate, s);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), x, static_cast<T *>(nullptr), gate, s);
+}
+
+// One V-cycle from a zero initial guess: x = V(b).
+template <typename T>
+void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_t s) {
+  if (l + 1 == H.lv.size()) {
+    coarse_solve(H, b, x, gate, s);
+    return;
+  }
+  DLevel<T> &L = H.lv[l];
+  DLevel<T> &C = H.lv[l + 1];
+  T *t = dptr<T>(L.t);
+  const T *dinv = dptr<const T>(L.dinv);
+  spmv<kPre0>(L.A, static_cast<const T *>(nullptr), b, dinv, dptr<T>(L.r), t, gate, s);  // t = D^-1 b, r = b - A t
+  spmv<kPlain>(L.R, dptr<const T>(L.r), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr),
+               dptr<T>(C.b), static_cast<T *>(nullptr), gate, s);  // b_c = R r
+  vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
+  spmv<kAccum>(L.P, dptr<const T>(C.x), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr), t,
+               static_cast<T *>(nullptr), gate, s);  // t += P x_c
+  spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, static_cast<T *>(nullptr), gate, s);  // post-smooth
+}
+
+// Q = `cycles` V-cycles as a stationary iteration from zero.
+template <typename T>
+void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStream_t s) {
+  vcycle(H, 0, r, z, gate, s);
+  const int n = H.n();
+  for (int c = 1; c < cycles; ++c) {
+    spmv<kResid>(H.lv[0].A, static_cast<const T *>(z), r, static_cast<const T *>(nullptr), dptr<T>(H.tmp_res),
+                 static_cast<T *>(nullptr), gate, s);
+    vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
+    hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
+                       gate);
+  }
+}
+
+// Algorithm 1: z = M_L r, with r and z laid out as [Omega; Gamma].
+template <typename T>
+void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
+  apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
+  if (P.n_g == 0) return;
+  T *rg = dptr<T>(P.rg);
+  spmv<kResid>(P.Ago, static_cast<const T *>(z), r + P.n_o, static_cast<const T *>(nullptr), rg,
+               static_cast<T *>(nullptr), gate, s);  // r_G - A_GO z_O
+  apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
+}
+
+template <typename T>
+std::unique_ptr<Precond<T>> upload_precond(const HostSystem &h, int vcycles, hipStream_t s) {
+  auto p = std::make_unique<Precond<T>>();
+  std::vector<std::vector<T>> keep;
+  p->n_o = h.n_o;
+  p->n_g = h.n_g;
+  p->vcycles = vcycles;
+  upload_hier(h.Ho, p->Ho, s, keep);
+  if (h.n_g > 0) {
+    upload_hier(h.Hg, p->Hg, s, keep);
+    upload_csr(h.Ago, p->Ago, s, keep);
+    p->rg.alloc(static_cast<size_t>(h.n_g) * sizeof(T));
+  }
+  MDP_HIP(hipStreamSynchronize(s));  // host staging vectors die here
+  return p;
+}
+
+template <int NC>
+void arnoldi_launch_dot(int64_t n, int ncols, const double *V, int64_t ld, const double *w, double *partial,
+                        const int *gate, hipStream_t s) {
+  hipLaunchKernelGGL(multi_dot_kernel<NC>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, ncols, V, ld, w, partial,
+                     gate);
+}
+template <int NC>
+void arnoldi_launch_axpy(int64_t n, int ncols, const double *V, int64_t ld, const double *coef, const double *w,
+                         double *out, double *npart, const int *gate, hipStream_t s) {
+  hipLaunchKernelGGL(multi_axpy_kernel<NC>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, ncols, V, ld, coef, w,
+                     out, npart, gate);
+}
+
+void multi_dot(int64_t n, int ncols, const double *V, int64_t ld, const double *w, double *partial,
+               const int *gate, hipStream_t s) {
+  if (ncols <= 8) arnoldi_launch_dot<8>(n, ncols, V, ld, w, partial, gate, s);
+  else if (ncols <= 16) arnoldi_launch_dot<16>(n, ncols, V, ld, w, partial, gate, s);
+  else if (ncols <= 32) arnoldi_launch_dot<32>(n, ncols, V, ld, w, partial, gate, s);
+  else arnoldi_launch_dot<64>(n, ncols, V, ld, w, partial, gate, s);
+}
+
+void multi_axpy(int64_t n, int ncols, const double *V, int64_t ld, const double *coef, const double *w,
+                double *out, double *npart, const int *gate, hipStream_t s) {
+  if (ncols <= 8) arnoldi_launch_axpy<8>(n, ncols, V, ld, coef, w, out, npart, gate, s);
+  else if (ncols <= 16) arnoldi_launch_axpy<16>(n, ncols, V, ld, coef, w, out, npart, gate, s);
+  else if (ncols <= 32) arnoldi_launch_axpy<32>(n, ncols, V, ld, coef, w, out, npart, gate, s);
+  else arnoldi_launch_axpy<64>(n, ncols, V, ld, coef, w, out, npart, gate, s);
+}
+
+template <typename TZ>
+void update_x(int64_t n, int ncols, const TZ *Z, int64_t ld, const double *y, double *x, hipStream_t s) {
+  const int g = grid_for(n);
+  if (ncols <= 8) hipLaunchKernelGGL((update_x_kernel<8, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+  else if (ncols <= 16) hipLaunchKernelGGL((update_x_kernel<16, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+  else if (ncols <= 32) hipLaunchKernelGGL((update_x_kernel<32, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+  else hipLaunchKernelGGL((update_x_kernel<64, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+}
+
+// ||v|| into ws.scalar (device) and returned to the host (synchronises s).
+double norm_sync(Workspace &ws, int64_t n, const double *v, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_partial_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, n, v, dptr<double>(ws.npartial));
+  hipLaunchKernelGGL(reduce_scalar_kernel, dim3(1), dim3(kThreads), 0, s, dptr<const double>(ws.npartial),
+                     dptr<double>(ws.scalar), 1);
+  MDP_HIP(hipMemcpyAsync(ws.host_scalar, ws.scalar.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+  MDP_HIP(hipStreamSynchronize(s));
+  return *ws.host_scalar;
+}
+
+template <typename T>
+int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, mdp_stats *st) {
+  Workspace &ws = S.ws;
+  const int64_t n = S.n, ld = ws.ld;
+  const int m = ws.m;
+  const bool use_x0 = (S.opt.flags & MDP_USE_X0) != 0;
+  double *V = dptr<double>(ws.V);
+  T *Z = dptr<T>(ws.Z);
+  double *w = dptr<double>(ws.w);
+  GmresState *dst = dptr<GmresState>(ws.state);
+  const int *gate = &dst->done;
+
+  // caller order -> [Omega; Gamma]
+  const double *bp = b;
+  double *xp = x;
+  if (!S.host.identity) {
+    const int g = grid_for(n);
+    hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, S.n, dptr<const int>(S.perm), b,
+                       dptr<double>(ws.bp));
+    bp = dptr<const double>(ws.bp);
+    xp = dptr<double>(ws.xp);
+    if (use_x0)
+      hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, S.n, dptr<const int>(S.perm), x, xp);
+  }
+  const double bnorm = norm_sync(ws, n, bp, s);
+  mdp_stats out{};
+  if (!std::isfinite(bnorm)) {
+    out.status = MDP_ENAN;
+    if (st) *st = out;
+    return MDP_ENAN;
+  }
+  if (!use_x0) MDP_HIP(hipMemsetAsync(xp, 0, n * sizeof(double), s));
+  if (bnorm == 0.0) {
+    if (use_x0) MDP_HIP(hipMemsetAsync(xp, 0, n * sizeof(double), s));
+    if (!S.host.identity)
+      hipLaunchKernelGGL(permute_kernel<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, S.n,
+                         dptr<const int>(S.perm), static_cast<const double *>(xp), x);
+    MDP_HIP(hipStreamSynchronize(s));
+    out.converged = 1;
+    out.status = MDP_OK;
+    if (st) *st = out;
+    return MDP_OK;
+  }
+  const double tol_abs = S.opt.rtol * bnorm;
+  double beta;
+  if (use_x0) {
+    spmv<kResid>(S.A, static_cast<const double *>(xp), bp, static_cast<const double *>(nullptr), V,
+                 static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
+    beta = norm_sync(ws, n, V, s);
+  } else {
+    MDP_HIP(hipMemcpyAsync(V, bp, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    beta = bnorm;  // ws.scalar holds ||b|| = ||r_0||
+  }
+
+  int iters = 0, cycles = 0, code = MDP_OK;
+  double est = beta;
+  while (true) {
+    if (!std::isfinite(beta)) {
+      code = MDP_ENAN;
+      break;
+    }
+    if (beta <= tol_abs || iters >= S.opt.max_iter) break;
+    const int kmax = std::min(m, S.opt.max_iter - iters);
+    hipLaunchKernelGGL(cycle_init_kernel, dim3(1), dim3(64), 0, s, dst, dptr<const double>(ws.scalar),
+                       dptr<double>(ws.g), dptr<double>(ws.scale), m);
+    int last = -1;
+    for (int j = 0; j < kmax; ++j) {
+      T *zj = Z + j * ld;
+      T *rin = dptr<T>(ws.rin);
+      hipLaunchKernelGGL((scale_copy_kernel<double, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, n,
+                         static_cast<const double *>(V + j * ld), dptr<const double>(ws.scale) + j, rin, gate);
+      apply_ml(P, static_cast<const T *>(rin), zj, gate, s);
+      spmv<kPlain>(S.A, static_cast<const T *>(zj), static_cast<const double *>(nullptr),
+                   static_cast<const double *>(nullptr), w, static_cast<double *>(nullptr), gate, s);
+      const int nc = j + 1;
+      multi_dot(n, nc, V, ld, w, dptr<double>(ws.partial), gate, s);
+      hipLaunchKernelGGL(reduce_cols_kernel, dim3(nc), dim3(kThreads), 0, s, nc, dptr<const double>(ws.partial),
+                         dptr<const double>(ws.scale), dptr<double>(ws.h1), dptr<double>(ws.c1), gate);
+      multi_axpy(n, nc, V, ld, dptr<const double>(ws.c1), w, w, static_cast<double *>(nullptr), gate, s);
+      multi_dot(n, nc, V, ld, w, dptr<double>(ws.partial), gate, s);
+      hipLaunchKernelGGL(reduce_cols_kernel, dim3(nc), dim3(kThreads), 0, s, nc, dptr<const double>(ws.partial),
+                         dptr<const double>(ws.scale), dptr<double>(ws.h2), dptr<double>(ws.c2), gate);
+      multi_axpy(n, nc, V, ld, dptr<const double>(ws.c2), w, V + (j + 1) * ld, dptr<double>(ws.npartial), gate, s);
+      hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(kThreads), 0, s, dst, j, kmax, tol_abs,
+                         dptr<const double>(ws.h1), dptr<const double>(ws.h2), dptr<const double>(ws.npartial),
+                         dptr<double>(ws.Hr), m + 1, dptr<double>(ws.cs), dptr<double>(ws.sn), dptr<double>(ws.g),
+                         dptr<double>(ws.scale), dptr<double>(ws.hist));
+      MDP_HIP(hipMemcpyAsync(&ws.host_state[j], dst, sizeof(GmresState), hipMemcpyDeviceToHost, s));
+      MDP_HIP(hipEventRecord(ws.ev[j], s));
+      last = j;
+      if (j >= 1) {
+        MDP_HIP(hipEventSynchronize(ws.ev[j - 1]));
+        if (ws.host_state[j - 1].done) break;
+      }
+    }
+    MDP_HIP(hipGetLastError());
+    MDP_HIP(hipEventSynchronize(ws.ev[last]));
+    const GmresState fs = ws.host_state[last];
+    if (fs.nan) {
+      code = MDP_ENAN;
+      break;
+    }
+    const int k = fs.k;
+    est = fs.est;
+    iters += k;
+    ++cycles;
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, dst, dptr<const double>(ws.Hr), m + 1,
+                       dptr<const double>(ws.g), dptr<double>(ws.y));
+    update_x(n, k, static_cast<const T *>(Z), ld, dptr<const double>(ws.y), xp, s);
+    spmv<kResid>(S.A, static_cast<const double *>(xp), bp, static_cast<const double *>(nullptr), V,
+                 static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
+    beta = norm_sync(ws, n, V, s);
+  }
+  if (!S.host.identity)
+    hipLaunchKernelGGL(permute_kernel<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, S.n,
+                       dptr<const int>(S.perm), static_cast<const double *>(xp), x);
+  MDP_HIP(hipGetLastError());
+  MDP_HIP(hipStreamSynchronize(s));
+  out.iters = iters;
+  out.restarts = std::max(cycles - 1, 0);
+  out.rel_res_true = beta / bnorm;
+  out.rel_res_est = est / bnorm;
+  out.converged = (code == MDP_OK && beta <= tol_abs) ? 1 : 0;
+  if (code == MDP_OK && !out.converged) code = MDP_NOT_CONVERGED;
+  out.status = code;
+  if (st) *st = out;
+  return code;
+}
+
+}  // namespace
+
+Workspace::~Workspace() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  if (host_state) (void)hipHostFree(host_state);
+  if (host_scalar) (void)hipHostFree(host_scalar);
+}
+
+void Solver::upload(hipStream_t s) {
+  n = host.n;
+  n_o = host.n_o;
+  n_g = host.n_g;
+  std::vector<std::vector<double>> keep;
+  upload_csr(host.A, A, s, keep);
+  if (!host.identity) upload_vec(perm, host.perm, s);
+  if (opt.precision == MDP_MIXED)
+    pc32 = upload_precond<float>(host, opt.vcycles, s);
+  else
+    pc64 = upload_precond<double>(host, opt.vcycles, s);
+
+  const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
+  ws.m = opt.restart;
+  ws.ld = padded_ld(n);
+  const size_t col8 = static_cast<size_t>(ws.ld) * sizeof(double);
+  ws.V.alloc(col8 * (ws.m + 1));
+  ws.Z.alloc(static_cast<size_t>(ws.ld) * tsz * ws.m);
+  ws.w.alloc(col8);
+  ws.rin.alloc(static_cast<size_t>(ws.ld) * tsz);
+  if (!host.identity) {
+    ws.bp.alloc(col8);
+    ws.xp.alloc(col8);
+  }
+  const size_t mm = static_cast<size_t>(ws.m) + 1;
+  for (DevMem *d : {&ws.h1, &ws.c1, &ws.h2, &ws.c2, &ws.cs, &ws.sn, &ws.g, &ws.scale, &ws.y, &ws.hist})
+    d->alloc(mm * sizeof(double));
+  ws.Hr.alloc(mm * ws.m * sizeof(double));
+  ws.partial.alloc(static_cast<size_t>(kMaxCols + 1) * kRedBlocks * sizeof(double));
+  ws.npartial.alloc(kRedBlocks * sizeof(double));
+  ws.scalar.alloc(sizeof(double));
+  ws.state.alloc(sizeof(GmresState));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.host_state), mm * sizeof(GmresState), hipHostMallocDefault));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.host_scalar), sizeof(double), hipHostMallocDefault));
+  ws.ev.resize(mm);
+  for (auto &e : ws.ev) MDP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  MDP_HIP(hipStreamSynchronize(s));
+  on_device = true;
+}
+
+int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = opt.precision == MDP_MIXED ? fgmres<float>(*this, *pc32, b, x, s, st)
+                                      : fgmres<double>(*this, *pc64, b, x, s, st);
+  const auto t1 = std::chrono::steady_clock::now();
+  if (st) {
+    st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    st->setup_ms = setup_ms;
+  }
+  return rc;
+}
+
+void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
+  const int64_t nn = n;
+  switch (op) {
+    case MDP_OP_A:
+      spmv<kPlain>(A, x, static_cast<const double *>(nullptr), static_cast<const double *>(nullptr), y,
+                   static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
+      break;
+    case MDP_OP_ML:
+    case MDP_OP_QOO:
+    case MDP_OP_QGG: {
+      const int64_t len = op == MDP_OP_ML ? nn : (op == MDP_OP_QOO ? n_o : n_g);
+      if (len == 0) break;
+      if (opt.precision == MDP_MIXED) {
+        float *in = dptr<float>(ws.rin);
+        float *out = dptr<float>(ws.Z);
+        hipLaunchKernelGGL((scale_copy_kernel<double, float>), dim3(grid_for(len)), dim3(kThreads), 0, s, len, x,
+                           static_cast<const double *>(nullptr), in, static_cast<const int *>(nullptr));
+        if (op == MDP_OP_ML) apply_ml(*pc32, static_cast<const float *>(in), out, nullptr, s);
+        else if (op == MDP_OP_QOO) apply_q(pc32->Ho, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
+        else apply_q(pc32->Hg, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
+        hipLaunchKernelGGL((scale_copy_kernel<float, double>), dim3(grid_for(len)), dim3(kThreads), 0, s, len,
+                           static_cast<const float *>(out), static_cast<const double *>(nullptr), y,
+                           static_cast<const int *>(nullptr));
+      } else {
+        if (op == MDP_OP_ML) apply_ml(*pc64, x, y, nullptr, s);
+        else if (op == MDP_OP_QOO) apply_q(pc64->Ho, pc64->vcycles, x, y, nullptr, s);
+        else apply_q(pc64->Hg, pc64->vcycles, x, y, nullptr, s);
+      }
+      break;
+    }
+    default:
+      raise(MDP_EINVAL, "unknown operator");
+  }
+  MDP_HIP(hipGetLastError());
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace mdp

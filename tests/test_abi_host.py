@@ -1,0 +1,185 @@
+"""C ABI on a machine without a GPU: the library loads, exports every
+declared entry point, validates its inputs, and its host-side setup (block
+split, S~ of eq. (7), SA-AMG of Section 3.3) reproduces the oracle's
+hierarchy level by level (handles built with MDP_HOST_ONLY, no device)."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import amg, blocks as ob
+from oracle import assembly as oa
+from paper_2206_03203_amd import _lib as L
+from paper_2206_03203_amd import tpfa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mdp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L.lib, name), name
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_options_default_values():
+    o = L.mdp_options_default()
+    assert (o.precision, o.vcycles, o.pre_sweeps, o.post_sweeps) == (L.MDP_FP64, 1, 1, 1)
+    assert (o.strength_theta, o.max_coarse, o.max_dense, o.max_levels) == (0.08, 400, 2000, 10)
+    assert (o.restart, o.max_iter, o.rtol, o.flags) == (64, 1000, 1e-8, 0)
+    assert L.mdp_version().startswith("mdp")
+
+
+def _host_handle(A, part, **kw):
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY, **kw)
+    return L.mdp_setup(A, part, o)
+
+
+def _csr(h, block, level, mat):
+    ptr, col, val, shape = L.mdp_level_export(h, block, level, mat)
+    return sp.csr_matrix((val, col, ptr), shape=shape)
+
+
+SCEN = [
+    lambda: synth.grid_2d_four_lines(32),
+    lambda: synth.regular_3d(n=12, seed=3),
+    lambda: synth.regular_3d(n=10, k_par=1e-4, kappa=1e4, seed=5),
+    lambda: synth.random_2d(4, n_range=(40, 60)),
+    lambda: synth.tiny_3d(9, seed=2),
+]
+
+
+@pytest.mark.parametrize("make", SCEN)
+def test_host_hierarchy_matches_oracle(make):
+    sc = make()
+    A, b, part = tpfa.assemble(sc)
+    opts = amg.AMGOptions(max_coarse=40)
+    h = _host_handle(A, part, max_coarse=40)
+    try:
+        Ao, bo, po = oa.assemble(sc)
+        _, _, Aoo, Aog, Ago, Agg = ob.split(Ao, po)
+        S = ob.approx_schur(Aoo, Aog, Ago, Agg)
+        info = L.mdp_info(h)
+        assert info["n_omega"] == Aoo.shape[0] and info["n_gamma"] == Agg.shape[0]
+        for block, M in ((L.MDP_BLOCK_OMEGA, S), (L.MDP_BLOCK_GAMMA, Agg)):
+            H = amg.setup(M, opts)
+            nl = info["levels_omega" if block == L.MDP_BLOCK_OMEGA else "levels_gamma"]
+            assert nl == len(H.levels)
+            for lvl, lv in enumerate(H.levels):
+                Ah = _csr(h, block, lvl, L.MDP_MAT_A)
+                scale = abs(lv.A).max()
+                assert Ah.shape == lv.A.shape
+                assert abs(Ah - lv.A).max() <= 1e-12 * scale
+                if lvl + 1 < len(H.levels):
+                    agg = L.mdp_level_aggregates(h, block, lvl)
+                    assert np.array_equal(agg, lv.agg)
+                    P = _csr(h, block, lvl, L.MDP_MAT_P)
+                    R = _csr(h, block, lvl, L.MDP_MAT_R)
+                    assert abs(P - lv.P).max() <= 1e-13
+                    assert (R != P.T).nnz == 0
+    finally:
+        L.mdp_destroy(h)
+
+
+def test_interleaved_unknowns_give_the_same_hierarchy():
+    """The library orders unknowns as [Omega; Gamma] keeping the caller's
+    relative order inside each block, so interleaving fracture unknowns
+    among host unknowns must not change anything."""
+    sc = synth.tiny_2d(10, seed=1)
+    A, b, part = tpfa.assemble(sc)
+    # random riffle: positions of the two blocks are mixed, each block's own
+    # order is kept
+    key = np.where(part == 0, np.arange(A.shape[0]), 0).astype(float)
+    key[part == 1] = np.sort(np.random.default_rng(3).uniform(0, part.size - part.sum(), part.sum()))
+    perm = np.argsort(key, kind="stable")
+    h0 = _host_handle(A, part)
+    h1 = _host_handle(A[perm][:, perm].tocsr(), part[perm])
+    try:
+        for lvl in range(L.mdp_info(h0)["levels_omega"]):
+            A0 = _csr(h0, 0, lvl, L.MDP_MAT_A)
+            A1 = _csr(h1, 0, lvl, L.MDP_MAT_A)
+            assert abs(A0 - A1).max() == 0.0
+    finally:
+        L.mdp_destroy(h0)
+        L.mdp_destroy(h1)
+
+
+def _expect(code, A, part, **kw):
+    with pytest.raises(L.MdpError) as e:
+        _host_handle(A, part, **kw)
+    assert e.value.code == code, str(e.value)
+
+
+def test_input_validation_errors():
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    n = A.shape[0]
+    # malformed CSR: non-monotone row_ptr, column out of range, bad part
+    ptr = A.indptr.copy()
+    ptr[3], ptr[4] = ptr[4], ptr[3]
+    _expect(L.MDP_EINVAL, (ptr, A.indices, A.data), part)
+    col = A.indices.copy()
+    col[5] = n + 3
+    _expect(L.MDP_EINVAL, (A.indptr, col, A.data), part)
+    bad = part.copy()
+    bad[0] = 2
+    _expect(L.MDP_EINVAL, A, bad)
+    # NaN in the values
+    val = A.data.copy()
+    val[7] = np.nan
+    _expect(L.MDP_ENAN, (A.indptr, A.indices, val), part)
+    # zero and negative diagonal
+    D = A.tolil()
+    D[2, 2] = 0.0
+    _expect(L.MDP_ENONPOS_DIAG, D.tocsr(), part)
+    D[2, 2] = -1.0
+    _expect(L.MDP_ENONPOS_DIAG, D.tocsr(), part)
+    # bad options
+    _expect(L.MDP_EINVAL, A, part, restart=65)
+    _expect(L.MDP_EINVAL, A, part, precision=7)
+    _expect(L.MDP_EINVAL, A, part, rtol=0.0)
+
+
+def test_singular_system_is_reported():
+    """Pure-Neumann host (no Dirichlet boundary): A 1 = 0, so the coarsest
+    level of the S~ hierarchy is singular."""
+    sc = synth.tiny_2d(8)
+    sc = synth.Scenario(2, sc.n, sc.k_host, sc.fractures, {})
+    A, b, part = tpfa.assemble(sc)
+    assert np.allclose(A @ np.ones(A.shape[0]), 0.0, atol=1e-12)
+    _expect(L.MDP_ESINGULAR, A, part)
+
+
+def test_no_fracture_unknowns_allowed():
+    n = 12
+    sc = synth.Scenario(2, n, np.ones(n * n), [], {(0, 0): 1.0, (0, 1): 0.0})
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part)
+    try:
+        info = L.mdp_info(h)
+        assert info["n_gamma"] == 0 and info["levels_gamma"] == 0
+    finally:
+        L.mdp_destroy(h)
+
+
+def test_host_only_handle_refuses_solve():
+    import ctypes
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part)
+    try:
+        rc = L.lib.mdp_solve(h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, A.shape[0], None, None)
+        assert rc == L.MDP_EINVAL
+    finally:
+        L.mdp_destroy(h)
