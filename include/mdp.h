@@ -124,6 +124,14 @@ int mdp_options_default(mdp_options *opt);
 int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt,
               void *hip_stream, mdp_handle **out);
 
+/* A second handle for the same system as src with other solve options
+ * (typically the other precision), reusing src's host-built blocks and AMG
+ * hierarchies instead of repeating the setup of eq. (7) and Section 3.3.
+ * The AMG options (strength_theta, max_coarse, max_dense, max_levels) must
+ * equal src's (EINVAL otherwise).  src is not modified and stays valid. */
+int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stream,
+                   mdp_handle **out);
+
 /* Release the handle and its device memory (NULL is a no-op). */
 int mdp_destroy(mdp_handle *h);
 
@@ -195,6 +203,27 @@ int mdp_poll(mdp_server *srv, uint64_t ticket, mdp_stats *stats);
 /* Stop the progress thread after draining admitted requests; frees the
  * server (handles stay owned by the caller). */
 int mdp_server_destroy(mdp_server *srv);
+
+/* ---- measurement ------------------------------------------------------ */
+
+/* Kernel classes for mdp_ktimer_*. */
+#define MDP_KC_OUTER_SPMV 0    /* w = A z_j with the FP64 system matrix                  */
+#define MDP_KC_FINE_SMOOTH 1   /* finest S~ level: fused pre-smoothing + residual, and
+                                  post-smoothing (the l1-Jacobi sweeps of Section 3.3)   */
+#define MDP_KC_VCYCLE_OTHER 2  /* the rest of both V-cycles and the A_GO update          */
+#define MDP_KC_ARNOLDI_DOT 3   /* multi-dot passes of the Arnoldi orthogonalisation      */
+#define MDP_KC_ARNOLDI_AXPY 4  /* multi-axpy passes of the Arnoldi orthogonalisation     */
+#define MDP_KC_OTHER 5         /* casts, reductions, Givens, update of x, residual       */
+
+/* Start timing every launch of one kernel class (process-wide): HIP events
+ * are recorded around each launch on the stream it is launched on, and the
+ * launch's algorithmic bytes (each matrix value/index and each vector read
+ * or written once) are accumulated.  Resets the class's counters. */
+int mdp_ktimer_begin(int32_t kind);
+
+/* Stop timing a class and report the summed kernel time (ms), the number of
+ * launches and the algorithmic bytes.  Waits for the recorded events. */
+int mdp_ktimer_end(int32_t kind, double *total_ms, int64_t *launches, double *bytes);
 
 /* ---- memory ----------------------------------------------------------- */
 

@@ -21,7 +21,25 @@ LIB_PATH = os.path.join(_HERE, "libmdp.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_03203_amd.build`")
 
+# torch brings its own HIP runtime.  Loading it first makes libmdp bind to
+# that same runtime (one runtime per process); the other order would map a
+# second HIP/HSA runtime whose allocations and streams torch cannot see.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped in this process (%s); import torch before "
+                      "loading libmdp" % ", ".join(_hip_runtimes()))
 
 MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING = 0, 1, 2
 MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP_EBUSY = -1, -2, -3, -4, -5, -6, -7
@@ -69,6 +87,7 @@ _ip = C.POINTER(C.c_int32)
 _sig = {
     "mdp_options_default": (C.c_int, [C.POINTER(mdp_options)]),
     "mdp_setup": (C.c_int, [C.POINTER(mdp_csr), _ip, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
+    "mdp_setup_like": (C.c_int, [_vp, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
     "mdp_destroy": (C.c_int, [_vp]),
     "mdp_solve": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int64, _vp, C.POINTER(mdp_stats)]),
     "mdp_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _ip, _vp,
@@ -84,6 +103,8 @@ _sig = {
     "mdp_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(mdp_stats)]),
     "mdp_server_destroy": (C.c_int, [_vp]),
     "mdp_set_allocator": (C.c_int, [_vp, _vp, _vp]),
+    "mdp_ktimer_begin": (C.c_int, [C.c_int32]),
+    "mdp_ktimer_end": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mdp_last_error": (C.c_char_p, []),
     "mdp_version": (C.c_char_p, []),
 }
@@ -150,6 +171,14 @@ def mdp_setup(A, part, opts: Optional[mdp_options] = None, stream=None) -> int:
     sp = None if host_only else _stream_ptr(stream)
     h = _vp()
     _check(lib.mdp_setup(C.byref(hold.s), part.ctypes.data_as(_ip), C.byref(opts), sp, C.byref(h)), "mdp_setup")
+    return h.value
+
+
+def mdp_setup_like(src: int, opts: mdp_options, stream=None) -> int:
+    """Another handle for src's system with other options (e.g. precision)."""
+    sp = None if (opts.flags & MDP_HOST_ONLY) else _stream_ptr(stream)
+    h = _vp()
+    _check(lib.mdp_setup_like(src, C.byref(opts), sp, C.byref(h)), "mdp_setup_like")
     return h.value
 
 

@@ -137,6 +137,36 @@ int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt, voi
   API_END
 }
 
+int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stream, mdp_handle **out) {
+  API_BEGIN
+  if (!src || !opt || !out) {
+    set_last_error("NULL argument");
+    return MDP_EINVAL;
+  }
+  *out = nullptr;
+  const mdp_options &o = *opt;
+  const int rc = check_options(o);
+  if (rc != MDP_OK) return rc;
+  const mdp_options &so = src->s.opt;
+  if (o.strength_theta != so.strength_theta || o.max_coarse != so.max_coarse || o.max_dense != so.max_dense ||
+      o.max_levels != so.max_levels) {
+    set_last_error("AMG options differ from the source handle");
+    return MDP_EINVAL;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  auto h = std::make_unique<mdp_handle>();
+  h->s.opt = o;
+  h->s.host = src->s.host;
+  h->s.n = h->s.host.n;
+  h->s.n_o = h->s.host.n_o;
+  h->s.n_g = h->s.host.n_g;
+  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h.release();
+  return MDP_OK;
+  API_END
+}
+
 int mdp_destroy(mdp_handle *h) {
   API_BEGIN
   delete h;

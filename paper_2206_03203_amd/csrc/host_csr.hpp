@@ -4,10 +4,44 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <stdexcept>
+#include <climits>
+#include <thread>
 #include <vector>
 
 namespace mdp {
+
+// Worker threads for the host setup (MDP_SETUP_THREADS, default: all cores,
+// at most 32).
+inline int setup_workers() {
+  static const int n = [] {
+    const char *e = std::getenv("MDP_SETUP_THREADS");
+    int t = e ? std::atoi(e) : static_cast<int>(std::thread::hardware_concurrency());
+    return std::max(1, std::min(t, 32));
+  }();
+  return n;
+}
+
+// Split [0, n) into at most setup_workers() contiguous chunks and run
+// f(begin, end, chunk) on each in its own thread.  The chunking depends only
+// on n, so two calls with the same n see the same chunks.  f must not throw.
+template <class F>
+void parallel_chunks(int64_t n, F &&f) {
+  const int T = (n < 8192) ? 1 : setup_workers();
+  const int64_t chunk = (n + T - 1) / T;
+  if (T == 1) {
+    f(int64_t{0}, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) {
+    const int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back([&f, b, e, t] { f(b, e, t); });
+  }
+  for (auto &x : th) x.join();
+}
 
 struct HCsr {
   int32_t nr = 0, nc = 0;
@@ -25,30 +59,65 @@ struct HCsr {
   }
 };
 
+// Build a matrix row by row in parallel: fn(i, chunk, cols, vals) appends the
+// entries of row i.  Rows are computed independently, so the result does not
+// depend on the number of threads.
+template <class RowFn>
+HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn) {
+  const int T = setup_workers();
+  std::vector<std::vector<int32_t>> lc(static_cast<size_t>(T));
+  std::vector<std::vector<double>> lv(static_cast<size_t>(T));
+  std::vector<int32_t> cnt(static_cast<size_t>(nr), 0);
+  std::vector<int64_t> first(static_cast<size_t>(T), -1);
+  parallel_chunks(nr, [&](int64_t b, int64_t e, int t) {
+    auto &C = lc[t];
+    auto &V = lv[t];
+    first[t] = b;
+    for (int64_t i = b; i < e; ++i) {
+      const size_t before = C.size();
+      fn(static_cast<int32_t>(i), t, C, V);
+      cnt[i] = static_cast<int32_t>(C.size() - before);
+    }
+  });
+  HCsr out = HCsr::empty(nr, nc);
+  int64_t acc = 0;
+  for (int32_t i = 0; i < nr; ++i) {
+    acc += cnt[i];
+    if (acc > INT32_MAX) throw std::length_error("matrix exceeds int32 indexing");
+    out.ptr[i + 1] = static_cast<int32_t>(acc);
+  }
+  out.col.resize(static_cast<size_t>(acc));
+  out.val.resize(static_cast<size_t>(acc));
+  parallel_chunks(T, [&](int64_t b, int64_t e, int) {
+    for (int64_t t = b; t < e; ++t) {
+      if (first[t] < 0) continue;
+      const int64_t off = out.ptr[first[t]];
+      std::copy(lc[t].begin(), lc[t].end(), out.col.begin() + off);
+      std::copy(lv[t].begin(), lv[t].end(), out.val.begin() + off);
+    }
+  });
+  return out;
+}
+
 // Sort the column indices of every row (values follow); duplicate columns are
 // summed in their stored order.
 inline void sort_rows(HCsr &a) {
-  std::vector<std::pair<int32_t, double>> tmp;
-  HCsr out = HCsr::empty(a.nr, a.nc);
-  out.col.reserve(a.col.size());
-  out.val.reserve(a.val.size());
-  for (int32_t i = 0; i < a.nr; ++i) {
-    tmp.clear();
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) tmp.emplace_back(a.col[p], a.val[p]);
-    std::stable_sort(tmp.begin(), tmp.end(),
-                     [](const auto &x, const auto &y) { return x.first < y.first; });
-    for (size_t k = 0; k < tmp.size(); ++k) {
-      if (!out.col.empty() && static_cast<int64_t>(out.col.size()) > out.ptr[i] &&
-          out.col.back() == tmp[k].first) {
-        out.val.back() += tmp[k].second;
+  std::vector<std::vector<std::pair<int32_t, double>>> tmp(static_cast<size_t>(setup_workers()));
+  a = build_rows(a.nr, a.nc, [&](int32_t i, int t, std::vector<int32_t> &C, std::vector<double> &V) {
+    auto &row = tmp[t];
+    row.clear();
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) row.emplace_back(a.col[p], a.val[p]);
+    std::stable_sort(row.begin(), row.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    const size_t start = C.size();
+    for (const auto &e : row) {
+      if (C.size() > start && C.back() == e.first) {
+        V.back() += e.second;
       } else {
-        out.col.push_back(tmp[k].first);
-        out.val.push_back(tmp[k].second);
+        C.push_back(e.first);
+        V.push_back(e.second);
       }
     }
-    out.ptr[i + 1] = static_cast<int32_t>(out.col.size());
-  }
-  a = std::move(out);
+  });
 }
 
 inline HCsr transpose(const HCsr &a) {
@@ -74,35 +143,39 @@ inline HCsr transpose(const HCsr &a) {
 // order.  Output columns sorted; entries that sum to exactly zero are dropped.
 inline HCsr spgemm(const HCsr &a, const HCsr &b) {
   if (a.nc != b.nr) throw std::invalid_argument("spgemm shape mismatch");
-  HCsr c = HCsr::empty(a.nr, b.nc);
-  std::vector<int32_t> mark(static_cast<size_t>(b.nc), -1);
-  std::vector<double> acc(static_cast<size_t>(b.nc), 0.0);
-  std::vector<int32_t> cols;
-  for (int32_t i = 0; i < a.nr; ++i) {
-    cols.clear();
+  const int T = setup_workers();
+  std::vector<std::vector<int32_t>> mark(static_cast<size_t>(T)), cols(static_cast<size_t>(T));
+  std::vector<std::vector<double>> acc(static_cast<size_t>(T));
+  return build_rows(a.nr, b.nc, [&](int32_t i, int t, std::vector<int32_t> &C, std::vector<double> &V) {
+    auto &mk = mark[t];
+    auto &ac = acc[t];
+    auto &cl = cols[t];
+    if (mk.empty()) {
+      mk.assign(static_cast<size_t>(b.nc), -1);
+      ac.assign(static_cast<size_t>(b.nc), 0.0);
+    }
+    cl.clear();
     for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
       const int32_t k = a.col[p];
       const double av = a.val[p];
       for (int32_t q = b.ptr[k]; q < b.ptr[k + 1]; ++q) {
         const int32_t j = b.col[q];
-        if (mark[j] != i) {
-          mark[j] = i;
-          acc[j] = av * b.val[q];
-          cols.push_back(j);
+        if (mk[j] != i) {
+          mk[j] = i;
+          ac[j] = av * b.val[q];
+          cl.push_back(j);
         } else {
-          acc[j] += av * b.val[q];
+          ac[j] += av * b.val[q];
         }
       }
     }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t j : cols) {
-      if (acc[j] == 0.0) continue;
-      c.col.push_back(j);
-      c.val.push_back(acc[j]);
+    std::sort(cl.begin(), cl.end());
+    for (int32_t j : cl) {
+      if (ac[j] == 0.0) continue;
+      C.push_back(j);
+      V.push_back(ac[j]);
     }
-    c.ptr[i + 1] = static_cast<int32_t>(c.col.size());
-  }
-  return c;
+  });
 }
 
 // C = A - B for matrices with sorted rows; entries present in only one operand
@@ -110,33 +183,28 @@ inline HCsr spgemm(const HCsr &a, const HCsr &b) {
 // that are exactly zero are dropped.
 inline HCsr subtract(const HCsr &a, const HCsr &b) {
   if (a.nr != b.nr || a.nc != b.nc) throw std::invalid_argument("subtract shape mismatch");
-  HCsr c = HCsr::empty(a.nr, a.nc);
-  c.col.reserve(a.col.size() + b.col.size());
-  c.val.reserve(a.col.size() + b.col.size());
-  for (int32_t i = 0; i < a.nr; ++i) {
+  return build_rows(a.nr, a.nc, [&](int32_t i, int, std::vector<int32_t> &C, std::vector<double> &V) {
     int32_t p = a.ptr[i], pe = a.ptr[i + 1], q = b.ptr[i], qe = b.ptr[i + 1];
     while (p < pe || q < qe) {
       if (q >= qe || (p < pe && a.col[p] < b.col[q])) {
-        c.col.push_back(a.col[p]);
-        c.val.push_back(a.val[p]);
+        C.push_back(a.col[p]);
+        V.push_back(a.val[p]);
         ++p;
       } else if (p >= pe || b.col[q] < a.col[p]) {
-        c.col.push_back(b.col[q]);
-        c.val.push_back(-b.val[q]);
+        C.push_back(b.col[q]);
+        V.push_back(-b.val[q]);
         ++q;
       } else {
         const double v = a.val[p] - b.val[q];
         if (v != 0.0) {
-          c.col.push_back(a.col[p]);
-          c.val.push_back(v);
+          C.push_back(a.col[p]);
+          V.push_back(v);
         }
         ++p;
         ++q;
       }
     }
-    c.ptr[i + 1] = static_cast<int32_t>(c.col.size());
-  }
-  return c;
+  });
 }
 
 inline std::vector<double> diagonal(const HCsr &a) {
@@ -161,19 +229,17 @@ inline std::vector<double> l1_row_norms(const HCsr &a) {
 // old -> new via colmap; colmap[c] = -1 drops the column).
 inline HCsr extract(const HCsr &a, const std::vector<int32_t> &rows,
                     const std::vector<int32_t> &colmap, int32_t ncols) {
-  HCsr s = HCsr::empty(static_cast<int32_t>(rows.size()), ncols);
-  for (size_t r = 0; r < rows.size(); ++r) {
-    const int32_t i = rows[r];
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
-      const int32_t c = colmap[a.col[p]];
-      if (c >= 0) {
-        s.col.push_back(c);
-        s.val.push_back(a.val[p]);
-      }
-    }
-    s.ptr[r + 1] = static_cast<int32_t>(s.col.size());
-  }
-  return s;
+  return build_rows(static_cast<int32_t>(rows.size()), ncols,
+                    [&](int32_t r, int, std::vector<int32_t> &C, std::vector<double> &V) {
+                      const int32_t i = rows[r];
+                      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+                        const int32_t c = colmap[a.col[p]];
+                        if (c >= 0) {
+                          C.push_back(c);
+                          V.push_back(a.val[p]);
+                        }
+                      }
+                    });
 }
 
 }  // namespace mdp

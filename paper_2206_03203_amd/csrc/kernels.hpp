@@ -180,79 +180,342 @@ __device__ __forceinline__ void red_range(int64_t n, int blk, int64_t &lo, int64
   hi = lo + chunk < n ? lo + chunk : n;
 }
 
-// partial[i * kRedBlocks + blk] = sum_{e in range(blk)} V[e + i*ld] * w[e], i < ncols.
-// NC: compile-time bound on ncols (8, 16, 32 or 64).
-template <int NC>
-__global__ __launch_bounds__(kThreads) void multi_dot_kernel(int64_t n, int ncols, const double *__restrict__ V,
-                                                             int64_t ld, const double *__restrict__ w,
-                                                             double *__restrict__ partial,
-                                                             const int *__restrict__ gate) {
-  if (gate && *gate) return;
-  __shared__ double lds[kThreads / 64];
-  int64_t lo, hi;
-  red_range(n, blockIdx.x, lo, hi);
-  double acc[NC];
+// ---------------------------------------------------------------------------
+// Arnoldi with classical Gram-Schmidt and delayed reorthogonalisation.
+//
+// At step j the basis V[:, 0..j-1] = q_0..q_{j-1} is final, V[:, j] = u_j is the
+// provisional vector (orthogonalised once), and w = A z_j with z_j = M u_j.
+// One fused pass computes a = Q^T u_j, b = Q^T w, alpha = u.u, beta = u.w,
+// gamma = w.w; a small kernel then finalises column j-1 (u_j re-orthogonalised
+// with a) and forms column j; one update pass writes q_j and u_{j+1}.
+
+constexpr int kDotU = 8;  // elements per thread in the fused reduction / update passes
+
+// Sum 8 values over the 64 lanes of a wavefront by recursive halving: after
+// the call, lane L holds in v[0] the wave total of value index
+// 4*bit5(L) + 2*bit4(L) + bit3(L) summed over the 8 lanes that share bits 5..3
+// (bits 2..0 are then reduced by a butterfly, so every lane of the group holds
+// the total).  10 shuffles instead of 48.
+__device__ __forceinline__ void wave_reduce8(double v[8]) {
+  const int lane = threadIdx.x % 64;
+  {
+    const bool hi = lane & 32;
 #pragma unroll
-  for (int i = 0; i < NC; ++i) acc[i] = 0.0;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) {
-    const double we = w[e];
-#pragma unroll
-    for (int i = 0; i < NC; ++i)
-      if (i < ncols) acc[i] += V[e + i * ld] * we;
+    for (int k = 0; k < 4; ++k) {
+      const double send = hi ? v[k] : v[k + 4];
+      const double keep = hi ? v[k + 4] : v[k];
+      v[k] = keep + __shfl_xor(send, 32, 64);
+    }
   }
+  {
+    const bool hi = lane & 16;
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    if (i >= ncols) break;
-    const double s = block_sum(acc[i], lds);
-    if (threadIdx.x == 0) partial[static_cast<int64_t>(i) * kRedBlocks + blockIdx.x] = s;
+    for (int k = 0; k < 2; ++k) {
+      const double send = hi ? v[k] : v[k + 2];
+      const double keep = hi ? v[k + 2] : v[k];
+      v[k] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+    const double send = hi ? v[0] : v[1];
+    const double keep = hi ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 8, 64);
+  }
+  v[0] += __shfl_xor(v[0], 4, 64);
+  v[0] += __shfl_xor(v[0], 2, 64);
+  v[0] += __shfl_xor(v[0], 1, 64);
+}
+
+__device__ __forceinline__ int wave_reduce8_index(int lane) {
+  return ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+}
+
+// Per-block partial sums, part[v * nblk + blk], of the 2*nq + 3 values
+// [a_0..a_{nq-1}, b_0..b_{nq-1}, alpha, beta, gamma].
+__global__ __launch_bounds__(kThreads) void dcgs_reduce_kernel(int64_t n, int nq, const double *__restrict__ V,
+                                                               int64_t ld, const double *__restrict__ w,
+                                                               double *__restrict__ part, int nblk,
+                                                               const int *__restrict__ gate) {
+  if (*gate) return;
+  __shared__ double lds[kThreads / 64][2 * kMaxCols + 8];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+  const double *u = V + static_cast<int64_t>(nq) * ld;
+  double uu[kDotU], ww[kDotU];
+#pragma unroll
+  for (int k = 0; k < kDotU; ++k) {
+    const int64_t e = base + k * kThreads;
+    uu[k] = e < n ? u[e] : 0.0;
+    ww[k] = e < n ? w[e] : 0.0;
+  }
+  const int slot = wave_reduce8_index(lane);
+  for (int c0 = 0; c0 < nq; c0 += 4) {
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c0 + c < nq) {
+        const double *q = V + static_cast<int64_t>(c0 + c) * ld;
+#pragma unroll
+        for (int k = 0; k < kDotU; ++k) {
+          const int64_t e = base + k * kThreads;
+          const double qe = e < n ? q[e] : 0.0;
+          acc[c] += qe * uu[k];
+          acc[4 + c] += qe * ww[k];
+        }
+      }
+    }
+    wave_reduce8(acc);
+    if ((lane & 7) == 0) {
+      const int c = slot & 3;
+      const int v = slot < 4 ? c0 + c : nq + c0 + c;
+      if (c0 + c < nq) lds[wave][v] = acc[0];
+    }
+  }
+  {
+    double acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDotU; ++k) {
+      acc[0] += uu[k] * uu[k];
+      acc[1] += uu[k] * ww[k];
+      acc[2] += ww[k] * ww[k];
+    }
+    wave_reduce8(acc);
+    if ((lane & 7) == 0 && slot < 3) lds[wave][2 * nq + slot] = acc[0];
+  }
+  __syncthreads();
+  const int nv = 2 * nq + 3;
+  for (int v = threadIdx.x; v < nv; v += kThreads) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kThreads / 64; ++wv) s += lds[wv][v];
+    part[static_cast<int64_t>(v) * nblk + blockIdx.x] = s;
   }
 }
 
-// out[e] = w[e] - sum_i coef[i] * V[e + i*ld]  (out may alias w), and partial
-// norms: partial[blk] = sum out[e]^2.
-template <int NC>
-__global__ __launch_bounds__(kThreads) void multi_axpy_kernel(int64_t n, int ncols, const double *__restrict__ V,
-                                                              int64_t ld, const double *__restrict__ coef,
-                                                              const double *w, double *out,
-                                                              double *__restrict__ partial_norm,
+// sums[v] = sum_blk part[v * nblk + blk]; one block per value.
+__global__ __launch_bounds__(kThreads) void block_sums_kernel(int nv, const double *__restrict__ part, int nblk,
+                                                              double *__restrict__ sums,
                                                               const int *__restrict__ gate) {
-  if (gate && *gate) return;
+  if (*gate) return;
   __shared__ double lds[kThreads / 64];
-  __shared__ double c[NC];
-  if (threadIdx.x < NC) c[threadIdx.x] = threadIdx.x < ncols ? coef[threadIdx.x] : 0.0;
-  __syncthreads();
-  int64_t lo, hi;
-  red_range(n, blockIdx.x, lo, hi);
-  double nrm = 0.0;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) {
-    double we = w[e];
-#pragma unroll
-    for (int i = 0; i < NC; ++i)
-      if (i < ncols) we -= c[i] * V[e + i * ld];
-    out[e] = we;
-    nrm += we * we;
+  const int v = blockIdx.x;
+  if (v >= nv) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kThreads) s += part[static_cast<int64_t>(v) * nblk + k];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) sums[v] = s;
+}
+
+// Givens rotation that zeroes b in (a, b).
+__device__ __forceinline__ void givens(double a, double b, double &c, double &s, double &r) {
+  r = hypot(a, b);
+  c = a / r;
+  s = b / r;
+}
+
+// Step j of the cycle (one thread does the O(j) scalar work):
+//  * j > 0: re-orthogonalise u_j against q_0..q_{j-1} (coefficients a) and
+//    finalise Hessenberg column j-1 = hprev + nu a, with subdiagonal nu r;
+//    apply the stored rotations, form rotation j-1, update g; the estimate
+//    |g_j| is final for basis size j.  Stop if it meets tol_abs or if the
+//    previous step announced that this step only finalises.
+//  * form column j from b, beta (its provisional subdiagonal from gamma),
+//    estimate the residual of basis size j+1 with a trial rotation, and
+//    announce the last step when that estimate meets tol_abs, when j+1 ==
+//    kmax, or on (near) breakdown.  Write the update-pass coefficients.
+__global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j, int kmax, double tol_abs,
+                                                           const double *__restrict__ sums,
+                                                           double *__restrict__ hprev, DcgsCoef *cf,
+                                                           double *__restrict__ Hr, int ldh,
+                                                           double *__restrict__ cs, double *__restrict__ sn,
+                                                           double *__restrict__ g, double *__restrict__ hist) {
+  if (st->done) return;
+  __shared__ double a[kMaxCols + 1], b[kMaxCols + 1], col[kMaxCols + 2], sc[kMaxCols + 1], ss[kMaxCols + 1];
+  const int t = threadIdx.x;
+  for (int i = t; i < j; i += 64) {
+    a[i] = sums[i];
+    b[i] = sums[j + i];
+    sc[i] = cs[i];
+    ss[i] = sn[i];
+    col[i] = hprev[i];
   }
-  if (partial_norm) {
-    const double s = block_sum(nrm, lds);
-    if (threadIdx.x == 0) partial_norm[blockIdx.x] = s;
+  __syncthreads();
+  if (t != 0) return;
+  const double alpha = sums[2 * j], beta = sums[2 * j + 1], gamma = sums[2 * j + 2];
+  bool bad = !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma);
+  double saa = 0.0, sab = 0.0;
+  for (int i = 0; i < j; ++i) {
+    saa += a[i] * a[i];
+    sab += a[i] * b[i];
+  }
+  double r2 = alpha - saa;
+  const double r = sqrt(r2 > 1e-30 * alpha ? r2 : 1e-30 * alpha);
+  if (j == 0) {
+    g[0] = r;  // the cycle's first vector is the unnormalised residual
+  } else {
+    const double nu = st->nu;
+    for (int i = 0; i < j; ++i) col[i] += nu * a[i];
+    col[j] = nu * r;
+    for (int i = 0; i + 1 < j; ++i) {
+      const double tt = sc[i] * col[i] + ss[i] * col[i + 1];
+      col[i + 1] = -ss[i] * col[i] + sc[i] * col[i + 1];
+      col[i] = tt;
+    }
+    double c, s, rr;
+    givens(col[j - 1], col[j], c, s, rr);
+    cs[j - 1] = c;
+    sn[j - 1] = s;
+    col[j - 1] = rr;
+    col[j] = 0.0;
+    for (int i = 0; i <= j; ++i) Hr[static_cast<int64_t>(j - 1) * ldh + i] = col[i];
+    const double gj = g[j - 1];
+    g[j] = -s * gj;
+    g[j - 1] = c * gj;
+    const double est = fabs(g[j]);
+    hist[j - 1] = est;
+    st->k = j;
+    st->est = est;
+    bad = bad || !isfinite(est);
+    if (bad || st->finishing || est <= tol_abs) {
+      st->nan = bad;
+      st->done = 1;
+      st->skip_apply = 1;
+      return;
+    }
+    for (int i = 0; i < j; ++i) sc[i] = cs[i], ss[i] = sn[i];
+  }
+  // provisional column j
+  double sh = 0.0;
+  for (int i = 0; i < j; ++i) {
+    col[i] = b[i];
+    sh += b[i] * b[i];
+  }
+  const double hj = (beta - sab) / r;
+  col[j] = hj;
+  sh += hj * hj;
+  const double nu2 = gamma - sh;
+  const bool brk = !(nu2 > 1e-24 * gamma);
+  const double nu = sqrt(brk ? 1e-24 * gamma : nu2);
+  for (int i = 0; i <= j; ++i) hprev[i] = col[i];
+  // trial rotation for the estimate of basis size j+1
+  for (int i = 0; i < j; ++i) {
+    const double tt = sc[i] * col[i] + ss[i] * col[i + 1];
+    col[i + 1] = -ss[i] * col[i] + sc[i] * col[i + 1];
+    col[i] = tt;
+  }
+  double c, s, rr;
+  givens(col[j], nu, c, s, rr);
+  const double est_next = fabs(s * g[j]);
+  bad = bad || !isfinite(hj) || !isfinite(nu) || !(r > 0.0);
+  cf->inv_r = 1.0 / r;
+  cf->hj = hj;
+  cf->inv_nu = 1.0 / nu;
+  for (int i = 0; i < j; ++i) {
+    cf->a[i] = a[i];
+    cf->b[i] = b[i];
+  }
+  st->nu = nu;
+  st->nan = bad;
+  if (bad) {
+    st->done = 1;
+    st->skip_apply = 1;
+    return;
+  }
+  if (brk || est_next <= tol_abs || j + 1 >= kmax) {
+    st->finishing = 1;
+    st->skip_apply = 1;
+  }
+}
+
+// q_j = (u_j - sum_i a_i q_i) * inv_r ;  u_{j+1} = (w - sum_i b_i q_i - hj q_j) * inv_nu
+__global__ __launch_bounds__(kThreads) void dcgs_update_kernel(int64_t n, int nq, double *__restrict__ V, int64_t ld,
+                                                               const double *__restrict__ w,
+                                                               const DcgsCoef *__restrict__ cf,
+                                                               const int *__restrict__ gate) {
+  if (*gate) return;
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+  double *u = V + static_cast<int64_t>(nq) * ld;
+  double *un = u + ld;
+  double uu[kDotU], ww[kDotU];
+#pragma unroll
+  for (int k = 0; k < kDotU; ++k) {
+    const int64_t e = base + k * kThreads;
+    uu[k] = e < n ? u[e] : 0.0;
+    ww[k] = e < n ? w[e] : 0.0;
+  }
+  int i = 0;
+  for (; i + 4 <= nq; i += 4) {
+    double ca[4], cb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ca[c] = cf->a[i + c];
+      cb[c] = cf->b[i + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double *q = V + static_cast<int64_t>(i + c) * ld;
+#pragma unroll
+      for (int k = 0; k < kDotU; ++k) {
+        const int64_t e = base + k * kThreads;
+        const double qe = e < n ? q[e] : 0.0;
+        uu[k] -= ca[c] * qe;
+        ww[k] -= cb[c] * qe;
+      }
+    }
+  }
+  for (; i < nq; ++i) {
+    const double ca = cf->a[i], cb = cf->b[i];
+    const double *q = V + static_cast<int64_t>(i) * ld;
+#pragma unroll
+    for (int k = 0; k < kDotU; ++k) {
+      const int64_t e = base + k * kThreads;
+      const double qe = e < n ? q[e] : 0.0;
+      uu[k] -= ca * qe;
+      ww[k] -= cb * qe;
+    }
+  }
+  const double inv_r = cf->inv_r, hj = cf->hj, inv_nu = cf->inv_nu;
+#pragma unroll
+  for (int k = 0; k < kDotU; ++k) {
+    const int64_t e = base + k * kThreads;
+    if (e < n) {
+      const double qj = uu[k] * inv_r;
+      u[e] = qj;
+      un[e] = (ww[k] - hj * qj) * inv_nu;
+    }
   }
 }
 
 // x[e] += sum_i y[i] * Z[e + i*ldz]  (Z in the preconditioner precision)
-template <int NC, typename TZ>
+template <typename TZ>
 __global__ __launch_bounds__(kThreads) void update_x_kernel(int64_t n, int ncols, const TZ *__restrict__ Z,
                                                             int64_t ldz, const double *__restrict__ y,
                                                             double *__restrict__ x) {
-  __shared__ double c[NC];
-  if (threadIdx.x < NC) c[threadIdx.x] = threadIdx.x < ncols ? y[threadIdx.x] : 0.0;
-  __syncthreads();
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; e < n;
-       e += static_cast<int64_t>(gridDim.x) * kThreads) {
-    double xe = x[e];
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+  double xx[kDotU];
 #pragma unroll
-    for (int i = 0; i < NC; ++i)
-      if (i < ncols) xe += c[i] * static_cast<double>(Z[e + i * ldz]);
-    x[e] = xe;
+  for (int k = 0; k < kDotU; ++k) {
+    const int64_t e = base + k * kThreads;
+    xx[k] = e < n ? x[e] : 0.0;
+  }
+  for (int i = 0; i < ncols; ++i) {
+    const double yi = y[i];
+    const TZ *z = Z + static_cast<int64_t>(i) * ldz;
+#pragma unroll
+    for (int k = 0; k < kDotU; ++k) {
+      const int64_t e = base + k * kThreads;
+      if (e < n) xx[k] += yi * static_cast<double>(z[e]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kDotU; ++k) {
+    const int64_t e = base + k * kThreads;
+    if (e < n) x[e] = xx[k];
   }
 }
 
@@ -268,28 +531,6 @@ __global__ __launch_bounds__(kThreads) void norm2_partial_kernel(int64_t n, cons
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// One block per column i < ncols:
-//   h[i] = scale[i] * sum_blk partial[i*kRedBlocks + blk];  coef[i] = h[i] * scale[i]
-// (scale = per-column normalisation of the stored Krylov vectors).
-__global__ __launch_bounds__(kThreads) void reduce_cols_kernel(int ncols, const double *__restrict__ partial,
-                                                               const double *__restrict__ scale,
-                                                               double *__restrict__ h,
-                                                               double *__restrict__ coef,
-                                                               const int *__restrict__ gate) {
-  if (gate && *gate) return;
-  __shared__ double lds[kThreads / 64];
-  const int i = blockIdx.x;
-  if (i >= ncols) return;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < kRedBlocks; k += kThreads) s += partial[static_cast<int64_t>(i) * kRedBlocks + k];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) {
-    const double hi = s * scale[i];
-    h[i] = hi;
-    coef[i] = hi * scale[i];
-  }
-}
-
 // Sum of kRedBlocks partials into *out (single block), sqrt if requested.
 __global__ __launch_bounds__(kThreads) void reduce_scalar_kernel(const double *__restrict__ partial,
                                                                  double *__restrict__ out, int take_sqrt) {
@@ -300,90 +541,38 @@ __global__ __launch_bounds__(kThreads) void reduce_scalar_kernel(const double *_
   if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
 }
 
-// ---------------------------------------------------------------------------
-
-
-// Start a cycle: beta = *rnorm, g = (beta, 0, ...), scale[0] = 1/beta.
-__global__ void cycle_init_kernel(GmresState *st, const double *__restrict__ rnorm, double *__restrict__ g,
-                                  double *__restrict__ scale, int m) {
-  const double beta = *rnorm;
+// Start a cycle: clear the state and g.
+__global__ void cycle_init_kernel(GmresState *st, double *__restrict__ g, int m) {
   for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = 0.0;
-  __syncthreads();
   if (threadIdx.x == 0) {
     st->done = 0;
+    st->skip_apply = 0;
+    st->finishing = 0;
     st->k = 0;
-    st->nan = !isfinite(beta);
-    st->breakdown = 0;
-    st->est = beta;
-    st->beta = beta;
-    g[0] = beta;
-    scale[0] = 1.0 / beta;
+    st->nan = 0;
+    st->est = 0.0;
+    st->nu = 1.0;
   }
 }
 
-// Givens step for column j (single thread does the O(j) work):
-//   H(:, j) = h1 + h2 (CGS2 coefficients), H(j+1, j) = ||w|| from partials.
-// Applies the stored rotations, builds the new one, updates g, sets the
-// residual estimate and the done flag (estimate <= tol_abs, breakdown, or j+1
-// == kmax), and scale[j+1] = 1 / H(j+1, j).
-__global__ __launch_bounds__(kThreads) void givens_kernel(GmresState *st, int j, int kmax, double tol_abs,
-                                                          const double *__restrict__ h1,
-                                                          const double *__restrict__ h2,
-                                                          const double *__restrict__ norm_partial,
-                                                          double *__restrict__ Hr /* (m+1) x m, col-major */,
-                                                          int ldh, double *__restrict__ cs,
-                                                          double *__restrict__ sn, double *__restrict__ g,
-                                                          double *__restrict__ scale,
-                                                          double *__restrict__ hist) {
-  if (st->done) return;
-  __shared__ double lds[kThreads / 64];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < kRedBlocks; k += kThreads) s += norm_partial[k];
-  s = block_sum(s, lds);
-  if (threadIdx.x != 0) return;
-  const double hn = sqrt(s);
-  double *col = Hr + static_cast<int64_t>(j) * ldh;
-  bool bad = !isfinite(hn);
-  for (int i = 0; i <= j; ++i) {
-    col[i] = h1[i] + h2[i];
-    bad = bad || !isfinite(col[i]);
-  }
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
-  }
-  const double a = col[j], bb = hn;
-  const double den = hypot(a, bb);
-  const double c = a / den, sg = bb / den;
-  cs[j] = c;
-  sn[j] = sg;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  const double gj = g[j];
-  g[j + 1] = -sg * gj;
-  g[j] = c * gj;
-  const double est = fabs(g[j + 1]);
-  hist[j] = est;
-  st->est = est;
-  st->k = j + 1;
-  const bool brk = (hn == 0.0);
-  bad = bad || !isfinite(est);
-  st->nan = bad;
-  st->breakdown = brk;
-  scale[j + 1] = brk ? 0.0 : 1.0 / hn;
-  if (bad || brk || est <= tol_abs || j + 1 >= kmax) st->done = 1;
-}
-
-// Back substitution y = R(0:k,0:k)^{-1} g(0:k) for the k steps of the cycle.
-__global__ void backsolve_kernel(const GmresState *st, const double *__restrict__ Hr, int ldh,
-                                 const double *__restrict__ g, double *__restrict__ y) {
-  if (threadIdx.x != 0) return;
-  const int k = st->k;
+// Back substitution y = R(0:k,0:k)^{-1} g(0:k), one wavefront: R is staged in
+// LDS, each step finishes one unknown and updates the remaining right-hand side
+// in parallel.
+__global__ __launch_bounds__(64) void backsolve_kernel(const GmresState *st, const double *__restrict__ Hr, int ldh,
+                                                       const double *__restrict__ g, double *__restrict__ y) {
+  __shared__ double R[kMaxCols][kMaxCols + 1];
+  __shared__ double rhs[kMaxCols];
+  const int k = st->k, t = threadIdx.x;
+  for (int c = 0; c < k; ++c)
+    for (int i = t; i <= c; i += 64) R[i][c] = Hr[static_cast<int64_t>(c) * ldh + i];
+  for (int i = t; i < k; i += 64) rhs[i] = g[i];
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int c = i + 1; c < k; ++c) s -= Hr[static_cast<int64_t>(c) * ldh + i] * y[c];
-    y[i] = s / Hr[static_cast<int64_t>(i) * ldh + i];
+    const double yi = rhs[i] / R[i][i];
+    __syncthreads();
+    for (int r = t; r < i; r += 64) rhs[r] -= R[r][i] * yi;
+    if (t == 0) y[i] = yi;
+    __syncthreads();
   }
 }
 

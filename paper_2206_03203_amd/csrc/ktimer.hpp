@@ -1,0 +1,49 @@
+// Kernel-class timers: HIP events recorded around each launch of a class on
+// the stream it is launched on, with the algorithmic bytes of that launch
+// (every matrix value and index once, every vector once).  Off by default.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mdp {
+
+enum KClass : int {
+  kKcOuterSpmv = 0,   // w = A z_j, FP64 system matrix
+  kKcFineSmooth = 1,  // finest level of the S~ hierarchy: fused pre-smoothing+residual, post-smoothing
+  kKcVcycleOther = 2, // other V-cycle kernels (restriction, prolongation, coarser levels, A_GG, A_GO)
+  kKcArnoldiDot = 3,  // multi-dot passes of CGS2
+  kKcArnoldiAxpy = 4, // multi-axpy passes of CGS2
+  kKcOther = 5,       // casts, reductions, Givens, solution update, residual
+  kKcCount = 6
+};
+
+bool ktimer_on(int kind);
+
+// Algorithmic-byte counters, saved before a batch of launches and restored
+// when those launches turn out to be retired no-ops (gated after
+// convergence): their time still counts, their bytes do not.
+struct KtBytes {
+  double b[kKcCount];
+};
+KtBytes ktimer_bytes();
+void ktimer_restore_bytes(const KtBytes &s);
+// Returns the event pair to record around the next launch of `kind`.
+void ktimer_pair(int kind, double bytes, hipEvent_t *start, hipEvent_t *stop);
+
+// Run `launch` bracketed by timing events when the class is enabled.
+template <typename F>
+inline void timed_launch(int kind, hipStream_t s, double bytes, F &&launch) {
+  if (!ktimer_on(kind)) {
+    launch();
+    return;
+  }
+  hipEvent_t a, b;
+  ktimer_pair(kind, bytes, &a, &b);
+  (void)hipEventRecord(a, s);
+  launch();
+  (void)hipEventRecord(b, s);
+}
+
+}  // namespace mdp

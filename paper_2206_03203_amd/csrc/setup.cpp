@@ -17,7 +17,10 @@
 //  * coarsest: dense LU inverse if n <= max_dense, else l1-Jacobi sweeps.
 #include "setup.hpp"
 
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <limits>
 #include <numeric>
 
@@ -26,6 +29,18 @@ namespace mdp {
 namespace {
 
 [[noreturn]] void fail(int code, const std::string &msg) { throw SetupError{code, msg}; }
+
+// Phase timings on stderr when MDP_SETUP_VERBOSE is set.
+struct PhaseClock {
+  bool on = std::getenv("MDP_SETUP_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char *what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[mdp setup] %-28s %8.3f s\n", what, std::chrono::duration<double>(now - t).count());
+    t = now;
+  }
+};
 
 void validate(const mdp_csr *A, const int32_t *part) {
   if (!A || !part) fail(MDP_EINVAL, "NULL matrix or partition");
@@ -218,6 +233,7 @@ void check_grounded(const HCsr &a) {
 }  // namespace
 
 HHier amg_setup(const HCsr &A, const AmgParams &prm) {
+  PhaseClock clk;
   HHier h;
   HCsr cur = A;
   std::vector<int32_t> sp, sc;
@@ -230,25 +246,35 @@ HHier amg_setup(const HCsr &A, const AmgParams &prm) {
     HLevel &L = h.lv.back();
     if (n <= prm.max_coarse || static_cast<int32_t>(h.lv.size()) >= prm.max_levels) break;
     strength(L.A, prm.theta, sp, sc);
+    clk.lap("strength");
     std::vector<int32_t> agg;
     const int32_t na = aggregate(n, sp, sc, agg);
+    clk.lap("aggregate");
     if (na == 0 || na > 0.9 * n) break;
     L.P = smooth_prolongator(L.A, tentative(agg, na));
+    clk.lap("prolongator");
     L.R = transpose(L.P);
     L.agg = std::move(agg);
-    cur = spgemm(spgemm(L.R, L.A), L.P);
+    clk.lap("transpose");
+    HCsr ra = spgemm(L.R, L.A);
+    clk.lap("R A");
+    cur = spgemm(ra, L.P);
+    clk.lap("(R A) P");
   }
   const HLevel &last = h.lv.back();
   if (last.A.nr <= prm.max_dense) {
     h.dense = true;
     h.coarse_inv = dense_inverse(last.A);
   }
+  clk.lap("coarsest inverse");
   return h;
 }
 
 void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_options &opt,
                        HostSystem &s) {
+  PhaseClock clk;
   validate(Ain, part);
+  clk.lap("validate");
   const int32_t n = Ain->n;
   s.n = n;
   s.perm.clear();
@@ -279,6 +305,7 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
   }
   sort_rows(A);
   check_diag(A, "A");
+  clk.lap("permute");
 
   // symmetry check (informational: the method does not need it)
   {
@@ -286,6 +313,7 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
     s.symmetric = (t.col == A.col && t.val == A.val);
   }
   if (s.symmetric) check_grounded(A);
+  clk.lap("symmetry + grounding");
 
   std::vector<int32_t> rows_o(static_cast<size_t>(s.n_o)), rows_g(static_cast<size_t>(s.n_g));
   std::iota(rows_o.begin(), rows_o.end(), 0);
@@ -308,6 +336,7 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
     s.S = s.Aoo;
   }
   check_diag(s.S, "S~");
+  clk.lap("blocks + S~");
 
   AmgParams prm;
   prm.theta = opt.strength_theta;

@@ -16,8 +16,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.hpp"
+#include "ktimer.hpp"
 #include "solver.hpp"
 
 namespace mdp {
@@ -86,26 +88,42 @@ int grid_for(int64_t n) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
 }
 
+// Algorithmic bytes of one sparse product: matrix values, column indices and
+// row pointers once, each vector entry read or written once.
+template <int MODE, typename TA, typename TX, typename TY>
+double spmv_bytes(const DCsr<TA> &A) {
+  double b = (sizeof(TA) + 4.0) * A.nnz + 4.0 * (A.nr + 1.0);
+  const double sx = sizeof(TX), sy = sizeof(TY);
+  if (MODE == kPlain) b += sx * A.nc + sy * A.nr;
+  if (MODE == kResid) b += sx * A.nc + 2 * sy * A.nr;
+  if (MODE == kSmooth) b += sx * A.nc + 3 * sy * A.nr;  // x, b, dinv, y
+  if (MODE == kPre0) b += 2 * sy * A.nc + 2 * sy * A.nr;  // b, dinv; y2, y
+  if (MODE == kAccum) b += sx * A.nc + 2 * sy * A.nr;
+  return b;
+}
+
 template <int LPR, int MODE, typename TA, typename TX, typename TY>
 void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2,
-                 const int *gate, hipStream_t s) {
+                 const int *gate, hipStream_t s, int kind) {
   const int64_t rows_per_blk = kThreads / LPR;
   const int blocks = static_cast<int>((A.nr + rows_per_blk - 1) / rows_per_blk);
-  hipLaunchKernelGGL((spmv_kernel<LPR, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
-                     A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+  timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+    hipLaunchKernelGGL((spmv_kernel<LPR, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
+                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+  });
 }
 
 template <int MODE, typename TA, typename TX, typename TY>
 void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, const int *gate,
-          hipStream_t s) {
+          hipStream_t s, int kind = kKcOther) {
   if (A.nr == 0) return;
   switch (A.lpr) {
-    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s); break;
-    case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s); break;
-    case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s); break;
-    case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s); break;
-    case 32: spmv_launch<32, MODE>(A, x, b, dinv, y, y2, gate, s); break;
-    default: spmv_launch<64, MODE>(A, x, b, dinv, y, y2, gate, s); break;
+    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+    case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+    case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+    case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+    case 32: spmv_launch<32, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+    default: spmv_launch<64, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
   }
 }
 
@@ -116,17 +134,20 @@ void coarse_solve(DHier<T> &H, const T *b, T *x, const int *gate, hipStream_t s)
   if (n == 0) return;
   if (H.dense) {
     const int blocks = (n + (kThreads / 64) - 1) / (kThreads / 64);
-    hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, n, dptr<const double>(H.cinv),
-                       b, x, gate);
+    timed_launch(kKcVcycleOther, s, 8.0 * n * n + 2.0 * sizeof(T) * n, [&] {
+      hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, n, dptr<const double>(H.cinv),
+                         b, x, gate);
+    });
     return;
   }
   // four l1-Jacobi sweeps from zero, ping-pong ending in x
   T *pa = dptr<T>(H.tmp_pp), *pb = pa + n;
   hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
                      dptr<const T>(L.dinv), pa, gate);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), pb, static_cast<T *>(nullptr), gate, s);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dptr<const T>(L.dinv), pa, static_cast<T *>(nullptr), gate, s);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), x, static_cast<T *>(nullptr), gate, s);
+  const int kc = kKcVcycleOther;
+  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), pb, static_cast<T *>(nullptr), gate, s, kc);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dptr<const T>(L.dinv), pa, static_cast<T *>(nullptr), gate, s, kc);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), x, static_cast<T *>(nullptr), gate, s, kc);
 }
 
 // One V-cycle from a zero initial guess: x = V(b).
@@ -140,13 +161,15 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_
   DLevel<T> &C = H.lv[l + 1];
   T *t = dptr<T>(L.t);
   const T *dinv = dptr<const T>(L.dinv);
-  spmv<kPre0>(L.A, static_cast<const T *>(nullptr), b, dinv, dptr<T>(L.r), t, gate, s);  // t = D^-1 b, r = b - A t
+  const int ks = (H.is_omega && l == 0) ? kKcFineSmooth : kKcVcycleOther;
+  const int ko = kKcVcycleOther;
+  spmv<kPre0>(L.A, static_cast<const T *>(nullptr), b, dinv, dptr<T>(L.r), t, gate, s, ks);  // t = D^-1 b, r = b - A t
   spmv<kPlain>(L.R, dptr<const T>(L.r), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr),
-               dptr<T>(C.b), static_cast<T *>(nullptr), gate, s);  // b_c = R r
+               dptr<T>(C.b), static_cast<T *>(nullptr), gate, s, ko);  // b_c = R r
   vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
   spmv<kAccum>(L.P, dptr<const T>(C.x), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr), t,
-               static_cast<T *>(nullptr), gate, s);  // t += P x_c
-  spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, static_cast<T *>(nullptr), gate, s);  // post-smooth
+               static_cast<T *>(nullptr), gate, s, ko);  // t += P x_c
+  spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, static_cast<T *>(nullptr), gate, s, ks);  // post-smooth
 }
 
 // Q = `cycles` V-cycles as a stationary iteration from zero.
@@ -156,7 +179,7 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStre
   const int n = H.n();
   for (int c = 1; c < cycles; ++c) {
     spmv<kResid>(H.lv[0].A, static_cast<const T *>(z), r, static_cast<const T *>(nullptr), dptr<T>(H.tmp_res),
-                 static_cast<T *>(nullptr), gate, s);
+                 static_cast<T *>(nullptr), gate, s, kKcVcycleOther);
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
                        gate);
@@ -170,7 +193,7 @@ void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
   if (P.n_g == 0) return;
   T *rg = dptr<T>(P.rg);
   spmv<kResid>(P.Ago, static_cast<const T *>(z), r + P.n_o, static_cast<const T *>(nullptr), rg,
-               static_cast<T *>(nullptr), gate, s);  // r_G - A_GO z_O
+               static_cast<T *>(nullptr), gate, s, kKcVcycleOther);  // r_G - A_GO z_O
   apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
 }
 
@@ -182,6 +205,7 @@ std::unique_ptr<Precond<T>> upload_precond(const HostSystem &h, int vcycles, hip
   p->n_g = h.n_g;
   p->vcycles = vcycles;
   upload_hier(h.Ho, p->Ho, s, keep);
+  p->Ho.is_omega = true;
   if (h.n_g > 0) {
     upload_hier(h.Hg, p->Hg, s, keep);
     upload_csr(h.Ago, p->Ago, s, keep);
@@ -191,42 +215,13 @@ std::unique_ptr<Precond<T>> upload_precond(const HostSystem &h, int vcycles, hip
   return p;
 }
 
-template <int NC>
-void arnoldi_launch_dot(int64_t n, int ncols, const double *V, int64_t ld, const double *w, double *partial,
-                        const int *gate, hipStream_t s) {
-  hipLaunchKernelGGL(multi_dot_kernel<NC>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, ncols, V, ld, w, partial,
-                     gate);
-}
-template <int NC>
-void arnoldi_launch_axpy(int64_t n, int ncols, const double *V, int64_t ld, const double *coef, const double *w,
-                         double *out, double *npart, const int *gate, hipStream_t s) {
-  hipLaunchKernelGGL(multi_axpy_kernel<NC>, dim3(kRedBlocks), dim3(kThreads), 0, s, n, ncols, V, ld, coef, w,
-                     out, npart, gate);
-}
-
-void multi_dot(int64_t n, int ncols, const double *V, int64_t ld, const double *w, double *partial,
-               const int *gate, hipStream_t s) {
-  if (ncols <= 8) arnoldi_launch_dot<8>(n, ncols, V, ld, w, partial, gate, s);
-  else if (ncols <= 16) arnoldi_launch_dot<16>(n, ncols, V, ld, w, partial, gate, s);
-  else if (ncols <= 32) arnoldi_launch_dot<32>(n, ncols, V, ld, w, partial, gate, s);
-  else arnoldi_launch_dot<64>(n, ncols, V, ld, w, partial, gate, s);
-}
-
-void multi_axpy(int64_t n, int ncols, const double *V, int64_t ld, const double *coef, const double *w,
-                double *out, double *npart, const int *gate, hipStream_t s) {
-  if (ncols <= 8) arnoldi_launch_axpy<8>(n, ncols, V, ld, coef, w, out, npart, gate, s);
-  else if (ncols <= 16) arnoldi_launch_axpy<16>(n, ncols, V, ld, coef, w, out, npart, gate, s);
-  else if (ncols <= 32) arnoldi_launch_axpy<32>(n, ncols, V, ld, coef, w, out, npart, gate, s);
-  else arnoldi_launch_axpy<64>(n, ncols, V, ld, coef, w, out, npart, gate, s);
-}
+int dcgs_blocks(int64_t n) { return static_cast<int>((n + kThreads * kDotU - 1) / (kThreads * kDotU)); }
 
 template <typename TZ>
 void update_x(int64_t n, int ncols, const TZ *Z, int64_t ld, const double *y, double *x, hipStream_t s) {
-  const int g = grid_for(n);
-  if (ncols <= 8) hipLaunchKernelGGL((update_x_kernel<8, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
-  else if (ncols <= 16) hipLaunchKernelGGL((update_x_kernel<16, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
-  else if (ncols <= 32) hipLaunchKernelGGL((update_x_kernel<32, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
-  else hipLaunchKernelGGL((update_x_kernel<64, TZ>), dim3(g), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+  timed_launch(kKcOther, s, (16.0 + sizeof(TZ) * ncols) * n, [&] {
+    hipLaunchKernelGGL((update_x_kernel<TZ>), dim3(dcgs_blocks(n)), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
+  });
 }
 
 // ||v|| into ws.scalar (device) and returned to the host (synchronises s).
@@ -249,7 +244,6 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
   T *Z = dptr<T>(ws.Z);
   double *w = dptr<double>(ws.w);
   GmresState *dst = dptr<GmresState>(ws.state);
-  const int *gate = &dst->done;
 
   // caller order -> [Omega; Gamma]
   const double *bp = b;
@@ -295,6 +289,9 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
 
   int iters = 0, cycles = 0, code = MDP_OK;
   double est = beta;
+  const int nblk = dcgs_blocks(n);
+  const int *gate_apply = &dst->skip_apply;
+  const int *gate_done = &dst->done;
   while (true) {
     if (!std::isfinite(beta)) {
       code = MDP_ENAN;
@@ -302,36 +299,58 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
     }
     if (beta <= tol_abs || iters >= S.opt.max_iter) break;
     const int kmax = std::min(m, S.opt.max_iter - iters);
-    hipLaunchKernelGGL(cycle_init_kernel, dim3(1), dim3(64), 0, s, dst, dptr<const double>(ws.scalar),
-                       dptr<double>(ws.g), dptr<double>(ws.scale), m);
+    // V[:, 0] holds the residual of the cycle start, unnormalised.
+    hipLaunchKernelGGL(cycle_init_kernel, dim3(1), dim3(64), 0, s, dst, dptr<double>(ws.g), m);
     int last = -1;
-    for (int j = 0; j < kmax; ++j) {
-      T *zj = Z + j * ld;
-      T *rin = dptr<T>(ws.rin);
-      hipLaunchKernelGGL((scale_copy_kernel<double, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, n,
-                         static_cast<const double *>(V + j * ld), dptr<const double>(ws.scale) + j, rin, gate);
-      apply_ml(P, static_cast<const T *>(rin), zj, gate, s);
+    // Steps 0..kmax-1 apply the preconditioner; step kmax (if reached) only
+    // finalises the last Hessenberg column.
+    for (int j = 0; j <= kmax; ++j) {
+      const KtBytes kt_before = ktimer_bytes();
+      T *zj = Z + std::min(j, kmax - 1) * ld;
+      const double *uj = V + j * ld;
+      const T *pin;
+      if constexpr (std::is_same<T, double>::value) {
+        pin = uj;
+      } else {
+        T *rin = dptr<T>(ws.rin);
+        timed_launch(kKcOther, s, 12.0 * n, [&] {
+          hipLaunchKernelGGL((scale_copy_kernel<double, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, uj,
+                             static_cast<const double *>(nullptr), rin, gate_apply);
+        });
+        pin = rin;
+      }
+      apply_ml(P, pin, zj, gate_apply, s);
       spmv<kPlain>(S.A, static_cast<const T *>(zj), static_cast<const double *>(nullptr),
-                   static_cast<const double *>(nullptr), w, static_cast<double *>(nullptr), gate, s);
-      const int nc = j + 1;
-      multi_dot(n, nc, V, ld, w, dptr<double>(ws.partial), gate, s);
-      hipLaunchKernelGGL(reduce_cols_kernel, dim3(nc), dim3(kThreads), 0, s, nc, dptr<const double>(ws.partial),
-                         dptr<const double>(ws.scale), dptr<double>(ws.h1), dptr<double>(ws.c1), gate);
-      multi_axpy(n, nc, V, ld, dptr<const double>(ws.c1), w, w, static_cast<double *>(nullptr), gate, s);
-      multi_dot(n, nc, V, ld, w, dptr<double>(ws.partial), gate, s);
-      hipLaunchKernelGGL(reduce_cols_kernel, dim3(nc), dim3(kThreads), 0, s, nc, dptr<const double>(ws.partial),
-                         dptr<const double>(ws.scale), dptr<double>(ws.h2), dptr<double>(ws.c2), gate);
-      multi_axpy(n, nc, V, ld, dptr<const double>(ws.c2), w, V + (j + 1) * ld, dptr<double>(ws.npartial), gate, s);
-      hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(kThreads), 0, s, dst, j, kmax, tol_abs,
-                         dptr<const double>(ws.h1), dptr<const double>(ws.h2), dptr<const double>(ws.npartial),
-                         dptr<double>(ws.Hr), m + 1, dptr<double>(ws.cs), dptr<double>(ws.sn), dptr<double>(ws.g),
-                         dptr<double>(ws.scale), dptr<double>(ws.hist));
+                   static_cast<const double *>(nullptr), w, static_cast<double *>(nullptr), gate_apply, s,
+                   kKcOuterSpmv);
+      const int nv = 2 * j + 3;
+      timed_launch(kKcArnoldiDot, s, 8.0 * n * (j + 2), [&] {
+        hipLaunchKernelGGL(dcgs_reduce_kernel, dim3(nblk), dim3(kThreads), 0, s, n, j, static_cast<const double *>(V),
+                           ld, static_cast<const double *>(w), dptr<double>(ws.partial), nblk, gate_done);
+      });
+      timed_launch(kKcOther, s, 8.0 * nv * nblk, [&] {
+        hipLaunchKernelGGL(block_sums_kernel, dim3(nv), dim3(kThreads), 0, s, nv, dptr<const double>(ws.partial),
+                           nblk, dptr<double>(ws.sums), gate_done);
+      });
+      timed_launch(kKcOther, s, 0.0, [&] {
+        hipLaunchKernelGGL(dcgs_finalize_kernel, dim3(1), dim3(64), 0, s, dst, j, kmax, tol_abs,
+                           dptr<const double>(ws.sums), dptr<double>(ws.hprev), dptr<DcgsCoef>(ws.coef),
+                           dptr<double>(ws.Hr), m + 1, dptr<double>(ws.cs), dptr<double>(ws.sn),
+                           dptr<double>(ws.g), dptr<double>(ws.hist));
+      });
+      timed_launch(kKcArnoldiAxpy, s, 8.0 * n * (j + 4), [&] {
+        hipLaunchKernelGGL(dcgs_update_kernel, dim3(nblk), dim3(kThreads), 0, s, n, j, V, ld,
+                           static_cast<const double *>(w), dptr<const DcgsCoef>(ws.coef), gate_done);
+      });
       MDP_HIP(hipMemcpyAsync(&ws.host_state[j], dst, sizeof(GmresState), hipMemcpyDeviceToHost, s));
       MDP_HIP(hipEventRecord(ws.ev[j], s));
       last = j;
       if (j >= 1) {
         MDP_HIP(hipEventSynchronize(ws.ev[j - 1]));
-        if (ws.host_state[j - 1].done) break;
+        if (ws.host_state[j - 1].done) {
+          ktimer_restore_bytes(kt_before);  // step j was queued after the cycle ended: a no-op
+          break;
+        }
       }
     }
     MDP_HIP(hipGetLastError());
@@ -345,8 +364,8 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
     est = fs.est;
     iters += k;
     ++cycles;
-    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, dst, dptr<const double>(ws.Hr), m + 1,
-                       dptr<const double>(ws.g), dptr<double>(ws.y));
+    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, static_cast<const GmresState *>(dst),
+                       dptr<const double>(ws.Hr), m + 1, dptr<const double>(ws.g), dptr<double>(ws.y));
     update_x(n, k, static_cast<const T *>(Z), ld, dptr<const double>(ws.y), xp, s);
     spmv<kResid>(S.A, static_cast<const double *>(xp), bp, static_cast<const double *>(nullptr), V,
                  static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
@@ -401,10 +420,11 @@ void Solver::upload(hipStream_t s) {
     ws.xp.alloc(col8);
   }
   const size_t mm = static_cast<size_t>(ws.m) + 1;
-  for (DevMem *d : {&ws.h1, &ws.c1, &ws.h2, &ws.c2, &ws.cs, &ws.sn, &ws.g, &ws.scale, &ws.y, &ws.hist})
-    d->alloc(mm * sizeof(double));
+  for (DevMem *d : {&ws.cs, &ws.sn, &ws.g, &ws.y, &ws.hist, &ws.hprev}) d->alloc(mm * sizeof(double));
   ws.Hr.alloc(mm * ws.m * sizeof(double));
-  ws.partial.alloc(static_cast<size_t>(kMaxCols + 1) * kRedBlocks * sizeof(double));
+  ws.coef.alloc(sizeof(DcgsCoef));
+  ws.sums.alloc((2 * mm + 3) * sizeof(double));
+  ws.partial.alloc((2 * mm + 3) * static_cast<size_t>(dcgs_blocks(n)) * sizeof(double));
   ws.npartial.alloc(kRedBlocks * sizeof(double));
   ws.scalar.alloc(sizeof(double));
   ws.state.alloc(sizeof(GmresState));

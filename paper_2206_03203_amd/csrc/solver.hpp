@@ -41,6 +41,7 @@ struct DHier {
   DevMem cinv;           // dense FP64 inverse of the coarsest level
   DevMem tmp_res, tmp_dz;  // extra cycles: residual and correction at level 0
   DevMem tmp_pp;          // coarsest l1-Jacobi ping-pong
+  bool is_omega = false;  // hierarchy on S~ (its finest level is timed separately)
   int32_t n() const { return lv.empty() ? 0 : lv[0].n; }
 };
 
@@ -58,7 +59,7 @@ struct Workspace {
   int64_t ld = 0;  // leading dimension of V / Z columns
   int m = 0;       // restart length
   DevMem V, Z, w, w2, bp, xp, rin;
-  DevMem h1, c1, h2, c2, Hr, cs, sn, g, scale, y, hist;
+  DevMem Hr, cs, sn, g, y, hist, hprev, coef, sums;
   DevMem partial, npartial, scalar;  // reduction scratch
   DevMem state;                      // GmresState
   GmresState *host_state = nullptr;  // pinned, one slot per Arnoldi step

@@ -12,12 +12,23 @@ constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi
 
 // Per-cycle FGMRES state in device memory.
 struct GmresState {
-  int done;      // set: later kernels of this cycle return at once
-  int k;         // Arnoldi steps completed in this cycle
-  int nan;       // a non-finite value appeared
-  int breakdown; // h_{k+1,k} == 0
-  double est;    // |g_k| (absolute residual estimate)
-  double beta;   // residual norm at the cycle start
+  int done;        // the cycle has ended: every later kernel of the cycle returns at once
+  int skip_apply;  // no further preconditioner / system-matrix applications this cycle
+  int finishing;   // the next step only finalises the last Hessenberg column
+  int k;           // Krylov basis size whose least-squares problem is final
+  int nan;         // a non-finite value appeared
+  int pad;
+  double est;      // |g_k|: residual-norm estimate for the final basis of size k
+  double nu;       // scale applied to the provisional vector of the next step
+};
+
+// Per-step coefficients written by the finalise kernel for the update pass.
+//   q_j     = (u_j - sum_i a_i q_i) * inv_r
+//   u_{j+1} = (w - sum_i b_i q_i - hj q_j) * inv_nu
+struct DcgsCoef {
+  double inv_r, hj, inv_nu, pad;
+  double a[kMaxCols + 1];
+  double b[kMaxCols + 1];
 };
 
 }  // namespace mdp

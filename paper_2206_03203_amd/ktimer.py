@@ -1,0 +1,31 @@
+"""Kernel-class timers of the library (mdp_ktimer_begin / mdp_ktimer_end):
+HIP events around every launch of a class on its launch stream, with the
+algorithmic bytes of each launch."""
+
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib as L
+
+CLASSES = {0: "outer_spmv", 1: "fine_smooth", 2: "vcycle_other", 3: "arnoldi_dot",
+           4: "arnoldi_axpy", 5: "other"}
+
+
+def mdp_ktimer_begin(kind: int) -> None:
+    L._check(L.lib.mdp_ktimer_begin(kind), "mdp_ktimer_begin")
+
+
+def mdp_ktimer_end(kind: int) -> dict:
+    ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+    L._check(L.lib.mdp_ktimer_end(kind, C.byref(ms), C.byref(n), C.byref(b)), "mdp_ktimer_end")
+    return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
+
+def begin_all() -> None:
+    for k in CLASSES:
+        mdp_ktimer_begin(k)
+
+
+def end_all() -> dict:
+    return {name: mdp_ktimer_end(k) for k, name in CLASSES.items()}
