@@ -43,8 +43,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--n", type=int, default=100, help="host cells per side")
     p.add_argument("--seeds", type=int, default=1, help="log-normal seeds per (K_par, kappa) pair")
+    p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-iters", type=int, default=10, help="oracle FGMRES iterations in the CPU sample")
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="only run a device-to-device copy of this many MiB (5 times) and exit; used to "
+                        "calibrate hardware traffic counters against a copy of known size")
     p.add_argument("--kernel-class", default="auto",
                    help="kernel class for the roofline object (auto = largest total time)")
     return p.parse_args()
@@ -58,6 +62,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+        return
 
     import synth
     from paper_2206_03203_amd import _lib as L
@@ -74,8 +89,10 @@ def main():
             t0 = time.perf_counter()
             A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
-            hs = {"fp64": L.mdp_setup(A, part, L.mdp_options_default(precision=L.MDP_FP64), stream)}
-            hs["mixed"] = L.mdp_setup_like(hs["fp64"], L.mdp_options_default(precision=L.MDP_MIXED), stream)
+            o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles)
+            o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles)
+            hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
+            hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
             t_asm += t1 - t0
             t_setup += t2 - t1
@@ -161,7 +178,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
-                   "fracture_perm_pairs": PAIRS, "rtol": 1e-8},
+                   "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles},
         "p50_ms": pct(fp["lat"], 50),
         "p99_ms": pct(fp["lat"], 99),
         "iters": sorted(set(fp["iters"])),

@@ -53,6 +53,37 @@ enum SpmvMode : int {
   kAccum = 4,   // y += A x                            (prolongation + correction)
 };
 
+// Per-row epilogue shared by the sparse kernels.
+template <int MODE, typename Acc, typename TX, typename TY>
+__device__ __forceinline__ void spmv_store(int row, Acc sum, const TX *__restrict__ x, const TY *__restrict__ b,
+                                           const TY *__restrict__ dinv, TY *__restrict__ y, TY *__restrict__ y2) {
+  if constexpr (MODE == kPlain) {
+    y[row] = static_cast<TY>(sum);
+  } else if constexpr (MODE == kResid) {
+    y[row] = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
+  } else if constexpr (MODE == kSmooth) {
+    y[row] = static_cast<TY>(static_cast<Acc>(x[row]) + static_cast<Acc>(dinv[row]) * (static_cast<Acc>(b[row]) - sum));
+  } else if constexpr (MODE == kPre0) {
+    y2[row] = b[row] * dinv[row];
+    y[row] = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
+  } else {
+    y[row] = static_cast<TY>(static_cast<Acc>(y[row]) + sum);
+  }
+}
+
+template <int MODE, typename Acc, typename TX, typename TY>
+__device__ __forceinline__ Acc spmv_gather(int c, const TX *__restrict__ x, const TY *__restrict__ b,
+                                           const TY *__restrict__ dinv) {
+  if constexpr (MODE == kPre0)
+    return static_cast<Acc>(b[c] * dinv[c]);
+  else
+    return static_cast<Acc>(x[c]);
+}
+
+// CSR-vector kernel for long rows: LPR lanes per row, each lane keeps
+// kCsrBatch entries in flight (indices and values loaded before the gathers).
+constexpr int kCsrBatch = 4;
+
 template <int LPR, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void spmv_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
@@ -66,31 +97,58 @@ __global__ __launch_bounds__(kThreads) void spmv_kernel(
   if (row >= nr) return;  // whole LPR groups leave together
   const int s = ptr[row], e = ptr[row + 1];
   Acc sum = 0;
-  for (int p = s + lane; p < e; p += LPR) {
-    const int c = col[p];
-    Acc xv;
-    if constexpr (MODE == kPre0)
-      xv = static_cast<Acc>(b[c] * dinv[c]);
-    else
-      xv = static_cast<Acc>(x[c]);
-    sum += static_cast<Acc>(val[p]) * xv;
+  for (int p0 = s + lane; p0 < e; p0 += kCsrBatch * LPR) {
+    int c[kCsrBatch];
+    Acc v[kCsrBatch];
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k) {
+      const int p = p0 + k * LPR;
+      // past the row end: value 0 and a column of this row (always in range)
+      c[k] = p < e ? col[p] : col[s];
+      v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
   }
   sum = group_sum<LPR>(sum);
-  if (lane == 0) {
-    if constexpr (MODE == kPlain) {
-      y[row] = static_cast<TY>(sum);
-    } else if constexpr (MODE == kResid) {
-      y[row] = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
-    } else if constexpr (MODE == kSmooth) {
-      y[row] = static_cast<TY>(static_cast<Acc>(x[row]) +
-                               static_cast<Acc>(dinv[row]) * (static_cast<Acc>(b[row]) - sum));
-    } else if constexpr (MODE == kPre0) {
-      y2[row] = b[row] * dinv[row];
-      y[row] = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
-    } else {
-      y[row] = static_cast<TY>(static_cast<Acc>(y[row]) + sum);
+  if (lane == 0) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+}
+
+// Sliced ELL (slices of 64 rows = one wavefront, one thread per row): entry k
+// of the row at lane L of slice s is stored at soff[s] + 64 k + L, so every
+// load of indices and values is one contiguous 64-wide access.  Padding
+// entries carry value 0 and a valid column.  The row loop is unrolled by
+// kSellBatch so that many gathers are in flight per thread.
+constexpr int kSellBatch = 8;
+
+template <int MODE, typename TA, typename TX, typename TY>
+__global__ __launch_bounds__(kThreads) void sell_kernel(
+    int nr, int nslices, const int *__restrict__ soff, const int *__restrict__ col, const TA *__restrict__ val,
+    const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TX>::type;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int slice = blk * (kThreads / 64) + static_cast<int>(threadIdx.x) / 64;
+  const int lane = threadIdx.x % 64;
+  if (slice >= nslices) return;
+  const int o0 = soff[slice], o1 = soff[slice + 1];
+  const int row = slice * 64 + lane;
+  Acc sum = 0;
+  int o = o0 + lane;
+  for (; o + (kSellBatch - 1) * 64 < o1; o += kSellBatch * 64) {
+    int c[kSellBatch];
+    Acc v[kSellBatch];
+#pragma unroll
+    for (int k = 0; k < kSellBatch; ++k) {
+      c[k] = col[o + k * 64];
+      v[k] = static_cast<Acc>(val[o + k * 64]);
     }
+#pragma unroll
+    for (int k = 0; k < kSellBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
   }
+  for (; o < o1; o += 64) sum += static_cast<Acc>(val[o]) * spmv_gather<MODE, Acc>(col[o], x, b, dinv);
+  if (row < nr) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
 }
 
 // Coarsest level: x = Ainv b with a dense FP64 inverse (row-major n x n); one

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -26,10 +27,12 @@ namespace mdp {
 
 namespace {
 
+// Lanes per row for the CSR-vector kernel: enough that one batch of
+// kCsrBatch entries per lane covers an average row.
 int choose_lpr(int64_t nnz, int32_t nr) {
   const double avg = nr > 0 ? static_cast<double>(nnz) / nr : 0.0;
-  int l = 2;
-  while (l < avg && l < 64) l *= 2;
+  int l = 4;
+  while (l * kCsrBatch < avg && l < 64) l *= 2;
   return l;
 }
 
@@ -39,15 +42,61 @@ void upload_vec(DevMem &d, const std::vector<T> &h, hipStream_t s) {
   if (!h.empty()) MDP_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Sliced ELL pays off when rows are short and similar within 64-row slices.
 template <typename T>
 void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vector<T>> &keep) {
   d.nr = h.nr;
   d.nc = h.nc;
   d.nnz = h.nnz();
   d.lpr = choose_lpr(d.nnz, d.nr);
-  upload_vec(d.ptr, h.ptr, s);
-  upload_vec(d.col, h.col, s);
-  keep.emplace_back(h.val.begin(), h.val.end());
+  const int32_t ns = (h.nr + 63) / 64;
+  int64_t padded = 0;
+  int32_t maxlen = 0;
+  for (int32_t sl = 0; sl < ns; ++sl) {
+    int32_t w = 0;
+    for (int32_t r = sl * 64; r < std::min(h.nr, sl * 64 + 64); ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+    padded += 64 * static_cast<int64_t>(w);
+    maxlen = std::max(maxlen, w);
+  }
+  d.sell = h.nr > 0 && maxlen <= 64 && padded <= 13 * std::max<int64_t>(d.nnz, 1) / 10 &&
+           padded < std::numeric_limits<int32_t>::max();
+  if (!d.sell) {
+    upload_vec(d.ptr, h.ptr, s);
+    upload_vec(d.col, h.col, s);
+    keep.emplace_back(h.val.begin(), h.val.end());
+    upload_vec(d.val, keep.back(), s);
+    return;
+  }
+  d.nslices = ns;
+  std::vector<int32_t> soff(static_cast<size_t>(ns) + 1, 0), col(static_cast<size_t>(padded));
+  std::vector<T> val(static_cast<size_t>(padded), T(0));
+  int64_t o = 0;
+  for (int32_t sl = 0; sl < ns; ++sl) {
+    const int32_t r0 = sl * 64, r1 = std::min(h.nr, r0 + 64);
+    int32_t w = 0;
+    for (int32_t r = r0; r < r1; ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+    soff[sl] = static_cast<int32_t>(o);
+    for (int32_t lane = 0; lane < 64; ++lane) {
+      const int32_t r = r0 + lane;
+      const int32_t len = r < r1 ? h.ptr[r + 1] - h.ptr[r] : 0;
+      int32_t lastc = 0;
+      for (int32_t k = 0; k < w; ++k) {
+        const int64_t dst = o + static_cast<int64_t>(k) * 64 + lane;
+        if (k < len) {
+          lastc = h.col[h.ptr[r] + k];
+          col[dst] = lastc;
+          val[dst] = static_cast<T>(h.val[h.ptr[r] + k]);
+        } else {
+          col[dst] = lastc;  // padding: a valid, nearby column with value 0
+        }
+      }
+    }
+    o += static_cast<int64_t>(w) * 64;
+  }
+  soff[ns] = static_cast<int32_t>(o);
+  upload_vec(d.ptr, soff, s);
+  upload_vec(d.col, col, s);
+  keep.push_back(std::move(val));
   upload_vec(d.val, keep.back(), s);
 }
 
@@ -117,8 +166,15 @@ template <int MODE, typename TA, typename TX, typename TY>
 void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, const int *gate,
           hipStream_t s, int kind = kKcOther) {
   if (A.nr == 0) return;
+  if (A.sell) {
+    const int blocks = (A.nslices + (kThreads / 64) - 1) / (kThreads / 64);
+    timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+      hipLaunchKernelGGL((sell_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nslices,
+                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+    });
+    return;
+  }
   switch (A.lpr) {
-    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;

@@ -13,11 +13,16 @@
 
 namespace mdp {
 
+// A device sparse matrix, stored either as CSR (long rows; `lpr` lanes per
+// row) or as sliced ELL with 64-row slices (`sell`; `ptr` then holds the
+// slice offsets).
 template <typename T>
 struct DCsr {
   int32_t nr = 0, nc = 0;
   int64_t nnz = 0;
   int lpr = 8;
+  bool sell = false;
+  int32_t nslices = 0;
   DevMem ptr, col, val;
   const int *p() const { return dptr<const int>(ptr); }
   const int *c() const { return dptr<const int>(col); }
