@@ -208,12 +208,13 @@ int mdp_server_destroy(mdp_server *srv);
 
 /* Kernel classes for mdp_ktimer_*. */
 #define MDP_KC_OUTER_SPMV 0    /* w = A z_j with the FP64 system matrix                  */
-#define MDP_KC_FINE_SMOOTH 1   /* finest S~ level: fused pre-smoothing + residual, and
-                                  post-smoothing (the l1-Jacobi sweeps of Section 3.3)   */
+#define MDP_KC_FINE_SMOOTH 1   /* finest S~ level: the post-smoothing l1-Jacobi sweep     */
 #define MDP_KC_VCYCLE_OTHER 2  /* the rest of both V-cycles and the A_GO update          */
-#define MDP_KC_ARNOLDI_DOT 3   /* multi-dot passes of the Arnoldi orthogonalisation      */
-#define MDP_KC_ARNOLDI_AXPY 4  /* multi-axpy passes of the Arnoldi orthogonalisation     */
+#define MDP_KC_ARNOLDI_DOT 3   /* fused reduction pass of each Arnoldi step              */
+#define MDP_KC_ARNOLDI_AXPY 4  /* update pass of each Arnoldi step                       */
 #define MDP_KC_OTHER 5         /* casts, reductions, Givens, update of x, residual       */
+#define MDP_KC_FINE_RESID 6    /* finest S~ level: residual after the first sweep, whose
+                                  iterate D^-1 b the producer of b has written already   */
 
 /* Start timing every launch of one kernel class (process-wide): HIP events
  * are recorded around each launch on the stream it is launched on, and the

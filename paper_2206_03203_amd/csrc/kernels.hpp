@@ -51,6 +51,8 @@ enum SpmvMode : int {
   kSmooth = 2,  // y = x + dinv .* (b - A x)          (one l1-Jacobi sweep, out of place)
   kPre0 = 3,    // y2 = dinv .* b ; y = b - A y2       (first sweep from zero, fused residual)
   kAccum = 4,   // y += A x                            (prolongation + correction)
+  kPlainScale = 5,  // y = A x ; y2 = dinv .* y         (restriction that also starts the coarse smoother)
+  kResidScale = 6,  // y = b - A x ; y2 = dinv .* y     (residual that also starts the next smoother)
 };
 
 // Per-row epilogue shared by the sparse kernels.
@@ -66,6 +68,14 @@ __device__ __forceinline__ void spmv_store(int row, Acc sum, const TX *__restric
   } else if constexpr (MODE == kPre0) {
     y2[row] = b[row] * dinv[row];
     y[row] = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
+  } else if constexpr (MODE == kPlainScale) {
+    const TY v = static_cast<TY>(sum);
+    y[row] = v;
+    y2[row] = v * dinv[row];
+  } else if constexpr (MODE == kResidScale) {
+    const TY v = static_cast<TY>(static_cast<Acc>(b[row]) - sum);
+    y[row] = v;
+    y2[row] = v * dinv[row];
   } else {
     y[row] = static_cast<TY>(static_cast<Acc>(y[row]) + sum);
   }
@@ -151,6 +161,38 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
   if (row < nr) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
 }
 
+// CSR with one thread per row, for short rows of uneven length (where slices
+// would carry much padding): entries are loaded kScalarBatch at a time,
+// predicated on the row length.
+constexpr int kScalarBatch = 4;
+
+template <int MODE, typename TA, typename TX, typename TY>
+__global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
+    int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
+    const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TX>::type;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * kThreads + static_cast<int>(threadIdx.x);
+  if (row >= nr) return;
+  const int s = ptr[row], e = ptr[row + 1];
+  Acc sum = 0;
+  for (int p0 = s; p0 < e; p0 += kScalarBatch) {
+    int c[kScalarBatch];
+    Acc v[kScalarBatch];
+#pragma unroll
+    for (int k = 0; k < kScalarBatch; ++k) {
+      const int p = p0 + k;
+      c[k] = p < e ? col[p] : col[s];
+      v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kScalarBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
+  }
+  spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+}
+
 // Coarsest level: x = Ainv b with a dense FP64 inverse (row-major n x n); one
 // wavefront per row, FP64 accumulation whatever the vector type.
 template <typename T>
@@ -180,6 +222,22 @@ __global__ __launch_bounds__(kThreads) void scale_copy_kernel(int64_t n, const T
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     out[i] = static_cast<TO>(static_cast<double>(in[i]) * s);
+}
+
+// rin = (float) u for all n entries; t[i] = rin[i] * dinv[i] for the first no
+// (the host block's first smoother iterate), when t is given.
+__global__ __launch_bounds__(kThreads) void cast_start_kernel(int64_t n, int no, const double *__restrict__ u,
+                                                              float *__restrict__ rin,
+                                                              const float *__restrict__ dinv,
+                                                              float *__restrict__ t,
+                                                              const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const float v = static_cast<float>(u[i]);
+    rin[i] = v;
+    if (t && i < no) t[i] = v * dinv[i];
+  }
 }
 
 // x = b .* dinv

@@ -10,13 +10,14 @@
 namespace mdp {
 
 enum KClass : int {
-  kKcOuterSpmv = 0,   // w = A z_j, FP64 system matrix
-  kKcFineSmooth = 1,  // finest level of the S~ hierarchy: fused pre-smoothing+residual, post-smoothing
-  kKcVcycleOther = 2, // other V-cycle kernels (restriction, prolongation, coarser levels, A_GG, A_GO)
-  kKcArnoldiDot = 3,  // multi-dot passes of CGS2
-  kKcArnoldiAxpy = 4, // multi-axpy passes of CGS2
-  kKcOther = 5,       // casts, reductions, Givens, solution update, residual
-  kKcCount = 6
+  kKcOuterSpmv = 0,    // w = A z_j, FP64 system matrix
+  kKcFineSmooth = 1,   // finest S~ level: post-smoothing sweep
+  kKcVcycleOther = 2,  // other V-cycle kernels (restriction, prolongation, coarser levels, A_GG, A_GO)
+  kKcArnoldiDot = 3,   // fused reduction pass of the Arnoldi step
+  kKcArnoldiAxpy = 4,  // update pass of the Arnoldi step
+  kKcOther = 5,        // casts, small reductions, Givens, solution update, residual
+  kKcFineResid = 6,    // finest S~ level: residual after the first sweep
+  kKcCount = 7
 };
 
 bool ktimer_on(int kind);

@@ -58,8 +58,12 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vecto
     padded += 64 * static_cast<int64_t>(w);
     maxlen = std::max(maxlen, w);
   }
-  d.sell = h.nr > 0 && maxlen <= 64 && padded <= 13 * std::max<int64_t>(d.nnz, 1) / 10 &&
+  // sliced ELL when slices carry little padding; one thread per row for other
+  // short rows; LPR lanes per row otherwise
+  const double avg = h.nr > 0 ? static_cast<double>(d.nnz) / h.nr : 0.0;
+  d.sell = h.nr > 0 && maxlen <= 64 && padded <= 23 * std::max<int64_t>(d.nnz, 1) / 20 &&
            padded < std::numeric_limits<int32_t>::max();
+  d.scalar = !d.sell && avg <= 12.0;
   if (!d.sell) {
     upload_vec(d.ptr, h.ptr, s);
     upload_vec(d.col, h.col, s);
@@ -148,6 +152,9 @@ double spmv_bytes(const DCsr<TA> &A) {
   if (MODE == kSmooth) b += sx * A.nc + 3 * sy * A.nr;  // x, b, dinv, y
   if (MODE == kPre0) b += 2 * sy * A.nc + 2 * sy * A.nr;  // b, dinv; y2, y
   if (MODE == kAccum) b += sx * A.nc + 2 * sy * A.nr;
+  if (MODE == kPlainScale) b += sx * A.nc + 2 * sy * A.nr;   // x; dinv, y (+ y2)
+  if (MODE == kResidScale) b += sx * A.nc + 4 * sy * A.nr;   // x; b, dinv, y, y2
+  if (MODE == kPlainScale) b += sy * A.nr;
   return b;
 }
 
@@ -174,6 +181,14 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     });
     return;
   }
+  if (A.scalar) {
+    const int blocks = (A.nr + kThreads - 1) / kThreads;
+    timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+      hipLaunchKernelGGL((csr_scalar_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.p(),
+                         A.c(), A.v(), x, b, dinv, y, y2, gate);
+    });
+    return;
+  }
   switch (A.lpr) {
     case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
@@ -181,6 +196,20 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     case 32: spmv_launch<32, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     default: spmv_launch<64, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
   }
+}
+
+// The V-cycle below expects the finest level's scratch `t` to hold the first
+// l1-Jacobi iterate from zero, x0 = D^-1 b; the kernels that produce b also
+// write x0 (restriction, the fracture-residual update, the input cast), so the
+// smoother's residual needs one gather per nonzero.
+template <typename T>
+void start_smoother(DHier<T> &H, const T *b, const int *gate, hipStream_t s) {
+  const int n = H.n();
+  if (n == 0 || (H.lv.size() == 1 && H.dense)) return;
+  timed_launch(kKcVcycleOther, s, 3.0 * sizeof(T) * n, [&] {
+    hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
+                       dptr<const T>(H.lv[0].dinv), dptr<T>(H.lv[0].t), gate);
+  });
 }
 
 template <typename T>
@@ -196,17 +225,17 @@ void coarse_solve(DHier<T> &H, const T *b, T *x, const int *gate, hipStream_t s)
     });
     return;
   }
-  // four l1-Jacobi sweeps from zero, ping-pong ending in x
+  // four l1-Jacobi sweeps from zero: the first is x0 = D^-1 b, already in t
   T *pa = dptr<T>(H.tmp_pp), *pb = pa + n;
-  hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
-                     dptr<const T>(L.dinv), pa, gate);
+  const T *t = dptr<const T>(L.t);
+  const T *dinv = dptr<const T>(L.dinv);
   const int kc = kKcVcycleOther;
-  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), pb, static_cast<T *>(nullptr), gate, s, kc);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dptr<const T>(L.dinv), pa, static_cast<T *>(nullptr), gate, s, kc);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dptr<const T>(L.dinv), x, static_cast<T *>(nullptr), gate, s, kc);
+  spmv<kSmooth>(L.A, t, b, dinv, pa, static_cast<T *>(nullptr), gate, s, kc);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dinv, pb, static_cast<T *>(nullptr), gate, s, kc);
+  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dinv, x, static_cast<T *>(nullptr), gate, s, kc);
 }
 
-// One V-cycle from a zero initial guess: x = V(b).
+// One V-cycle from a zero initial guess: x = V(b), with lv[l].t = D^-1 b on entry.
 template <typename T>
 void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_t s) {
   if (l + 1 == H.lv.size()) {
@@ -217,39 +246,43 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_
   DLevel<T> &C = H.lv[l + 1];
   T *t = dptr<T>(L.t);
   const T *dinv = dptr<const T>(L.dinv);
-  const int ks = (H.is_omega && l == 0) ? kKcFineSmooth : kKcVcycleOther;
+  const bool fine = H.is_omega && l == 0;
+  const int ks = fine ? kKcFineSmooth : kKcVcycleOther;
+  const int kr = fine ? kKcFineResid : kKcVcycleOther;
   const int ko = kKcVcycleOther;
-  spmv<kPre0>(L.A, static_cast<const T *>(nullptr), b, dinv, dptr<T>(L.r), t, gate, s, ks);  // t = D^-1 b, r = b - A t
-  spmv<kPlain>(L.R, dptr<const T>(L.r), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr),
-               dptr<T>(C.b), static_cast<T *>(nullptr), gate, s, ko);  // b_c = R r
+  spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), static_cast<T *>(nullptr), gate, s,
+               kr);  // pre-smoothing x = t = D^-1 b done; r = b - A t
+  spmv<kPlainScale>(L.R, dptr<const T>(L.r), static_cast<const T *>(nullptr), dptr<const T>(C.dinv), dptr<T>(C.b),
+                    dptr<T>(C.t), gate, s, ko);  // b_c = R r, t_c = D_c^-1 b_c
   vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
   spmv<kAccum>(L.P, dptr<const T>(C.x), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr), t,
                static_cast<T *>(nullptr), gate, s, ko);  // t += P x_c
   spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, static_cast<T *>(nullptr), gate, s, ks);  // post-smooth
 }
 
-// Q = `cycles` V-cycles as a stationary iteration from zero.
+// Q = `cycles` V-cycles as a stationary iteration from zero (lv[0].t = D^-1 r on entry).
 template <typename T>
 void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStream_t s) {
   vcycle(H, 0, r, z, gate, s);
   const int n = H.n();
   for (int c = 1; c < cycles; ++c) {
-    spmv<kResid>(H.lv[0].A, static_cast<const T *>(z), r, static_cast<const T *>(nullptr), dptr<T>(H.tmp_res),
-                 static_cast<T *>(nullptr), gate, s, kKcVcycleOther);
+    spmv<kResidScale>(H.lv[0].A, static_cast<const T *>(z), r, dptr<const T>(H.lv[0].dinv), dptr<T>(H.tmp_res),
+                      dptr<T>(H.lv[0].t), gate, s, kKcVcycleOther);
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
                        gate);
   }
 }
 
-// Algorithm 1: z = M_L r, with r and z laid out as [Omega; Gamma].
+// Algorithm 1: z = M_L r, with r and z laid out as [Omega; Gamma].  On entry
+// Ho.lv[0].t = D^-1 r_O (see start_smoother).
 template <typename T>
 void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
   apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
   if (P.n_g == 0) return;
   T *rg = dptr<T>(P.rg);
-  spmv<kResid>(P.Ago, static_cast<const T *>(z), r + P.n_o, static_cast<const T *>(nullptr), rg,
-               static_cast<T *>(nullptr), gate, s, kKcVcycleOther);  // r_G - A_GO z_O
+  spmv<kResidScale>(P.Ago, static_cast<const T *>(z), r + P.n_o, dptr<const T>(P.Hg.lv[0].dinv), rg,
+                    dptr<T>(P.Hg.lv[0].t), gate, s, kKcVcycleOther);  // r_G - A_GO z_O (and D^-1 of it)
   apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
 }
 
@@ -367,11 +400,15 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
       const T *pin;
       if constexpr (std::is_same<T, double>::value) {
         pin = uj;
+        start_smoother(P.Ho, pin, gate_apply, s);
       } else {
         T *rin = dptr<T>(ws.rin);
-        timed_launch(kKcOther, s, 12.0 * n, [&] {
-          hipLaunchKernelGGL((scale_copy_kernel<double, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, uj,
-                             static_cast<const double *>(nullptr), rin, gate_apply);
+        const int no = P.n_o;
+        const bool need_t = !(P.Ho.lv.size() == 1 && P.Ho.dense);
+        timed_launch(kKcOther, s, 12.0 * n + 8.0 * no, [&] {
+          hipLaunchKernelGGL(cast_start_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, no, uj, rin,
+                             dptr<const float>(P.Ho.lv[0].dinv), need_t ? dptr<float>(P.Ho.lv[0].t) : nullptr,
+                             gate_apply);
         });
         pin = rin;
       }
@@ -521,16 +558,18 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
         float *out = dptr<float>(ws.Z);
         hipLaunchKernelGGL((scale_copy_kernel<double, float>), dim3(grid_for(len)), dim3(kThreads), 0, s, len, x,
                            static_cast<const double *>(nullptr), in, static_cast<const int *>(nullptr));
+        auto &H = op == MDP_OP_QGG ? pc32->Hg : pc32->Ho;
+        start_smoother(H, static_cast<const float *>(in), nullptr, s);
         if (op == MDP_OP_ML) apply_ml(*pc32, static_cast<const float *>(in), out, nullptr, s);
-        else if (op == MDP_OP_QOO) apply_q(pc32->Ho, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
-        else apply_q(pc32->Hg, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
+        else apply_q(H, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
         hipLaunchKernelGGL((scale_copy_kernel<float, double>), dim3(grid_for(len)), dim3(kThreads), 0, s, len,
                            static_cast<const float *>(out), static_cast<const double *>(nullptr), y,
                            static_cast<const int *>(nullptr));
       } else {
+        auto &H = op == MDP_OP_QGG ? pc64->Hg : pc64->Ho;
+        start_smoother(H, x, nullptr, s);
         if (op == MDP_OP_ML) apply_ml(*pc64, x, y, nullptr, s);
-        else if (op == MDP_OP_QOO) apply_q(pc64->Ho, pc64->vcycles, x, y, nullptr, s);
-        else apply_q(pc64->Hg, pc64->vcycles, x, y, nullptr, s);
+        else apply_q(H, pc64->vcycles, x, y, nullptr, s);
       }
       break;
     }

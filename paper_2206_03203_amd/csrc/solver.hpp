@@ -22,6 +22,7 @@ struct DCsr {
   int64_t nnz = 0;
   int lpr = 8;
   bool sell = false;
+  bool scalar = false;  // CSR, one thread per row
   int32_t nslices = 0;
   DevMem ptr, col, val;
   const int *p() const { return dptr<const int>(ptr); }

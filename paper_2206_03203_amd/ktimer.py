@@ -9,7 +9,12 @@ import ctypes as C
 from . import _lib as L
 
 CLASSES = {0: "outer_spmv", 1: "fine_smooth", 2: "vcycle_other", 3: "arnoldi_dot",
-           4: "arnoldi_axpy", 5: "other"}
+           4: "arnoldi_axpy", 5: "other", 6: "fine_resid"}
+# classes whose launches are all of one kernel symbol (per precision)
+SINGLE_KERNEL = {"outer_spmv": "sell_kernel<0, double, T, double>",
+                 "fine_smooth": "post-smoothing sweep on the finest S~ level",
+                 "fine_resid": "residual after the first sweep on the finest S~ level",
+                 "arnoldi_dot": "dcgs_reduce_kernel", "arnoldi_axpy": "dcgs_update_kernel"}
 
 
 def mdp_ktimer_begin(kind: int) -> None:
@@ -22,10 +27,11 @@ def mdp_ktimer_end(kind: int) -> dict:
     return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
 
-def begin_all() -> None:
-    for k in CLASSES:
-        mdp_ktimer_begin(k)
+def begin_all(names=None) -> None:
+    for k, name in CLASSES.items():
+        if names is None or name in names:
+            mdp_ktimer_begin(k)
 
 
-def end_all() -> dict:
-    return {name: mdp_ktimer_end(k) for k, name in CLASSES.items()}
+def end_all(names=None) -> dict:
+    return {name: mdp_ktimer_end(k) for k, name in CLASSES.items() if names is None or name in names}
