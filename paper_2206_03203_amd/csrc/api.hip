@@ -1,6 +1,8 @@
 // C ABI entry points (include/mdp.h): argument checking, error translation
 // and handle lifecycle around the host setup and the device solver.
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -16,6 +18,24 @@ namespace {
 thread_local std::string g_last_error;
 std::mutex g_hook_mu;
 AllocHook g_hook;
+
+// The most recent batch plan: block-diagonal concatenations of the pairs of
+// the last mdp_solve_batch call, split into chunks of bounded size.  Reused
+// while the same handles and right-hand-side counts come back.
+struct BatchCache {
+  std::vector<const mdp_handle *> handles;
+  std::vector<int32_t> nrhs;
+  std::vector<std::unique_ptr<Batch>> chunks;
+  std::vector<int> first_pair;  // per chunk
+};
+std::mutex g_batch_mu;
+std::unique_ptr<BatchCache> g_batch;
+
+int64_t batch_max_unknowns() {
+  const char *e = std::getenv("MDP_BATCH_MAX_UNKNOWNS");
+  const long long v = e ? std::atoll(e) : 0;
+  return v > 0 ? v : (int64_t{24} << 20);
+}
 }  // namespace
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
@@ -169,6 +189,11 @@ int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stre
 
 int mdp_destroy(mdp_handle *h) {
   API_BEGIN
+  if (h) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (g_batch && std::find(g_batch->handles.begin(), g_batch->handles.end(), h) != g_batch->handles.end())
+      g_batch.reset();
+  }
   delete h;
   return MDP_OK;
   API_END
@@ -204,14 +229,64 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     set_last_error("bad batch arguments");
     return MDP_EINVAL;
   }
-  int worst = MDP_OK;
-  int64_t slot = 0;
+  std::vector<const Solver *> pairs;
+  std::vector<PairIO> io;
   for (int32_t i = 0; i < nsys; ++i) {
-    const int rc = mdp_solve(hs[i], b[i], x[i], nrhs[i], hs[i] ? hs[i]->s.n : 0, hip_stream,
-                             stats ? stats + slot : nullptr);
-    slot += nrhs[i];
-    if (rc < 0) return rc;
-    if (rc > worst) worst = rc;
+    if (!hs[i] || !b[i] || !x[i] || nrhs[i] < 0) {
+      set_last_error("bad batch entry " + std::to_string(i));
+      return MDP_EINVAL;
+    }
+    const Solver &s0 = hs[0]->s, &si = hs[i]->s;
+    if (!si.on_device) {
+      set_last_error("handle " + std::to_string(i) + " was set up host-only");
+      return MDP_EINVAL;
+    }
+    if (si.opt.precision != s0.opt.precision || si.opt.vcycles != s0.opt.vcycles ||
+        si.opt.restart != s0.opt.restart || si.opt.max_iter != s0.opt.max_iter || si.opt.rtol != s0.opt.rtol ||
+        si.opt.flags != s0.opt.flags) {
+      set_last_error("all handles of a batch need the same solve options");
+      return MDP_EINVAL;
+    }
+    for (int32_t k = 0; k < nrhs[i]; ++k) {
+      pairs.push_back(&si);
+      io.push_back(PairIO{b[i] + static_cast<int64_t>(k) * si.n, x[i] + static_cast<int64_t>(k) * si.n});
+    }
+  }
+  if (pairs.empty()) return MDP_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  const std::vector<const mdp_handle *> key_h(hs, hs + nsys);
+  const std::vector<int32_t> key_r(nrhs, nrhs + nsys);
+  if (!g_batch || g_batch->handles != key_h || g_batch->nrhs != key_r) {
+    g_batch.reset();
+    auto bc = std::make_unique<BatchCache>();
+    bc->handles = key_h;
+    bc->nrhs = key_r;
+    const int64_t cap = batch_max_unknowns();
+    size_t p0 = 0;
+    while (p0 < pairs.size()) {
+      size_t p1 = p0;
+      int64_t tot = 0;
+      while (p1 < pairs.size() && (p1 == p0 || tot + pairs[p1]->n <= cap)) tot += pairs[p1++]->n;
+      auto bt = std::make_unique<Batch>();
+      bt->build(std::vector<const Solver *>(pairs.begin() + p0, pairs.begin() + p1), s);
+      bc->first_pair.push_back(static_cast<int>(p0));
+      bc->chunks.push_back(std::move(bt));
+      p0 = p1;
+    }
+    g_batch = std::move(bc);
+  }
+  int worst = MDP_OK;
+  for (size_t c = 0; c < g_batch->chunks.size(); ++c) {
+    Batch &bt = *g_batch->chunks[c];
+    const int p0 = g_batch->first_pair[c];
+    const std::vector<PairIO> sub(io.begin() + p0, io.begin() + p0 + bt.npairs);
+    const int rc = bt.solve(sub, s, stats ? stats + p0 : nullptr);
+    if (rc < 0) {
+      if (worst >= 0 || rc < worst) worst = rc;
+    } else if (worst >= 0 && rc > worst) {
+      worst = rc;
+    }
   }
   return worst;
   API_END

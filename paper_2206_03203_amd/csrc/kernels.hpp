@@ -211,6 +211,48 @@ __global__ __launch_bounds__(kThreads) void dense_gemv_kernel(int n, const doubl
   if (lane == 0) x[row] = static_cast<T>(s);
 }
 
+// Coarsest levels of several systems at once: x = Ainv_d b on each
+// descriptor's rows; grid (ceil(max n / 4), ndesc), one wavefront per row.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void dense_gemv_batched_kernel(const DenseDesc *__restrict__ desc,
+                                                                      const double *__restrict__ ainv,
+                                                                      const T *__restrict__ b, T *__restrict__ x,
+                                                                      const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  const DenseDesc d = desc[blockIdx.y];
+  const int row = blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= d.n) return;
+  const double *a = ainv + d.inv_off + static_cast<int64_t>(row) * d.n;
+  const T *bb = b + d.row;
+  double s = 0.0;
+  for (int j = lane; j < d.n; j += 64) s += a[j] * static_cast<double>(bb[j]);
+  s = group_sum<64>(s);
+  if (lane == 0) x[d.row + row] = static_cast<T>(s);
+}
+
+// Batched gather / scatter between the callers' vectors (one device pointer
+// per pair, caller order) and the global layout.
+__global__ __launch_bounds__(kThreads) void gather_pairs_kernel(int64_t n, const int *__restrict__ gpair,
+                                                                const int *__restrict__ gidx,
+                                                                const double *const *__restrict__ src,
+                                                                double *__restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    out[i] = src[gpair[i]][gidx[i]];
+}
+__global__ __launch_bounds__(kThreads) void scatter_pairs_kernel(int64_t n, const int *__restrict__ gpair,
+                                                                 const int *__restrict__ gidx,
+                                                                 const double *__restrict__ in,
+                                                                 double *const *__restrict__ dst,
+                                                                 const int *__restrict__ active) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int p = gpair[i];
+    if (!active || active[p]) dst[p][gidx[i]] = in[i];
+  }
+}
+
 // out = in * (*scale) (scale may be null: 1), with a type conversion.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kThreads) void scale_copy_kernel(int64_t n, const TI *__restrict__ in,
@@ -305,13 +347,10 @@ __device__ __forceinline__ void red_range(int64_t n, int blk, int64_t &lo, int64
 // gamma = w.w; a small kernel then finalises column j-1 (u_j re-orthogonalised
 // with a) and forms column j; one update pass writes q_j and u_{j+1}.
 
-constexpr int kDotU = 8;  // elements per thread in the fused reduction / update passes
-
 // Sum 8 values over the 64 lanes of a wavefront by recursive halving: after
-// the call, lane L holds in v[0] the wave total of value index
-// 4*bit5(L) + 2*bit4(L) + bit3(L) summed over the 8 lanes that share bits 5..3
-// (bits 2..0 are then reduced by a butterfly, so every lane of the group holds
-// the total).  10 shuffles instead of 48.
+// the call, every lane holds in v[0] the wave total of value index
+// 4*bit5(L) + 2*bit4(L) + bit3(L) (see wave_reduce8_index).  10 shuffles
+// instead of 48.
 __device__ __forceinline__ void wave_reduce8(double v[8]) {
   const int lane = threadIdx.x % 64;
   {
@@ -347,23 +386,26 @@ __device__ __forceinline__ int wave_reduce8_index(int lane) {
   return ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
 }
 
-// Per-block partial sums, part[v * nblk + blk], of the 2*nq + 3 values
-// [a_0..a_{nq-1}, b_0..b_{nq-1}, alpha, beta, gamma].
-__global__ __launch_bounds__(kThreads) void dcgs_reduce_kernel(int64_t n, int nq, const double *__restrict__ V,
-                                                               int64_t ld, const double *__restrict__ w,
-                                                               double *__restrict__ part, int nblk,
-                                                               const int *__restrict__ gate) {
-  if (*gate) return;
+// Per-tile partial sums, part[v * ntiles + tile], of the 2*nq + 3 values
+// [a_0..a_{nq-1}, b_0..b_{nq-1}, alpha, beta, gamma] of the tile's pair.
+__global__ __launch_bounds__(kThreads) void dcgs_reduce_kernel(const Tile *__restrict__ tiles, int ntiles, int nq,
+                                                               const double *__restrict__ V, int64_t ld,
+                                                               const double *__restrict__ w,
+                                                               double *__restrict__ part,
+                                                               const GmresState *__restrict__ st) {
+  const Tile tl = tiles[blockIdx.x];
+  if (st[tl.pair].done) return;
   __shared__ double lds[kThreads / 64][2 * kMaxCols + 8];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+  const int64_t base = tl.start + threadIdx.x;
+  const int lim = tl.len - static_cast<int>(threadIdx.x);
   const double *u = V + static_cast<int64_t>(nq) * ld;
   double uu[kDotU], ww[kDotU];
 #pragma unroll
   for (int k = 0; k < kDotU; ++k) {
-    const int64_t e = base + k * kThreads;
-    uu[k] = e < n ? u[e] : 0.0;
-    ww[k] = e < n ? w[e] : 0.0;
+    const bool in = k * kThreads < lim;
+    uu[k] = in ? u[base + k * kThreads] : 0.0;
+    ww[k] = in ? w[base + k * kThreads] : 0.0;
   }
   const int slot = wave_reduce8_index(lane);
   for (int c0 = 0; c0 < nq; c0 += 4) {
@@ -376,8 +418,7 @@ __global__ __launch_bounds__(kThreads) void dcgs_reduce_kernel(int64_t n, int nq
         const double *q = V + static_cast<int64_t>(c0 + c) * ld;
 #pragma unroll
         for (int k = 0; k < kDotU; ++k) {
-          const int64_t e = base + k * kThreads;
-          const double qe = e < n ? q[e] : 0.0;
+          const double qe = k * kThreads < lim ? q[base + k * kThreads] : 0.0;
           acc[c] += qe * uu[k];
           acc[4 + c] += qe * ww[k];
         }
@@ -409,22 +450,50 @@ __global__ __launch_bounds__(kThreads) void dcgs_reduce_kernel(int64_t n, int nq
     double s = 0.0;
 #pragma unroll
     for (int wv = 0; wv < kThreads / 64; ++wv) s += lds[wv][v];
-    part[static_cast<int64_t>(v) * nblk + blockIdx.x] = s;
+    part[static_cast<int64_t>(v) * ntiles + blockIdx.x] = s;
   }
 }
 
-// sums[v] = sum_blk part[v * nblk + blk]; one block per value.
-__global__ __launch_bounds__(kThreads) void block_sums_kernel(int nv, const double *__restrict__ part, int nblk,
-                                                              double *__restrict__ sums,
-                                                              const int *__restrict__ gate) {
-  if (*gate) return;
+// sums[p * sstride + v] = sum over the tiles of pair p of part[v * ntiles + t];
+// grid (nv, npairs).
+__global__ __launch_bounds__(kThreads) void pair_sums_kernel(int nv, const double *__restrict__ part, int ntiles,
+                                                             const int *__restrict__ tile_off,
+                                                             double *__restrict__ sums, int sstride,
+                                                             const GmresState *__restrict__ st) {
   __shared__ double lds[kThreads / 64];
-  const int v = blockIdx.x;
-  if (v >= nv) return;
+  const int v = blockIdx.x, p = blockIdx.y;
+  if (v >= nv || st[p].done) return;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kThreads) s += part[static_cast<int64_t>(v) * nblk + k];
+  for (int t = tile_off[p] + threadIdx.x; t < tile_off[p + 1]; t += kThreads) s += part[static_cast<int64_t>(v) * ntiles + t];
   s = block_sum(s, lds);
-  if (threadIdx.x == 0) sums[v] = s;
+  if (threadIdx.x == 0) sums[static_cast<int64_t>(p) * sstride + v] = s;
+}
+
+// part[t] = sum over tile t of v[e]^2, for every tile (no gating).
+__global__ __launch_bounds__(kThreads) void tile_norm2_kernel(const Tile *__restrict__ tiles,
+                                                              const double *__restrict__ v,
+                                                              double *__restrict__ part) {
+  __shared__ double lds[kThreads / 64];
+  const Tile tl = tiles[blockIdx.x];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < tl.len; i += kThreads) {
+    const double x = v[tl.start + i];
+    s += x * x;
+  }
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[p] = sqrt(sum of the pair's tile partials); one block per pair.
+__global__ __launch_bounds__(kThreads) void pair_norm_kernel(const double *__restrict__ part,
+                                                             const int *__restrict__ tile_off,
+                                                             double *__restrict__ out) {
+  __shared__ double lds[kThreads / 64];
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int t = tile_off[p] + threadIdx.x; t < tile_off[p + 1]; t += kThreads) s += part[t];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) out[p] = sqrt(s);
 }
 
 // Givens rotation that zeroes b in (a, b).
@@ -434,23 +503,54 @@ __device__ __forceinline__ void givens(double a, double b, double &c, double &s,
   s = b / r;
 }
 
-// Step j of the cycle (one thread does the O(j) scalar work):
+// Mark pair state `s` as no longer applying the preconditioner / as finished,
+// maintaining the batch-wide counters.
+__device__ __forceinline__ void pair_stop_apply(GmresState *s, BatchCtl *ctl) {
+  if (!s->skip_apply) {
+    s->skip_apply = 1;
+    if (atomicSub(&ctl->napply_left, 1) == 1) ctl->skip_all_apply = 1;
+  }
+}
+__device__ __forceinline__ void pair_finish(GmresState *s, BatchCtl *ctl, int npairs) {
+  pair_stop_apply(s, ctl);
+  s->done = 1;
+  if (atomicAdd(&ctl->ndone, 1) == npairs - 1) ctl->all_done = 1;
+}
+
+// Step j of the cycle for pair blockIdx.x (one thread does the O(j) scalar work):
 //  * j > 0: re-orthogonalise u_j against q_0..q_{j-1} (coefficients a) and
 //    finalise Hessenberg column j-1 = hprev + nu a, with subdiagonal nu r;
 //    apply the stored rotations, form rotation j-1, update g; the estimate
-//    |g_j| is final for basis size j.  Stop if it meets tol_abs or if the
-//    previous step announced that this step only finalises.
+//    |g_j| is final for basis size j.  Stop if it meets the tolerance or if
+//    the previous step announced that this step only finalises.
 //  * form column j from b, beta (its provisional subdiagonal from gamma),
 //    estimate the residual of basis size j+1 with a trial rotation, and
-//    announce the last step when that estimate meets tol_abs, when j+1 ==
-//    kmax, or on (near) breakdown.  Write the update-pass coefficients.
-__global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j, int kmax, double tol_abs,
-                                                           const double *__restrict__ sums,
-                                                           double *__restrict__ hprev, DcgsCoef *cf,
-                                                           double *__restrict__ Hr, int ldh,
-                                                           double *__restrict__ cs, double *__restrict__ sn,
-                                                           double *__restrict__ g, double *__restrict__ hist) {
+//    announce the last step when that estimate meets the tolerance, when
+//    j+1 == kmax, or on (near) breakdown.  Write the update-pass coefficients.
+// Per-pair arrays are laid out with the strides ldh*m (Hr), ldv (vectors of
+// length m+1) and sstride (sums).
+__global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restrict__ st_all, BatchCtl *ctl, int npairs,
+                                                           int j, const int *__restrict__ kmaxp,
+                                                           const double *__restrict__ tolp,
+                                                           const double *__restrict__ sums_all, int sstride,
+                                                           double *__restrict__ hprev_all, DcgsCoef *cf_all,
+                                                           double *__restrict__ Hr_all, int ldh, int m,
+                                                           double *__restrict__ cs_all, double *__restrict__ sn_all,
+                                                           double *__restrict__ g_all, double *__restrict__ hist_all,
+                                                           int ldv) {
+  const int p = blockIdx.x;
+  GmresState *st = st_all + p;
   if (st->done) return;
+  const double *sums = sums_all + static_cast<int64_t>(p) * sstride;
+  double *hprev = hprev_all + static_cast<int64_t>(p) * ldv;
+  double *cs = cs_all + static_cast<int64_t>(p) * ldv;
+  double *sn = sn_all + static_cast<int64_t>(p) * ldv;
+  double *g = g_all + static_cast<int64_t>(p) * ldv;
+  double *hist = hist_all + static_cast<int64_t>(p) * ldv;
+  double *Hr = Hr_all + static_cast<int64_t>(p) * ldh * m;
+  DcgsCoef *cf = cf_all + p;
+  const int kmax = kmaxp[p];
+  const double tol_abs = tolp[p];
   __shared__ double a[kMaxCols + 1], b[kMaxCols + 1], col[kMaxCols + 2], sc[kMaxCols + 1], ss[kMaxCols + 1];
   const int t = threadIdx.x;
   for (int i = t; i < j; i += 64) {
@@ -469,7 +569,7 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j
     saa += a[i] * a[i];
     sab += a[i] * b[i];
   }
-  double r2 = alpha - saa;
+  const double r2 = alpha - saa;
   const double r = sqrt(r2 > 1e-30 * alpha ? r2 : 1e-30 * alpha);
   if (j == 0) {
     g[0] = r;  // the cycle's first vector is the unnormalised residual
@@ -499,8 +599,7 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j
     bad = bad || !isfinite(est);
     if (bad || st->finishing || est <= tol_abs) {
       st->nan = bad;
-      st->done = 1;
-      st->skip_apply = 1;
+      pair_finish(st, ctl, npairs);
       return;
     }
     for (int i = 0; i < j; ++i) sc[i] = cs[i], ss[i] = sn[i];
@@ -516,9 +615,8 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j
   sh += hj * hj;
   const double nu2 = gamma - sh;
   const bool brk = !(nu2 > 1e-24 * gamma);
-  const double nu = sqrt(brk ? 1e-24 * gamma : nu2);
+  const double nu = sqrt(brk ? fmax(1e-24 * gamma, 1e-300) : nu2);
   for (int i = 0; i <= j; ++i) hprev[i] = col[i];
-  // trial rotation for the estimate of basis size j+1
   for (int i = 0; i < j; ++i) {
     const double tt = sc[i] * col[i] + ss[i] * col[i + 1];
     col[i + 1] = -ss[i] * col[i] + sc[i] * col[i + 1];
@@ -538,31 +636,35 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *st, int j
   st->nu = nu;
   st->nan = bad;
   if (bad) {
-    st->done = 1;
-    st->skip_apply = 1;
+    pair_finish(st, ctl, npairs);
     return;
   }
   if (brk || est_next <= tol_abs || j + 1 >= kmax) {
     st->finishing = 1;
-    st->skip_apply = 1;
+    pair_stop_apply(st, ctl);
   }
 }
 
 // q_j = (u_j - sum_i a_i q_i) * inv_r ;  u_{j+1} = (w - sum_i b_i q_i - hj q_j) * inv_nu
-__global__ __launch_bounds__(kThreads) void dcgs_update_kernel(int64_t n, int nq, double *__restrict__ V, int64_t ld,
+// on one tile of one pair.
+__global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__restrict__ tiles, int nq,
+                                                               double *__restrict__ V, int64_t ld,
                                                                const double *__restrict__ w,
-                                                               const DcgsCoef *__restrict__ cf,
-                                                               const int *__restrict__ gate) {
-  if (*gate) return;
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+                                                               const DcgsCoef *__restrict__ cf_all,
+                                                               const GmresState *__restrict__ st) {
+  const Tile tl = tiles[blockIdx.x];
+  if (st[tl.pair].done) return;
+  const DcgsCoef *cf = cf_all + tl.pair;
+  const int64_t base = tl.start + threadIdx.x;
+  const int lim = tl.len - static_cast<int>(threadIdx.x);
   double *u = V + static_cast<int64_t>(nq) * ld;
   double *un = u + ld;
   double uu[kDotU], ww[kDotU];
 #pragma unroll
   for (int k = 0; k < kDotU; ++k) {
-    const int64_t e = base + k * kThreads;
-    uu[k] = e < n ? u[e] : 0.0;
-    ww[k] = e < n ? w[e] : 0.0;
+    const bool in = k * kThreads < lim;
+    uu[k] = in ? u[base + k * kThreads] : 0.0;
+    ww[k] = in ? w[base + k * kThreads] : 0.0;
   }
   int i = 0;
   for (; i + 4 <= nq; i += 4) {
@@ -577,8 +679,7 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(int64_t n, int nq
       const double *q = V + static_cast<int64_t>(i + c) * ld;
 #pragma unroll
       for (int k = 0; k < kDotU; ++k) {
-        const int64_t e = base + k * kThreads;
-        const double qe = e < n ? q[e] : 0.0;
+        const double qe = k * kThreads < lim ? q[base + k * kThreads] : 0.0;
         uu[k] -= ca[c] * qe;
         ww[k] -= cb[c] * qe;
       }
@@ -589,8 +690,7 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(int64_t n, int nq
     const double *q = V + static_cast<int64_t>(i) * ld;
 #pragma unroll
     for (int k = 0; k < kDotU; ++k) {
-      const int64_t e = base + k * kThreads;
-      const double qe = e < n ? q[e] : 0.0;
+      const double qe = k * kThreads < lim ? q[base + k * kThreads] : 0.0;
       uu[k] -= ca * qe;
       ww[k] -= cb * qe;
     }
@@ -598,87 +698,82 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(int64_t n, int nq
   const double inv_r = cf->inv_r, hj = cf->hj, inv_nu = cf->inv_nu;
 #pragma unroll
   for (int k = 0; k < kDotU; ++k) {
-    const int64_t e = base + k * kThreads;
-    if (e < n) {
+    if (k * kThreads < lim) {
       const double qj = uu[k] * inv_r;
-      u[e] = qj;
-      un[e] = (ww[k] - hj * qj) * inv_nu;
+      u[base + k * kThreads] = qj;
+      un[base + k * kThreads] = (ww[k] - hj * qj) * inv_nu;
     }
   }
 }
 
-// x[e] += sum_i y[i] * Z[e + i*ldz]  (Z in the preconditioner precision)
+// x[e] += sum_{i < k} y[i] * Z[e + i*ldz] on one tile, k and y of the tile's pair.
 template <typename TZ>
-__global__ __launch_bounds__(kThreads) void update_x_kernel(int64_t n, int ncols, const TZ *__restrict__ Z,
-                                                            int64_t ldz, const double *__restrict__ y,
+__global__ __launch_bounds__(kThreads) void update_x_kernel(const Tile *__restrict__ tiles, const TZ *__restrict__ Z,
+                                                            int64_t ldz, const double *__restrict__ y_all, int ldv,
+                                                            const GmresState *__restrict__ st,
+                                                            const int *__restrict__ active,
                                                             double *__restrict__ x) {
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kThreads * kDotU) + threadIdx.x;
+  const Tile tl = tiles[blockIdx.x];
+  if (!active[tl.pair]) return;
+  const int ncols = st[tl.pair].k;
+  const double *y = y_all + static_cast<int64_t>(tl.pair) * ldv;
+  const int64_t base = tl.start + threadIdx.x;
+  const int lim = tl.len - static_cast<int>(threadIdx.x);
   double xx[kDotU];
 #pragma unroll
-  for (int k = 0; k < kDotU; ++k) {
-    const int64_t e = base + k * kThreads;
-    xx[k] = e < n ? x[e] : 0.0;
-  }
+  for (int k = 0; k < kDotU; ++k) xx[k] = k * kThreads < lim ? x[base + k * kThreads] : 0.0;
   for (int i = 0; i < ncols; ++i) {
     const double yi = y[i];
     const TZ *z = Z + static_cast<int64_t>(i) * ldz;
 #pragma unroll
-    for (int k = 0; k < kDotU; ++k) {
-      const int64_t e = base + k * kThreads;
-      if (e < n) xx[k] += yi * static_cast<double>(z[e]);
-    }
+    for (int k = 0; k < kDotU; ++k)
+      if (k * kThreads < lim) xx[k] += yi * static_cast<double>(z[base + k * kThreads]);
   }
 #pragma unroll
-  for (int k = 0; k < kDotU; ++k) {
-    const int64_t e = base + k * kThreads;
-    if (e < n) x[e] = xx[k];
-  }
+  for (int k = 0; k < kDotU; ++k)
+    if (k * kThreads < lim) x[base + k * kThreads] = xx[k];
 }
 
-// partial[blk] = sum over the block's range of v[e]^2
-__global__ __launch_bounds__(kThreads) void norm2_partial_kernel(int64_t n, const double *__restrict__ v,
-                                                                  double *__restrict__ partial) {
-  __shared__ double lds[kThreads / 64];
-  int64_t lo, hi;
-  red_range(n, blockIdx.x, lo, hi);
-  double s = 0.0;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) s += v[e] * v[e];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// Sum of kRedBlocks partials into *out (single block), sqrt if requested.
-__global__ __launch_bounds__(kThreads) void reduce_scalar_kernel(const double *__restrict__ partial,
-                                                                 double *__restrict__ out, int take_sqrt) {
-  __shared__ double lds[kThreads / 64];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < kRedBlocks; k += kThreads) s += partial[k];
-  s = block_sum(s, lds);
-  if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
-}
-
-// Start a cycle: clear the state and g.
-__global__ void cycle_init_kernel(GmresState *st, double *__restrict__ g, int m) {
-  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = 0.0;
+// Start a cycle: per pair, clear the state and g (done = not active); pair 0's
+// block also resets the batch control words.
+__global__ __launch_bounds__(64) void cycle_init_kernel(GmresState *__restrict__ st, BatchCtl *ctl, int npairs,
+                                                        int nactive, const int *__restrict__ active,
+                                                        double *__restrict__ g_all, int ldv) {
+  const int p = blockIdx.x;
+  double *g = g_all + static_cast<int64_t>(p) * ldv;
+  for (int i = threadIdx.x; i < ldv; i += blockDim.x) g[i] = 0.0;
   if (threadIdx.x == 0) {
-    st->done = 0;
-    st->skip_apply = 0;
-    st->finishing = 0;
-    st->k = 0;
-    st->nan = 0;
-    st->est = 0.0;
-    st->nu = 1.0;
+    const int on = active[p] != 0;
+    st[p].done = !on;
+    st[p].skip_apply = !on;
+    st[p].finishing = 0;
+    st[p].k = 0;
+    st[p].nan = 0;
+    st[p].est = 0.0;
+    st[p].nu = 1.0;
+    if (p == 0) {
+      ctl->napply_left = nactive;
+      ctl->ndone = npairs - nactive;
+      ctl->skip_all_apply = nactive == 0;
+      ctl->all_done = nactive == 0;
+    }
   }
 }
 
-// Back substitution y = R(0:k,0:k)^{-1} g(0:k), one wavefront: R is staged in
-// LDS, each step finishes one unknown and updates the remaining right-hand side
-// in parallel.
-__global__ __launch_bounds__(64) void backsolve_kernel(const GmresState *st, const double *__restrict__ Hr, int ldh,
-                                                       const double *__restrict__ g, double *__restrict__ y) {
+// Back substitution y = R(0:k,0:k)^{-1} g(0:k) for pair blockIdx.x, one
+// wavefront: R is staged in LDS, each step finishes one unknown and updates
+// the remaining right-hand side in parallel.
+__global__ __launch_bounds__(64) void backsolve_kernel(const GmresState *__restrict__ st_all,
+                                                       const double *__restrict__ Hr_all, int ldh, int m,
+                                                       const double *__restrict__ g_all,
+                                                       double *__restrict__ y_all, int ldv) {
   __shared__ double R[kMaxCols][kMaxCols + 1];
   __shared__ double rhs[kMaxCols];
-  const int k = st->k, t = threadIdx.x;
+  const int p = blockIdx.x;
+  const int k = st_all[p].k, t = threadIdx.x;
+  const double *Hr = Hr_all + static_cast<int64_t>(p) * ldh * m;
+  const double *g = g_all + static_cast<int64_t>(p) * ldv;
+  double *y = y_all + static_cast<int64_t>(p) * ldv;
   for (int c = 0; c < k; ++c)
     for (int i = t; i <= c; i += 64) R[i][c] = Hr[static_cast<int64_t>(c) * ldh + i];
   for (int i = t; i < k; i += 64) rhs[i] = g[i];

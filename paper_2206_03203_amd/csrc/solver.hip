@@ -1,22 +1,27 @@
-// Device side of the solve phase: upload of the host-built hierarchy, the
-// V-cycle that defines Q_OO / Q_GG (Section 3.3), the preconditioner action of
-// Algorithm 1 (M_L of eq. (8)) and right-preconditioned flexible GMRES
-// (Section 3.2; zero initial guess and relative-residual stop, Section 4).
+// Device side of the solve phase: upload of host-built hierarchies (one
+// system, or many concatenated block-diagonally), the V-cycle that defines
+// Q_OO / Q_GG (Section 3.3), the preconditioner action of Algorithm 1 (M_L of
+// eq. (8)) and right-preconditioned flexible GMRES (Section 3.2; zero
+// initial guess and relative-residual stop, Section 4).
 //
 // Precision: the preconditioner runs in T (double, or float in mixed mode);
 // the outer matrix, Krylov basis V, Hessenberg/Givens data and the coarsest
-// dense inverse are always FP64.  Z (the preconditioned directions) is kept
-// in T: A z_j is formed from the stored z_j, so FP32 storage is exact for
-// the flexible method.
+// dense inverses are always FP64.  Z (the preconditioned directions) is kept
+// in T: A z_j is formed from the stored z_j, so FP32 storage is exact for the
+// flexible method.
 //
-// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): every pass reads
-// each basis vector once and reductions use fixed trees, so results do not
-// depend on scheduling.  Basis vectors are stored unnormalised with a
-// per-column scale (1/norm) applied on every read, which saves a pass.
+// Arnoldi: classical Gram-Schmidt whose reorthogonalisation of basis vector j
+// is folded into step j+1 (one fused reduction pass and one update pass per
+// step).  Reductions use fixed trees over fixed tiles, so results do not
+// depend on scheduling.  Every (system, rhs) pair runs its own Krylov process
+// with its own convergence test; whole-batch kernels (preconditioner, system
+// matrix) stop once no pair needs them in the current cycle.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <tuple>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -26,6 +31,9 @@
 namespace mdp {
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Upload helpers
 
 // Lanes per row for the CSR-vector kernel: enough that one batch of
 // kCsrBatch entries per lane covers an average row.
@@ -42,9 +50,36 @@ void upload_vec(DevMem &d, const std::vector<T> &h, hipStream_t s) {
   if (!h.empty()) MDP_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-// Sliced ELL pays off when rows are short and similar within 64-row slices.
+// Host staging buffers must outlive the asynchronous copies: they are kept
+// here until the stream is synchronised.
+struct Keep {
+  std::vector<std::vector<int32_t>> i32;
+  std::vector<std::vector<double>> f64;
+  std::vector<std::vector<float>> f32;
+  std::vector<std::vector<DenseDesc>> dd;
+  std::vector<int32_t> &put(std::vector<int32_t> &&v) {
+    i32.push_back(std::move(v));
+    return i32.back();
+  }
+  std::vector<double> &put(std::vector<double> &&v) {
+    f64.push_back(std::move(v));
+    return f64.back();
+  }
+  std::vector<float> &put(std::vector<float> &&v) {
+    f32.push_back(std::move(v));
+    return f32.back();
+  }
+  std::vector<DenseDesc> &put(std::vector<DenseDesc> &&v) {
+    dd.push_back(std::move(v));
+    return dd.back();
+  }
+};
+
+// Upload a host CSR in the device format that suits it: sliced ELL when the
+// 64-row slices carry little padding, one thread per row for other short
+// rows, LPR lanes per row otherwise.
 template <typename T>
-void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vector<T>> &keep) {
+void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   d.nr = h.nr;
   d.nc = h.nc;
   d.nnz = h.nnz();
@@ -58,8 +93,6 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vecto
     padded += 64 * static_cast<int64_t>(w);
     maxlen = std::max(maxlen, w);
   }
-  // sliced ELL when slices carry little padding; one thread per row for other
-  // short rows; LPR lanes per row otherwise
   const double avg = h.nr > 0 ? static_cast<double>(d.nnz) / h.nr : 0.0;
   d.sell = h.nr > 0 && maxlen <= 64 && padded <= 23 * std::max<int64_t>(d.nnz, 1) / 20 &&
            padded < std::numeric_limits<int32_t>::max();
@@ -67,8 +100,7 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vecto
   if (!d.sell) {
     upload_vec(d.ptr, h.ptr, s);
     upload_vec(d.col, h.col, s);
-    keep.emplace_back(h.val.begin(), h.val.end());
-    upload_vec(d.val, keep.back(), s);
+    upload_vec(d.val, keep.put(std::vector<T>(h.val.begin(), h.val.end())), s);
     return;
   }
   d.nslices = ns;
@@ -98,48 +130,150 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, std::vector<std::vecto
     o += static_cast<int64_t>(w) * 64;
   }
   soff[ns] = static_cast<int32_t>(o);
-  upload_vec(d.ptr, soff, s);
-  upload_vec(d.col, col, s);
-  keep.push_back(std::move(val));
-  upload_vec(d.val, keep.back(), s);
+  upload_vec(d.ptr, keep.put(std::move(soff)), s);
+  upload_vec(d.col, keep.put(std::move(col)), s);
+  upload_vec(d.val, keep.put(std::move(val)), s);
+}
+
+using Piece = std::tuple<const HCsr *, int32_t, int32_t>;  // matrix, row offset, column offset
+
+// Block-diagonal concatenation of pieces into an nr x nc matrix.
+HCsr concat_blocks(int32_t nr, int32_t nc, const std::vector<Piece> &pieces) {
+  std::vector<int32_t> rowlen(static_cast<size_t>(nr), 0);
+  for (const auto &pc : pieces) {
+    const HCsr &m = *std::get<0>(pc);
+    const int32_t ro = std::get<1>(pc);
+    for (int32_t i = 0; i < m.nr; ++i) rowlen[ro + i] = m.ptr[i + 1] - m.ptr[i];
+  }
+  HCsr out = HCsr::empty(nr, nc);
+  for (int32_t i = 0; i < nr; ++i) out.ptr[i + 1] = out.ptr[i] + rowlen[i];
+  out.col.resize(static_cast<size_t>(out.ptr[nr]));
+  out.val.resize(static_cast<size_t>(out.ptr[nr]));
+  for (const auto &pc : pieces) {
+    const HCsr &m = *std::get<0>(pc);
+    const int32_t ro = std::get<1>(pc), co = std::get<2>(pc);
+    for (int32_t i = 0; i < m.nr; ++i) {
+      int32_t q = out.ptr[ro + i];
+      for (int32_t p = m.ptr[i]; p < m.ptr[i + 1]; ++p, ++q) {
+        out.col[q] = m.col[p] + co;
+        out.val[q] = m.val[p];
+      }
+    }
+  }
+  return out;
+}
+
+// Level orderings of a batch of hierarchies: at every level, systems that
+// continue to the next level first, then dense-coarsest ones, then swept
+// ones (each group in pair order).  off[l][p] = row offset of hierarchy p at
+// level l (-1 if absent).
+struct LevelPlan {
+  std::vector<std::vector<int>> order;
+  std::vector<std::vector<int64_t>> off;
+  std::vector<int32_t> n, ncont, sw_off;
+};
+
+LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
+  LevelPlan pl;
+  size_t L = 0;
+  for (const HHier *h : hs) L = std::max(L, h->lv.size());
+  pl.order.resize(L);
+  pl.off.assign(L, std::vector<int64_t>(hs.size(), -1));
+  pl.n.assign(L, 0);
+  pl.ncont.assign(L, 0);
+  pl.sw_off.assign(L, 0);
+  for (size_t l = 0; l < L; ++l) {
+    std::vector<int> cont, dense, sweep;
+    for (size_t p = 0; p < hs.size(); ++p) {
+      const HHier &h = *hs[p];
+      if (h.lv.size() <= l) continue;
+      if (l + 1 < h.lv.size())
+        cont.push_back(static_cast<int>(p));
+      else if (h.dense)
+        dense.push_back(static_cast<int>(p));
+      else
+        sweep.push_back(static_cast<int>(p));
+    }
+    int64_t o = 0;
+    auto place = [&](const std::vector<int> &v) {
+      for (int p : v) {
+        pl.off[l][p] = o;
+        pl.order[l].push_back(p);
+        o += hs[p]->lv[l].A.nr;
+      }
+    };
+    place(cont);
+    pl.ncont[l] = static_cast<int32_t>(o);
+    place(dense);
+    pl.sw_off[l] = static_cast<int32_t>(o);
+    place(sweep);
+    if (o > std::numeric_limits<int32_t>::max()) raise(MDP_EINVAL, "batch level exceeds int32 indexing");
+    pl.n[l] = static_cast<int32_t>(o);
+  }
+  return pl;
 }
 
 template <typename T>
-void upload_hier(const HHier &h, DHier<T> &d, hipStream_t s, std::vector<std::vector<T>> &keep) {
+void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep) {
+  const size_t L = pl.order.size();
   d.lv.clear();
-  d.lv.resize(h.lv.size());
-  for (size_t l = 0; l < h.lv.size(); ++l) {
-    const HLevel &hl = h.lv[l];
+  d.lv.resize(L);
+  std::vector<double> cinv;
+  for (size_t l = 0; l < L; ++l) {
     DLevel<T> &dl = d.lv[l];
-    dl.n = hl.A.nr;
-    upload_csr(hl.A, dl.A, s, keep);
-    std::vector<T> dinv(hl.dl1.size());
-    for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = static_cast<T>(1.0 / hl.dl1[i]);
-    keep.push_back(std::move(dinv));
-    upload_vec(dl.dinv, keep.back(), s);
+    dl.n = pl.n[l];
+    dl.ncont = pl.ncont[l];
+    dl.sw_off = pl.sw_off[l];
+    std::vector<Piece> pa, pp, pr, psw;
+    std::vector<T> dinv(static_cast<size_t>(dl.n));
+    std::vector<DenseDesc> desc;
+    for (int p : pl.order[l]) {
+      const HHier &h = *hs[p];
+      const HLevel &hl = h.lv[l];
+      const int32_t o = static_cast<int32_t>(pl.off[l][p]);
+      for (int32_t i = 0; i < hl.A.nr; ++i) dinv[o + i] = static_cast<T>(1.0 / hl.dl1[i]);
+      if (l + 1 < h.lv.size()) {
+        const int32_t oc = static_cast<int32_t>(pl.off[l + 1][p]);
+        pa.emplace_back(&hl.A, o, o);
+        pp.emplace_back(&hl.P, o, oc);
+        pr.emplace_back(&hl.R, oc, o);
+      } else if (h.dense) {
+        desc.push_back(DenseDesc{o, hl.A.nr, static_cast<int64_t>(cinv.size())});
+        cinv.insert(cinv.end(), h.coarse_inv.begin(), h.coarse_inv.end());
+        dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
+      } else {
+        psw.emplace_back(&hl.A, o - dl.sw_off, o - dl.sw_off);
+      }
+    }
+    upload_csr(concat_blocks(dl.ncont, dl.ncont, pa), dl.A, s, keep);
+    if (l + 1 < L) {
+      upload_csr(concat_blocks(dl.ncont, pl.n[l + 1], pp), dl.P, s, keep);
+      upload_csr(concat_blocks(pl.n[l + 1], dl.ncont, pr), dl.R, s, keep);
+    }
+    upload_csr(concat_blocks(dl.n - dl.sw_off, dl.n - dl.sw_off, psw), dl.Asw, s, keep);
+    dl.ndense = static_cast<int32_t>(desc.size());
+    upload_vec(dl.dense, keep.put(std::move(desc)), s);
+    upload_vec(dl.dinv, keep.put(std::move(dinv)), s);
     const size_t nb = static_cast<size_t>(std::max(dl.n, 1)) * sizeof(T);
     dl.x.alloc(nb);
     dl.b.alloc(nb);
     dl.t.alloc(nb);
     dl.r.alloc(nb);
-    if (l + 1 < h.lv.size()) {
-      upload_csr(hl.P, dl.P, s, keep);
-      upload_csr(hl.R, dl.R, s, keep);
-    }
+    if (dl.n > dl.sw_off) dl.pp.alloc(2 * static_cast<size_t>(dl.n - dl.sw_off) * sizeof(T));
   }
-  d.dense = h.dense;
-  d.nc = h.lv.back().A.nr;
-  if (h.dense) upload_vec(d.cinv, h.coarse_inv, s);
+  upload_vec(d.cinv, keep.put(std::move(cinv)), s);
   const size_t n0 = static_cast<size_t>(std::max(d.n(), 1)) * sizeof(T);
   d.tmp_res.alloc(n0);
   d.tmp_dz.alloc(n0);
-  d.tmp_pp.alloc(2 * static_cast<size_t>(std::max(d.nc, 1)) * sizeof(T));
 }
 
 int grid_for(int64_t n) {
   const int64_t b = (n + kThreads - 1) / kThreads;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
 }
+
+// ---------------------------------------------------------------------------
+// Sparse products
 
 // Algorithmic bytes of one sparse product: matrix values, column indices and
 // row pointers once, each vector entry read or written once.
@@ -149,12 +283,10 @@ double spmv_bytes(const DCsr<TA> &A) {
   const double sx = sizeof(TX), sy = sizeof(TY);
   if (MODE == kPlain) b += sx * A.nc + sy * A.nr;
   if (MODE == kResid) b += sx * A.nc + 2 * sy * A.nr;
-  if (MODE == kSmooth) b += sx * A.nc + 3 * sy * A.nr;  // x, b, dinv, y
-  if (MODE == kPre0) b += 2 * sy * A.nc + 2 * sy * A.nr;  // b, dinv; y2, y
+  if (MODE == kSmooth) b += sx * A.nc + 3 * sy * A.nr;      // x, b, dinv, y
   if (MODE == kAccum) b += sx * A.nc + 2 * sy * A.nr;
-  if (MODE == kPlainScale) b += sx * A.nc + 2 * sy * A.nr;   // x; dinv, y (+ y2)
-  if (MODE == kResidScale) b += sx * A.nc + 4 * sy * A.nr;   // x; b, dinv, y, y2
-  if (MODE == kPlainScale) b += sy * A.nr;
+  if (MODE == kPlainScale) b += sx * A.nc + 3 * sy * A.nr;  // x; dinv, y, y2
+  if (MODE == kResidScale) b += sx * A.nc + 4 * sy * A.nr;  // x; b, dinv, y, y2
   return b;
 }
 
@@ -198,66 +330,79 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
   }
 }
 
-// The V-cycle below expects the finest level's scratch `t` to hold the first
-// l1-Jacobi iterate from zero, x0 = D^-1 b; the kernels that produce b also
-// write x0 (restriction, the fracture-residual update, the input cast), so the
+template <typename T>
+const T *cnull() {
+  return static_cast<const T *>(nullptr);
+}
+template <typename T>
+T *mnull() {
+  return static_cast<T *>(nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Section 3.3): l1-Jacobi pre-smoothing from zero, residual,
+// restriction, coarse correction, prolongation, l1-Jacobi post-smoothing.
+//
+// The finest level's scratch `t` must hold the first smoothing iterate
+// x0 = D^-1 b on entry; the kernels that produce b also write x0
+// (restriction, the fracture-residual update, the input cast), so the
 // smoother's residual needs one gather per nonzero.
+
 template <typename T>
 void start_smoother(DHier<T> &H, const T *b, const int *gate, hipStream_t s) {
   const int n = H.n();
-  if (n == 0 || (H.lv.size() == 1 && H.dense)) return;
+  if (n == 0 || H.dense_only()) return;
   timed_launch(kKcVcycleOther, s, 3.0 * sizeof(T) * n, [&] {
     hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
                        dptr<const T>(H.lv[0].dinv), dptr<T>(H.lv[0].t), gate);
   });
 }
 
+// Systems whose coarsest level is l: dense inverses, or four l1-Jacobi sweeps
+// from zero (the first, D^-1 b, is already in t).
 template <typename T>
-void coarse_solve(DHier<T> &H, const T *b, T *x, const int *gate, hipStream_t s) {
-  DLevel<T> &L = H.lv.back();
-  const int n = L.n;
-  if (n == 0) return;
-  if (H.dense) {
-    const int blocks = (n + (kThreads / 64) - 1) / (kThreads / 64);
-    timed_launch(kKcVcycleOther, s, 8.0 * n * n + 2.0 * sizeof(T) * n, [&] {
-      hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(blocks), dim3(kThreads), 0, s, n, dptr<const double>(H.cinv),
-                         b, x, gate);
+void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, const int *gate, hipStream_t s) {
+  if (L.ndense > 0) {
+    const dim3 grid((L.max_dense_n + (kThreads / 64) - 1) / (kThreads / 64), L.ndense);
+    timed_launch(kKcVcycleOther, s, 0.0, [&] {
+      hipLaunchKernelGGL(dense_gemv_batched_kernel<T>, grid, dim3(kThreads), 0, s, dptr<const DenseDesc>(L.dense),
+                         dptr<const double>(H.cinv), b, x, gate);
     });
-    return;
   }
-  // four l1-Jacobi sweeps from zero: the first is x0 = D^-1 b, already in t
-  T *pa = dptr<T>(H.tmp_pp), *pb = pa + n;
-  const T *t = dptr<const T>(L.t);
-  const T *dinv = dptr<const T>(L.dinv);
-  const int kc = kKcVcycleOther;
-  spmv<kSmooth>(L.A, t, b, dinv, pa, static_cast<T *>(nullptr), gate, s, kc);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pa), b, dinv, pb, static_cast<T *>(nullptr), gate, s, kc);
-  spmv<kSmooth>(L.A, static_cast<const T *>(pb), b, dinv, x, static_cast<T *>(nullptr), gate, s, kc);
+  const int nsw = L.n - L.sw_off;
+  if (nsw > 0) {
+    const int o = L.sw_off;
+    T *pa = dptr<T>(L.pp), *pb = pa + nsw;
+    const T *t = dptr<const T>(L.t) + o;
+    const T *dinv = dptr<const T>(L.dinv) + o;
+    const int kc = kKcVcycleOther;
+    spmv<kSmooth>(L.Asw, t, b + o, dinv, pa, mnull<T>(), gate, s, kc);
+    spmv<kSmooth>(L.Asw, static_cast<const T *>(pa), b + o, dinv, pb, mnull<T>(), gate, s, kc);
+    spmv<kSmooth>(L.Asw, static_cast<const T *>(pb), b + o, dinv, x + o, mnull<T>(), gate, s, kc);
+  }
 }
 
-// One V-cycle from a zero initial guess: x = V(b), with lv[l].t = D^-1 b on entry.
 template <typename T>
 void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_t s) {
-  if (l + 1 == H.lv.size()) {
-    coarse_solve(H, b, x, gate, s);
-    return;
-  }
   DLevel<T> &L = H.lv[l];
-  DLevel<T> &C = H.lv[l + 1];
-  T *t = dptr<T>(L.t);
-  const T *dinv = dptr<const T>(L.dinv);
-  const bool fine = H.is_omega && l == 0;
-  const int ks = fine ? kKcFineSmooth : kKcVcycleOther;
-  const int kr = fine ? kKcFineResid : kKcVcycleOther;
-  const int ko = kKcVcycleOther;
-  spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), static_cast<T *>(nullptr), gate, s,
-               kr);  // pre-smoothing x = t = D^-1 b done; r = b - A t
-  spmv<kPlainScale>(L.R, dptr<const T>(L.r), static_cast<const T *>(nullptr), dptr<const T>(C.dinv), dptr<T>(C.b),
-                    dptr<T>(C.t), gate, s, ko);  // b_c = R r, t_c = D_c^-1 b_c
-  vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
-  spmv<kAccum>(L.P, dptr<const T>(C.x), static_cast<const T *>(nullptr), static_cast<const T *>(nullptr), t,
-               static_cast<T *>(nullptr), gate, s, ko);  // t += P x_c
-  spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, static_cast<T *>(nullptr), gate, s, ks);  // post-smooth
+  if (L.ncont > 0) {
+    DLevel<T> &C = H.lv[l + 1];
+    T *t = dptr<T>(L.t);
+    const T *dinv = dptr<const T>(L.dinv);
+    const bool fine = H.is_omega && l == 0;
+    const int ks = fine ? kKcFineSmooth : kKcVcycleOther;
+    const int kr = fine ? kKcFineResid : kKcVcycleOther;
+    const int ko = kKcVcycleOther;
+    // pre-smoothing from zero is t = D^-1 b; its residual r = b - A t
+    spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), mnull<T>(), gate, s, kr);
+    // b_c = R r and the coarse level's first iterate t_c = D_c^-1 b_c
+    spmv<kPlainScale>(L.R, dptr<const T>(L.r), cnull<T>(), dptr<const T>(C.dinv), dptr<T>(C.b), dptr<T>(C.t),
+                      gate, s, ko);
+    vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
+    spmv<kAccum>(L.P, dptr<const T>(C.x), cnull<T>(), cnull<T>(), t, mnull<T>(), gate, s, ko);  // t += P x_c
+    spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, mnull<T>(), gate, s, ks);       // post-smooth
+  }
+  if (L.ncont < L.n) coarse_solve(H, L, b, x, gate, s);
 }
 
 // Q = `cycles` V-cycles as a stationary iteration from zero (lv[0].t = D^-1 r on entry).
@@ -265,9 +410,18 @@ template <typename T>
 void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStream_t s) {
   vcycle(H, 0, r, z, gate, s);
   const int n = H.n();
+  DLevel<T> &L0 = H.lv[0];
   for (int c = 1; c < cycles; ++c) {
-    spmv<kResidScale>(H.lv[0].A, static_cast<const T *>(z), r, dptr<const T>(H.lv[0].dinv), dptr<T>(H.tmp_res),
-                      dptr<T>(H.lv[0].t), gate, s, kKcVcycleOther);
+    // residual r - A z and its first smoothing iterate, for the continuing
+    // and the swept systems; dense-solved systems are exact already, so their
+    // residual is zero
+    spmv<kResidScale>(L0.A, static_cast<const T *>(z), r, dptr<const T>(L0.dinv), dptr<T>(H.tmp_res), dptr<T>(L0.t),
+                      gate, s, kKcVcycleOther);
+    const int o = L0.sw_off;
+    if (L0.n > o)
+      spmv<kResidScale>(L0.Asw, static_cast<const T *>(z) + o, r + o, dptr<const T>(L0.dinv) + o,
+                        dptr<T>(H.tmp_res) + o, dptr<T>(L0.t) + o, gate, s, kKcVcycleOther);
+    if (L0.ncont < o) MDP_HIP(hipMemsetAsync(dptr<T>(H.tmp_res) + L0.ncont, 0, sizeof(T) * (o - L0.ncont), s));
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
                        gate);
@@ -286,116 +440,120 @@ void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
   apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
 }
 
+// Preconditioner for a list of pairs' host systems, laid out block-diagonally
+// with the level orders plan_o (all pairs) and plan_g (pairs gpairs, which
+// have fracture unknowns).
 template <typename T>
-std::unique_ptr<Precond<T>> upload_precond(const HostSystem &h, int vcycles, hipStream_t s) {
+std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *> &sys, const LevelPlan &plan_o,
+                                           const LevelPlan &plan_g, const std::vector<int> &gpairs, int vcycles,
+                                           hipStream_t s) {
   auto p = std::make_unique<Precond<T>>();
-  std::vector<std::vector<T>> keep;
-  p->n_o = h.n_o;
-  p->n_g = h.n_g;
+  Keep keep;
   p->vcycles = vcycles;
-  upload_hier(h.Ho, p->Ho, s, keep);
+  std::vector<const HHier *> ho, hg;
+  for (const HostSystem *h : sys) ho.push_back(&h->Ho);
+  for (int q : gpairs) hg.push_back(&sys[q]->Hg);
+  upload_hier(ho, plan_o, p->Ho, s, keep);
   p->Ho.is_omega = true;
-  if (h.n_g > 0) {
-    upload_hier(h.Hg, p->Hg, s, keep);
-    upload_csr(h.Ago, p->Ago, s, keep);
-    p->rg.alloc(static_cast<size_t>(h.n_g) * sizeof(T));
+  p->n_o = p->Ho.n();
+  if (!gpairs.empty()) {
+    upload_hier(hg, plan_g, p->Hg, s, keep);
+    p->n_g = p->Hg.n();
+    std::vector<Piece> pieces;
+    for (size_t k = 0; k < gpairs.size(); ++k) {
+      const int q = gpairs[k];
+      pieces.emplace_back(&sys[q]->Ago, static_cast<int32_t>(plan_g.off[0][k]),
+                          static_cast<int32_t>(plan_o.off[0][q]));
+    }
+    upload_csr(concat_blocks(p->n_g, p->n_o, pieces), p->Ago, s, keep);
+    p->rg.alloc(static_cast<size_t>(p->n_g) * sizeof(T));
   }
   MDP_HIP(hipStreamSynchronize(s));  // host staging vectors die here
   return p;
 }
 
-int dcgs_blocks(int64_t n) { return static_cast<int>((n + kThreads * kDotU - 1) / (kThreads * kDotU)); }
-
-template <typename TZ>
-void update_x(int64_t n, int ncols, const TZ *Z, int64_t ld, const double *y, double *x, hipStream_t s) {
-  timed_launch(kKcOther, s, (16.0 + sizeof(TZ) * ncols) * n, [&] {
-    hipLaunchKernelGGL((update_x_kernel<TZ>), dim3(dcgs_blocks(n)), dim3(kThreads), 0, s, n, ncols, Z, ld, y, x);
-  });
-}
-
-// ||v|| into ws.scalar (device) and returned to the host (synchronises s).
-double norm_sync(Workspace &ws, int64_t n, const double *v, hipStream_t s) {
-  hipLaunchKernelGGL(norm2_partial_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, n, v, dptr<double>(ws.npartial));
-  hipLaunchKernelGGL(reduce_scalar_kernel, dim3(1), dim3(kThreads), 0, s, dptr<const double>(ws.npartial),
-                     dptr<double>(ws.scalar), 1);
-  MDP_HIP(hipMemcpyAsync(ws.host_scalar, ws.scalar.get(), sizeof(double), hipMemcpyDeviceToHost, s));
-  MDP_HIP(hipStreamSynchronize(s));
-  return *ws.host_scalar;
-}
+// ---------------------------------------------------------------------------
+// FGMRES over a batch of pairs
 
 template <typename T>
-int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, mdp_stats *st) {
-  Workspace &ws = S.ws;
-  const int64_t n = S.n, ld = ws.ld;
-  const int m = ws.m;
-  const bool use_x0 = (S.opt.flags & MDP_USE_X0) != 0;
+struct Problem {
+  const DCsr<double> *A;
+  Precond<T> *P;
+  const Layout *L;
+  Workspace *ws;
+  const mdp_options *opt;
+};
+
+// Per-pair norms of v (device) into ws.host_norms (synchronises s).
+void pair_norms(Workspace &ws, const Layout &L, const double *v, hipStream_t s) {
+  hipLaunchKernelGGL(tile_norm2_kernel, dim3(L.ntiles), dim3(kThreads), 0, s, dptr<const Tile>(L.tiles), v,
+                     dptr<double>(ws.npart));
+  hipLaunchKernelGGL(pair_norm_kernel, dim3(L.npairs), dim3(kThreads), 0, s, dptr<const double>(ws.npart),
+                     dptr<const int>(L.tile_off), dptr<double>(ws.norms));
+  MDP_HIP(hipMemcpyAsync(ws.host_norms, ws.norms.get(), sizeof(double) * L.npairs, hipMemcpyDeviceToHost, s));
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
+// Solve A x = b for every pair; bg / xg are in the global layout.  st has one
+// entry per pair.  Returns the most severe code (errors before non-convergence).
+template <typename T>
+int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_t s, mdp_stats *st) {
+  Workspace &ws = *pb.ws;
+  const Layout &L = *pb.L;
+  const DCsr<double> &A = *pb.A;
+  Precond<T> &P = *pb.P;
+  const mdp_options &opt = *pb.opt;
+  const int64_t n = L.n, ld = ws.ld;
+  const int m = ws.m, np = L.npairs;
   double *V = dptr<double>(ws.V);
   T *Z = dptr<T>(ws.Z);
   double *w = dptr<double>(ws.w);
   GmresState *dst = dptr<GmresState>(ws.state);
+  BatchCtl *ctl = dptr<BatchCtl>(ws.ctl);
+  const int *gate_apply = &ctl->skip_all_apply;
+  const Tile *tiles = dptr<const Tile>(L.tiles);
 
-  // caller order -> [Omega; Gamma]
-  const double *bp = b;
-  double *xp = x;
-  if (!S.host.identity) {
-    const int g = grid_for(n);
-    hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, S.n, dptr<const int>(S.perm), b,
-                       dptr<double>(ws.bp));
-    bp = dptr<const double>(ws.bp);
-    xp = dptr<double>(ws.xp);
-    if (use_x0)
-      hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, S.n, dptr<const int>(S.perm), x, xp);
+  std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0);
+  std::vector<int> iters(np, 0), cycles(np, 0), code(np, MDP_OK), active(np, 0), kmax_h(np, 0);
+  pair_norms(ws, L, bg, s);
+  for (int p = 0; p < np; ++p) {
+    bnorm[p] = ws.host_norms[p];
+    tol[p] = opt.rtol * bnorm[p];
+    if (!std::isfinite(bnorm[p])) code[p] = MDP_ENAN;
   }
-  const double bnorm = norm_sync(ws, n, bp, s);
-  mdp_stats out{};
-  if (!std::isfinite(bnorm)) {
-    out.status = MDP_ENAN;
-    if (st) *st = out;
-    return MDP_ENAN;
-  }
-  if (!use_x0) MDP_HIP(hipMemsetAsync(xp, 0, n * sizeof(double), s));
-  if (bnorm == 0.0) {
-    if (use_x0) MDP_HIP(hipMemsetAsync(xp, 0, n * sizeof(double), s));
-    if (!S.host.identity)
-      hipLaunchKernelGGL(permute_kernel<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, S.n,
-                         dptr<const int>(S.perm), static_cast<const double *>(xp), x);
-    MDP_HIP(hipStreamSynchronize(s));
-    out.converged = 1;
-    out.status = MDP_OK;
-    if (st) *st = out;
-    return MDP_OK;
-  }
-  const double tol_abs = S.opt.rtol * bnorm;
-  double beta;
+  if (!use_x0) MDP_HIP(hipMemsetAsync(xg, 0, n * sizeof(double), s));
   if (use_x0) {
-    spmv<kResid>(S.A, static_cast<const double *>(xp), bp, static_cast<const double *>(nullptr), V,
-                 static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
-    beta = norm_sync(ws, n, V, s);
+    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), nullptr, s);
+    pair_norms(ws, L, V, s);
+    for (int p = 0; p < np; ++p) beta[p] = ws.host_norms[p];
   } else {
-    MDP_HIP(hipMemcpyAsync(V, bp, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    beta = bnorm;  // ws.scalar holds ||b|| = ||r_0||
+    MDP_HIP(hipMemcpyAsync(V, bg, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    beta = bnorm;
   }
 
-  int iters = 0, cycles = 0, code = MDP_OK;
-  double est = beta;
-  const int nblk = dcgs_blocks(n);
-  const int *gate_apply = &dst->skip_apply;
-  const int *gate_done = &dst->done;
   while (true) {
-    if (!std::isfinite(beta)) {
-      code = MDP_ENAN;
-      break;
+    int nactive = 0, kmax_all = 0;
+    for (int p = 0; p < np; ++p) {
+      if (code[p] == MDP_OK && !std::isfinite(beta[p])) code[p] = MDP_ENAN;
+      active[p] = code[p] == MDP_OK && bnorm[p] > 0.0 && beta[p] > tol[p] && iters[p] < opt.max_iter;
+      kmax_h[p] = std::min(m, opt.max_iter - iters[p]);
+      if (active[p]) {
+        ++nactive;
+        kmax_all = std::max(kmax_all, kmax_h[p]);
+      }
     }
-    if (beta <= tol_abs || iters >= S.opt.max_iter) break;
-    const int kmax = std::min(m, S.opt.max_iter - iters);
-    // V[:, 0] holds the residual of the cycle start, unnormalised.
-    hipLaunchKernelGGL(cycle_init_kernel, dim3(1), dim3(64), 0, s, dst, dptr<double>(ws.g), m);
-    int last = -1;
+    if (nactive == 0) break;
+    MDP_HIP(hipMemcpyAsync(ws.active.get(), active.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+    MDP_HIP(hipMemcpyAsync(ws.kmaxp.get(), kmax_h.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+    MDP_HIP(hipMemcpyAsync(ws.tolp.get(), tol.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(cycle_init_kernel, dim3(np), dim3(64), 0, s, dst, ctl, np, nactive,
+                       dptr<const int>(ws.active), dptr<double>(ws.g), ws.ldv);
+    // V[:, 0] holds every pair's residual at the cycle start, unnormalised.
     // Steps 0..kmax-1 apply the preconditioner; step kmax (if reached) only
     // finalises the last Hessenberg column.
-    for (int j = 0; j <= kmax; ++j) {
+    for (int j = 0; j <= kmax_all; ++j) {
       const KtBytes kt_before = ktimer_bytes();
-      T *zj = Z + std::min(j, kmax - 1) * ld;
+      T *zj = Z + std::min(j, kmax_all - 1) * ld;
       const double *uj = V + j * ld;
       const T *pin;
       if constexpr (std::is_same<T, double>::value) {
@@ -404,7 +562,7 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
       } else {
         T *rin = dptr<T>(ws.rin);
         const int no = P.n_o;
-        const bool need_t = !(P.Ho.lv.size() == 1 && P.Ho.dense);
+        const bool need_t = !P.Ho.dense_only();
         timed_launch(kKcOther, s, 12.0 * n + 8.0 * no, [&] {
           hipLaunchKernelGGL(cast_start_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, no, uj, rin,
                              dptr<const float>(P.Ho.lv[0].dinv), need_t ? dptr<float>(P.Ho.lv[0].t) : nullptr,
@@ -413,131 +571,209 @@ int fgmres(Solver &S, Precond<T> &P, const double *b, double *x, hipStream_t s, 
         pin = rin;
       }
       apply_ml(P, pin, zj, gate_apply, s);
-      spmv<kPlain>(S.A, static_cast<const T *>(zj), static_cast<const double *>(nullptr),
-                   static_cast<const double *>(nullptr), w, static_cast<double *>(nullptr), gate_apply, s,
-                   kKcOuterSpmv);
+      spmv<kPlain>(A, static_cast<const T *>(zj), cnull<double>(), cnull<double>(), w, mnull<double>(), gate_apply,
+                   s, kKcOuterSpmv);
       const int nv = 2 * j + 3;
       timed_launch(kKcArnoldiDot, s, 8.0 * n * (j + 2), [&] {
-        hipLaunchKernelGGL(dcgs_reduce_kernel, dim3(nblk), dim3(kThreads), 0, s, n, j, static_cast<const double *>(V),
-                           ld, static_cast<const double *>(w), dptr<double>(ws.partial), nblk, gate_done);
+        hipLaunchKernelGGL(dcgs_reduce_kernel, dim3(L.ntiles), dim3(kThreads), 0, s, tiles, L.ntiles, j,
+                           static_cast<const double *>(V), ld, static_cast<const double *>(w),
+                           dptr<double>(ws.partial), static_cast<const GmresState *>(dst));
       });
-      timed_launch(kKcOther, s, 8.0 * nv * nblk, [&] {
-        hipLaunchKernelGGL(block_sums_kernel, dim3(nv), dim3(kThreads), 0, s, nv, dptr<const double>(ws.partial),
-                           nblk, dptr<double>(ws.sums), gate_done);
+      timed_launch(kKcOther, s, 8.0 * nv * L.ntiles, [&] {
+        hipLaunchKernelGGL(pair_sums_kernel, dim3(nv, np), dim3(kThreads), 0, s, nv, dptr<const double>(ws.partial),
+                           L.ntiles, dptr<const int>(L.tile_off), dptr<double>(ws.sums), ws.sstride,
+                           static_cast<const GmresState *>(dst));
       });
       timed_launch(kKcOther, s, 0.0, [&] {
-        hipLaunchKernelGGL(dcgs_finalize_kernel, dim3(1), dim3(64), 0, s, dst, j, kmax, tol_abs,
-                           dptr<const double>(ws.sums), dptr<double>(ws.hprev), dptr<DcgsCoef>(ws.coef),
-                           dptr<double>(ws.Hr), m + 1, dptr<double>(ws.cs), dptr<double>(ws.sn),
-                           dptr<double>(ws.g), dptr<double>(ws.hist));
+        hipLaunchKernelGGL(dcgs_finalize_kernel, dim3(np), dim3(64), 0, s, dst, ctl, np, j,
+                           dptr<const int>(ws.kmaxp), dptr<const double>(ws.tolp), dptr<const double>(ws.sums),
+                           ws.sstride, dptr<double>(ws.hprev), dptr<DcgsCoef>(ws.coef), dptr<double>(ws.Hr), m + 1,
+                           m, dptr<double>(ws.cs), dptr<double>(ws.sn), dptr<double>(ws.g), dptr<double>(ws.hist),
+                           ws.ldv);
       });
       timed_launch(kKcArnoldiAxpy, s, 8.0 * n * (j + 4), [&] {
-        hipLaunchKernelGGL(dcgs_update_kernel, dim3(nblk), dim3(kThreads), 0, s, n, j, V, ld,
-                           static_cast<const double *>(w), dptr<const DcgsCoef>(ws.coef), gate_done);
+        hipLaunchKernelGGL(dcgs_update_kernel, dim3(L.ntiles), dim3(kThreads), 0, s, tiles, j, V, ld,
+                           static_cast<const double *>(w), dptr<const DcgsCoef>(ws.coef),
+                           static_cast<const GmresState *>(dst));
       });
-      MDP_HIP(hipMemcpyAsync(&ws.host_state[j], dst, sizeof(GmresState), hipMemcpyDeviceToHost, s));
+      MDP_HIP(hipMemcpyAsync(&ws.host_ctl[j], ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
       MDP_HIP(hipEventRecord(ws.ev[j], s));
-      last = j;
       if (j >= 1) {
         MDP_HIP(hipEventSynchronize(ws.ev[j - 1]));
-        if (ws.host_state[j - 1].done) {
+        if (ws.host_ctl[j - 1].all_done) {
           ktimer_restore_bytes(kt_before);  // step j was queued after the cycle ended: a no-op
           break;
         }
       }
     }
     MDP_HIP(hipGetLastError());
-    MDP_HIP(hipEventSynchronize(ws.ev[last]));
-    const GmresState fs = ws.host_state[last];
-    if (fs.nan) {
-      code = MDP_ENAN;
-      break;
+    MDP_HIP(hipMemcpyAsync(ws.host_state, dst, sizeof(GmresState) * np, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(backsolve_kernel, dim3(np), dim3(64), 0, s, static_cast<const GmresState *>(dst),
+                       dptr<const double>(ws.Hr), m + 1, m, dptr<const double>(ws.g), dptr<double>(ws.y), ws.ldv);
+    timed_launch(kKcOther, s, 16.0 * n, [&] {
+      hipLaunchKernelGGL((update_x_kernel<T>), dim3(L.ntiles), dim3(kThreads), 0, s, tiles,
+                         static_cast<const T *>(Z), ld, dptr<const double>(ws.y), ws.ldv,
+                         static_cast<const GmresState *>(dst), dptr<const int>(ws.active), xg);
+    });
+    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), nullptr, s);
+    pair_norms(ws, L, V, s);  // synchronises: host_state is valid too
+    for (int p = 0; p < np; ++p) {
+      if (!active[p]) continue;
+      const GmresState &gs = ws.host_state[p];
+      if (gs.nan) code[p] = MDP_ENAN;
+      iters[p] += gs.k;
+      est[p] = gs.est;
+      ++cycles[p];
+      beta[p] = ws.host_norms[p];
     }
-    const int k = fs.k;
-    est = fs.est;
-    iters += k;
-    ++cycles;
-    hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, static_cast<const GmresState *>(dst),
-                       dptr<const double>(ws.Hr), m + 1, dptr<const double>(ws.g), dptr<double>(ws.y));
-    update_x(n, k, static_cast<const T *>(Z), ld, dptr<const double>(ws.y), xp, s);
-    spmv<kResid>(S.A, static_cast<const double *>(xp), bp, static_cast<const double *>(nullptr), V,
-                 static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
-    beta = norm_sync(ws, n, V, s);
   }
-  if (!S.host.identity)
-    hipLaunchKernelGGL(permute_kernel<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, S.n,
-                       dptr<const int>(S.perm), static_cast<const double *>(xp), x);
   MDP_HIP(hipGetLastError());
-  MDP_HIP(hipStreamSynchronize(s));
-  out.iters = iters;
-  out.restarts = std::max(cycles - 1, 0);
-  out.rel_res_true = beta / bnorm;
-  out.rel_res_est = est / bnorm;
-  out.converged = (code == MDP_OK && beta <= tol_abs) ? 1 : 0;
-  if (code == MDP_OK && !out.converged) code = MDP_NOT_CONVERGED;
-  out.status = code;
-  if (st) *st = out;
-  return code;
+  int worst = MDP_OK;
+  for (int p = 0; p < np; ++p) {
+    mdp_stats o{};
+    o.iters = iters[p];
+    o.restarts = std::max(cycles[p] - 1, 0);
+    if (bnorm[p] == 0.0) {
+      o.converged = code[p] == MDP_OK;
+    } else {
+      o.rel_res_true = beta[p] / bnorm[p];
+      o.rel_res_est = (cycles[p] > 0 ? est[p] : beta[p]) / bnorm[p];
+      o.converged = (code[p] == MDP_OK && beta[p] <= tol[p]) ? 1 : 0;
+    }
+    if (code[p] == MDP_OK && !o.converged) code[p] = MDP_NOT_CONVERGED;
+    o.status = code[p];
+    if (st) st[p] = o;
+    if (code[p] < 0) {
+      if (worst >= 0 || code[p] < worst) worst = code[p];
+    } else if (worst >= 0 && code[p] > worst) {
+      worst = code[p];
+    }
+  }
+  return worst;
 }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+
+void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges, int64_t n_total,
+                   hipStream_t s) {
+  npairs = static_cast<int>(ranges.size());
+  n = n_total;
+  std::vector<Tile> tl;
+  std::vector<int32_t> off(static_cast<size_t>(npairs) + 1, 0);
+  for (int p = 0; p < npairs; ++p) {
+    for (const auto &r : ranges[p])
+      for (int64_t o = 0; o < r.second; o += kTileElems)
+        tl.push_back(Tile{r.first + o, static_cast<int32_t>(std::min<int64_t>(kTileElems, r.second - o)), p});
+    off[p + 1] = static_cast<int32_t>(tl.size());
+  }
+  ntiles = static_cast<int>(tl.size());
+  upload_vec(tiles, tl, s);
+  upload_vec(tile_off, off, s);
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
+void Workspace::alloc(int64_t n, int m_, int np, int ntiles, size_t tsz, hipStream_t s) {
+  m = m_;
+  npairs = np;
+  ld = padded_ld(n);
+  ldv = m + 2;
+  sstride = 2 * (m + 1) + 4;
+  const size_t col8 = static_cast<size_t>(ld) * sizeof(double);
+  V.alloc(col8 * (m + 1));
+  Z.alloc(static_cast<size_t>(ld) * tsz * m);
+  w.alloc(col8);
+  rin.alloc(static_cast<size_t>(ld) * tsz);
+  // whole-batch kernels also read the columns of pairs that stopped early:
+  // start from finite values
+  MDP_HIP(hipMemsetAsync(V.get(), 0, V.bytes(), s));
+  MDP_HIP(hipMemsetAsync(Z.get(), 0, Z.bytes(), s));
+  const size_t pv = static_cast<size_t>(np) * ldv * sizeof(double);
+  for (DevMem *d : {&cs, &sn, &g, &y, &hist, &hprev}) d->alloc(pv);
+  Hr.alloc(static_cast<size_t>(np) * (m + 1) * m * sizeof(double));
+  coef.alloc(static_cast<size_t>(np) * sizeof(DcgsCoef));
+  sums.alloc(static_cast<size_t>(np) * sstride * sizeof(double));
+  partial.alloc(static_cast<size_t>(2 * (m + 1) + 3) * std::max(ntiles, 1) * sizeof(double));
+  npart.alloc(static_cast<size_t>(std::max(ntiles, 1)) * sizeof(double));
+  state.alloc(static_cast<size_t>(np) * sizeof(GmresState));
+  ctl.alloc(sizeof(BatchCtl));
+  kmaxp.alloc(static_cast<size_t>(np) * sizeof(int));
+  tolp.alloc(static_cast<size_t>(np) * sizeof(double));
+  active.alloc(static_cast<size_t>(np) * sizeof(int));
+  norms.alloc(static_cast<size_t>(np) * sizeof(double));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_ctl), (m + 2) * sizeof(BatchCtl), hipHostMallocDefault));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_state), np * sizeof(GmresState), hipHostMallocDefault));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_norms), np * sizeof(double), hipHostMallocDefault));
+  ev.resize(static_cast<size_t>(m) + 2);
+  for (auto &e : ev) MDP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
 Workspace::~Workspace() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  if (host_ctl) (void)hipHostFree(host_ctl);
   if (host_state) (void)hipHostFree(host_state);
-  if (host_scalar) (void)hipHostFree(host_scalar);
+  if (host_norms) (void)hipHostFree(host_norms);
 }
 
 void Solver::upload(hipStream_t s) {
   n = host.n;
   n_o = host.n_o;
   n_g = host.n_g;
-  std::vector<std::vector<double>> keep;
+  Keep keep;
   upload_csr(host.A, A, s, keep);
   if (!host.identity) upload_vec(perm, host.perm, s);
+  const std::vector<const HostSystem *> sys{&host};
+  const LevelPlan po = plan_levels({&host.Ho});
+  const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
+  const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(host, opt.vcycles, s);
+    pc32 = upload_precond<float>(sys, po, pg, gp, opt.vcycles, s);
   else
-    pc64 = upload_precond<double>(host, opt.vcycles, s);
-
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt.vcycles, s);
+  layout.build({{{0, n}}}, n, s);
   const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
-  ws.m = opt.restart;
-  ws.ld = padded_ld(n);
-  const size_t col8 = static_cast<size_t>(ws.ld) * sizeof(double);
-  ws.V.alloc(col8 * (ws.m + 1));
-  ws.Z.alloc(static_cast<size_t>(ws.ld) * tsz * ws.m);
-  ws.w.alloc(col8);
-  ws.rin.alloc(static_cast<size_t>(ws.ld) * tsz);
+  ws.alloc(n, opt.restart, 1, layout.ntiles, tsz, s);
   if (!host.identity) {
-    ws.bp.alloc(col8);
-    ws.xp.alloc(col8);
+    ws.bp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+    ws.xp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
   }
-  const size_t mm = static_cast<size_t>(ws.m) + 1;
-  for (DevMem *d : {&ws.cs, &ws.sn, &ws.g, &ws.y, &ws.hist, &ws.hprev}) d->alloc(mm * sizeof(double));
-  ws.Hr.alloc(mm * ws.m * sizeof(double));
-  ws.coef.alloc(sizeof(DcgsCoef));
-  ws.sums.alloc((2 * mm + 3) * sizeof(double));
-  ws.partial.alloc((2 * mm + 3) * static_cast<size_t>(dcgs_blocks(n)) * sizeof(double));
-  ws.npartial.alloc(kRedBlocks * sizeof(double));
-  ws.scalar.alloc(sizeof(double));
-  ws.state.alloc(sizeof(GmresState));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.host_state), mm * sizeof(GmresState), hipHostMallocDefault));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.host_scalar), sizeof(double), hipHostMallocDefault));
-  ws.ev.resize(mm);
-  for (auto &e : ws.ev) MDP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   MDP_HIP(hipStreamSynchronize(s));
   on_device = true;
 }
 
 int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
-  int rc = opt.precision == MDP_MIXED ? fgmres<float>(*this, *pc32, b, x, s, st)
-                                      : fgmres<double>(*this, *pc64, b, x, s, st);
-  const auto t1 = std::chrono::steady_clock::now();
-  if (st) {
-    st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    st->setup_ms = setup_ms;
+  const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
+  const double *bp = b;
+  double *xp = x;
+  if (!host.identity) {
+    const int g = grid_for(n);
+    hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, n, dptr<const int>(perm), b,
+                       dptr<double>(ws.bp));
+    bp = dptr<const double>(ws.bp);
+    xp = dptr<double>(ws.xp);
+    if (use_x0)
+      hipLaunchKernelGGL(permute_kernel<true>, dim3(g), dim3(kThreads), 0, s, n, dptr<const int>(perm), x, xp);
   }
+  mdp_stats out{};
+  int rc;
+  if (opt.precision == MDP_MIXED) {
+    Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt};
+    rc = fgmres<float>(pb, bp, xp, use_x0, s, &out);
+  } else {
+    Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt};
+    rc = fgmres<double>(pb, bp, xp, use_x0, s, &out);
+  }
+  if (!host.identity)
+    hipLaunchKernelGGL(permute_kernel<false>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const int>(perm),
+                       static_cast<const double *>(xp), x);
+  MDP_HIP(hipGetLastError());
+  MDP_HIP(hipStreamSynchronize(s));
+  out.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  out.setup_ms = setup_ms;
+  if (st) *st = out;
   return rc;
 }
 
@@ -545,8 +781,7 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
   const int64_t nn = n;
   switch (op) {
     case MDP_OP_A:
-      spmv<kPlain>(A, x, static_cast<const double *>(nullptr), static_cast<const double *>(nullptr), y,
-                   static_cast<double *>(nullptr), static_cast<const int *>(nullptr), s);
+      spmv<kPlain>(A, x, cnull<double>(), cnull<double>(), y, mnull<double>(), nullptr, s);
       break;
     case MDP_OP_ML:
     case MDP_OP_QOO:
@@ -557,19 +792,22 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
         float *in = dptr<float>(ws.rin);
         float *out = dptr<float>(ws.Z);
         hipLaunchKernelGGL((scale_copy_kernel<double, float>), dim3(grid_for(len)), dim3(kThreads), 0, s, len, x,
-                           static_cast<const double *>(nullptr), in, static_cast<const int *>(nullptr));
+                           cnull<double>(), in, nullptr);
         auto &H = op == MDP_OP_QGG ? pc32->Hg : pc32->Ho;
         start_smoother(H, static_cast<const float *>(in), nullptr, s);
-        if (op == MDP_OP_ML) apply_ml(*pc32, static_cast<const float *>(in), out, nullptr, s);
-        else apply_q(H, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
+        if (op == MDP_OP_ML)
+          apply_ml(*pc32, static_cast<const float *>(in), out, nullptr, s);
+        else
+          apply_q(H, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
         hipLaunchKernelGGL((scale_copy_kernel<float, double>), dim3(grid_for(len)), dim3(kThreads), 0, s, len,
-                           static_cast<const float *>(out), static_cast<const double *>(nullptr), y,
-                           static_cast<const int *>(nullptr));
+                           static_cast<const float *>(out), cnull<double>(), y, nullptr);
       } else {
         auto &H = op == MDP_OP_QGG ? pc64->Hg : pc64->Ho;
         start_smoother(H, x, nullptr, s);
-        if (op == MDP_OP_ML) apply_ml(*pc64, x, y, nullptr, s);
-        else apply_q(H, pc64->vcycles, x, y, nullptr, s);
+        if (op == MDP_OP_ML)
+          apply_ml(*pc64, x, y, nullptr, s);
+        else
+          apply_q(H, pc64->vcycles, x, y, nullptr, s);
       }
       break;
     }
@@ -578,6 +816,125 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
   }
   MDP_HIP(hipGetLastError());
   MDP_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s) {
+  sys = pairs;
+  npairs = static_cast<int>(pairs.size());
+  opt = pairs[0]->opt;
+  std::vector<const HostSystem *> hsys;
+  std::vector<const HHier *> ho, hg;
+  std::vector<int> gpairs;
+  for (int p = 0; p < npairs; ++p) {
+    hsys.push_back(&pairs[p]->host);
+    ho.push_back(&pairs[p]->host.Ho);
+    if (pairs[p]->host.n_g > 0) {
+      gpairs.push_back(p);
+      hg.push_back(&pairs[p]->host.Hg);
+    }
+  }
+  const LevelPlan po = plan_levels(ho);
+  const LevelPlan pg = gpairs.empty() ? LevelPlan{} : plan_levels(hg);
+  n_o = po.n[0];
+  n_g = gpairs.empty() ? 0 : pg.n[0];
+  if (static_cast<int64_t>(n_o) + n_g > std::numeric_limits<int32_t>::max())
+    raise(MDP_EINVAL, "batch exceeds int32 indexing");
+  n = n_o + n_g;
+  // global row of (pair, internal index): Omega rows in the S~ hierarchies'
+  // level-0 order, then Gamma rows in the A_GG hierarchies' level-0 order
+  std::vector<int64_t> goff_g(static_cast<size_t>(npairs), -1);
+  for (size_t k = 0; k < gpairs.size(); ++k) goff_g[gpairs[k]] = n_o + pg.off[0][k];
+  std::vector<int32_t> gidx_h(static_cast<size_t>(n)), gpair_h(static_cast<size_t>(n));
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> ranges(static_cast<size_t>(npairs));
+  HCsr Ag = HCsr::empty(n, n);
+  {
+    std::vector<int32_t> rowlen(static_cast<size_t>(n), 0);
+    for (int p = 0; p < npairs; ++p) {
+      const HostSystem &h = *hsys[p];
+      const int64_t oo = po.off[0][p], og = goff_g[p];
+      ranges[p].push_back({oo, h.n_o});
+      if (h.n_g > 0) ranges[p].push_back({og, h.n_g});
+      for (int32_t i = 0; i < h.n; ++i) {
+        const int64_t g = i < h.n_o ? oo + i : og + (i - h.n_o);
+        rowlen[g] = h.A.ptr[i + 1] - h.A.ptr[i];
+        gidx_h[g] = h.perm[i];
+        gpair_h[g] = p;
+      }
+    }
+    for (int32_t i = 0; i < n; ++i) Ag.ptr[i + 1] = Ag.ptr[i] + rowlen[i];
+    Ag.col.resize(static_cast<size_t>(Ag.ptr[n]));
+    Ag.val.resize(static_cast<size_t>(Ag.ptr[n]));
+    for (int p = 0; p < npairs; ++p) {
+      const HostSystem &h = *hsys[p];
+      const int64_t oo = po.off[0][p], og = goff_g[p];
+      auto gmap = [&](int32_t i) { return static_cast<int32_t>(i < h.n_o ? oo + i : og + (i - h.n_o)); };
+      for (int32_t i = 0; i < h.n; ++i) {
+        int32_t q = Ag.ptr[gmap(i)];
+        for (int32_t k = h.A.ptr[i]; k < h.A.ptr[i + 1]; ++k, ++q) {
+          Ag.col[q] = gmap(h.A.col[k]);
+          Ag.val[q] = h.A.val[k];
+        }
+      }
+    }
+  }
+  Keep keep;
+  upload_csr(Ag, A, s, keep);
+  upload_vec(gidx, keep.put(std::move(gidx_h)), s);
+  upload_vec(gpair, keep.put(std::move(gpair_h)), s);
+  if (opt.precision == MDP_MIXED)
+    pc32 = upload_precond<float>(hsys, po, pg, gpairs, opt.vcycles, s);
+  else
+    pc64 = upload_precond<double>(hsys, po, pg, gpairs, opt.vcycles, s);
+  layout.build(ranges, n, s);
+  const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
+  ws.alloc(n, opt.restart, npairs, layout.ntiles, tsz, s);
+  ws.bp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+  ws.xp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
+int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
+  std::vector<const double *> bptr(static_cast<size_t>(npairs));
+  std::vector<double *> xptr(static_cast<size_t>(npairs));
+  for (int p = 0; p < npairs; ++p) {
+    bptr[p] = io[p].b;
+    xptr[p] = io[p].x;
+  }
+  DevMem bdev(sizeof(void *) * npairs), xdev(sizeof(void *) * npairs);
+  MDP_HIP(hipMemcpyAsync(bdev.get(), bptr.data(), sizeof(void *) * npairs, hipMemcpyHostToDevice, s));
+  MDP_HIP(hipMemcpyAsync(xdev.get(), xptr.data(), sizeof(void *) * npairs, hipMemcpyHostToDevice, s));
+  const int g = grid_for(n);
+  double *bg = dptr<double>(ws.bp), *xg = dptr<double>(ws.xp);
+  hipLaunchKernelGGL(gather_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
+                     dptr<const int>(gpair), dptr<const int>(gidx), dptr<const double *const>(bdev), bg);
+  if (use_x0)
+    hipLaunchKernelGGL(gather_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
+                       dptr<const int>(gpair), dptr<const int>(gidx), dptr<const double *const>(xdev), xg);
+  int rc;
+  if (opt.precision == MDP_MIXED) {
+    Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt};
+    rc = fgmres<float>(pb, bg, xg, use_x0, s, st);
+  } else {
+    Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt};
+    rc = fgmres<double>(pb, bg, xg, use_x0, s, st);
+  }
+  hipLaunchKernelGGL(scatter_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
+                     dptr<const int>(gpair), dptr<const int>(gidx), static_cast<const double *>(xg),
+                     dptr<double *const>(xdev), static_cast<const int *>(nullptr));
+  MDP_HIP(hipGetLastError());
+  MDP_HIP(hipStreamSynchronize(s));  // bdev / xdev die here
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st)
+    for (int p = 0; p < npairs; ++p) {
+      st[p].solve_ms = ms;
+      st[p].setup_ms = sys[p]->setup_ms;
+    }
+  return rc;
 }
 
 }  // namespace mdp

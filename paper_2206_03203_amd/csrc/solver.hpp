@@ -1,5 +1,11 @@
-// Device-resident solver state: the uploaded matrices and AMG hierarchies,
-// the Krylov workspace and the FGMRES driver.
+// Device-resident solver state: uploaded matrices and AMG hierarchies, the
+// Krylov workspace, and the FGMRES driver shared by single and batched solves.
+//
+// A "pair" is one (system, right-hand side) whose Krylov process runs on its
+// own; a single solve is a batch of one pair.  Several systems are solved
+// together as one block-diagonal system whose unknowns are laid out as
+// [Omega of every pair; Gamma of every pair], so that every sparse kernel of
+// the single-system path applies unchanged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,22 +13,22 @@
 #include <memory>
 #include <vector>
 
-#include "types.hpp"
 #include "runtime.hpp"
 #include "setup.hpp"
+#include "types.hpp"
 
 namespace mdp {
 
-// A device sparse matrix, stored either as CSR (long rows; `lpr` lanes per
-// row) or as sliced ELL with 64-row slices (`sell`; `ptr` then holds the
-// slice offsets).
+// A device sparse matrix: sliced ELL (`sell`, 64-row slices, `ptr` = slice
+// offsets), CSR with one thread per row (`scalar`), or CSR with `lpr` lanes
+// per row.
 template <typename T>
 struct DCsr {
   int32_t nr = 0, nc = 0;
   int64_t nnz = 0;
   int lpr = 8;
   bool sell = false;
-  bool scalar = false;  // CSR, one thread per row
+  bool scalar = false;
   int32_t nslices = 0;
   DevMem ptr, col, val;
   const int *p() const { return dptr<const int>(ptr); }
@@ -30,25 +36,33 @@ struct DCsr {
   const T *v() const { return dptr<const T>(val); }
 };
 
+// One level of a (possibly batched) hierarchy.  Rows [0, ncont) belong to
+// systems that continue to the next level; then come the systems whose
+// coarsest level this is: dense-inverse ones, then l1-Jacobi-swept ones
+// (rows [sw_off, n)).
 template <typename T>
 struct DLevel {
   int32_t n = 0;
-  DCsr<T> A, P, R;
-  DevMem dinv;     // 1 / sum_j |a_ij|
-  DevMem x, b, t;  // coarse-level unknown / right-hand side, smoothing scratch
-  DevMem r;        // residual after pre-smoothing
+  int32_t ncont = 0;
+  DCsr<T> A, P, R;  // A: operator of the continuing systems; P, R to/from the next level
+  DevMem dinv;      // n entries: 1 / sum_j |a_ij|
+  int32_t ndense = 0, max_dense_n = 0;
+  DevMem dense;     // DenseDesc[ndense]
+  int32_t sw_off = 0;
+  DCsr<T> Asw;      // swept coarsest systems, indices relative to sw_off
+  DevMem x, b, t, r;  // unknown, right-hand side, smoothing scratch, residual
+  DevMem pp;          // ping-pong for the swept coarsest systems
 };
 
 template <typename T>
 struct DHier {
   std::vector<DLevel<T>> lv;
-  bool dense = false;
-  int32_t nc = 0;
-  DevMem cinv;           // dense FP64 inverse of the coarsest level
-  DevMem tmp_res, tmp_dz;  // extra cycles: residual and correction at level 0
-  DevMem tmp_pp;          // coarsest l1-Jacobi ping-pong
+  DevMem cinv;            // dense FP64 inverses of the coarsest levels
+  DevMem tmp_res, tmp_dz; // extra cycles: residual and correction at level 0
   bool is_omega = false;  // hierarchy on S~ (its finest level is timed separately)
   int32_t n() const { return lv.empty() ? 0 : lv[0].n; }
+  // true when nothing at level 0 smooths (only dense-solved systems there)
+  bool dense_only() const { return lv.size() == 1 && lv[0].ncont == 0 && lv[0].sw_off == lv[0].n; }
 };
 
 // Preconditioner M_L in precision T (Algorithm 1).
@@ -61,17 +75,39 @@ struct Precond {
   int vcycles = 1;
 };
 
+// Tile work list over the pairs' unknowns (global vector layout).
+struct Layout {
+  int npairs = 0;
+  int64_t n = 0;
+  int ntiles = 0;
+  DevMem tiles;     // Tile[ntiles], grouped by pair
+  DevMem tile_off;  // npairs + 1
+  // ranges[p] = the (start, length) pieces of pair p in the global vector
+  void build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges, int64_t n_total,
+             hipStream_t s);
+};
+
 struct Workspace {
   int64_t ld = 0;  // leading dimension of V / Z columns
   int m = 0;       // restart length
-  DevMem V, Z, w, w2, bp, xp, rin;
+  int npairs = 0;
+  int ldv = 0;     // per-pair stride of length-(m+1) arrays
+  int sstride = 0; // per-pair stride of the step sums
+  DevMem V, Z, w, rin, bp, xp;
   DevMem Hr, cs, sn, g, y, hist, hprev, coef, sums;
-  DevMem partial, npartial, scalar;  // reduction scratch
-  DevMem state;                      // GmresState
-  GmresState *host_state = nullptr;  // pinned, one slot per Arnoldi step
-  double *host_scalar = nullptr;     // pinned
+  DevMem partial, npart;
+  DevMem state, ctl, kmaxp, tolp, active, norms;
+  BatchCtl *host_ctl = nullptr;      // pinned, one slot per step
+  GmresState *host_state = nullptr;  // pinned, npairs
+  double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
+  void alloc(int64_t n, int m, int npairs, int ntiles, size_t tsz, hipStream_t s);
   ~Workspace();
+};
+
+struct PairIO {
+  const double *b;  // caller's right-hand side (caller order), device
+  double *x;        // caller's solution (caller order), device
 };
 
 struct Solver {
@@ -83,12 +119,30 @@ struct Solver {
   DevMem perm;     // new -> caller index
   std::unique_ptr<Precond<double>> pc64;
   std::unique_ptr<Precond<float>> pc32;
+  Layout layout;
   Workspace ws;
   double setup_ms = 0.0;
 
   void upload(hipStream_t s);
   int solve(const double *b, double *x, hipStream_t s, mdp_stats *st);
   void apply(int op, const double *x, double *y, hipStream_t s);
+};
+
+// A block-diagonal batch of pairs (a system appears once per right-hand side).
+struct Batch {
+  std::vector<const Solver *> sys;  // per pair
+  int npairs = 0;
+  int32_t n = 0, n_o = 0, n_g = 0;
+  mdp_options opt{};
+  DCsr<double> A;
+  DevMem gidx;  // per global row: caller index within its pair's system
+  DevMem gpair; // per global row: pair
+  std::unique_ptr<Precond<double>> pc64;
+  std::unique_ptr<Precond<float>> pc32;
+  Layout layout;
+  Workspace ws;
+  void build(const std::vector<const Solver *> &pairs, hipStream_t s);
+  int solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st);
 };
 
 }  // namespace mdp

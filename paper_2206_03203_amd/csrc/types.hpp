@@ -9,6 +9,8 @@ constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 constexpr int kRedBlocks = 1024;  // fixed number of partial sums per reduction
 constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi pass
+constexpr int kDotU = 8;          // elements per thread in the Arnoldi passes
+constexpr int kTileElems = 256 * kDotU;
 
 // Per-cycle FGMRES state in device memory.
 struct GmresState {
@@ -20,6 +22,29 @@ struct GmresState {
   int pad;
   double est;      // |g_k|: residual-norm estimate for the final basis of size k
   double nu;       // scale applied to the provisional vector of the next step
+};
+
+// Batch-wide control words (device memory), reset at the start of a cycle.
+struct BatchCtl {
+  int napply_left;     // pairs still applying the preconditioner this cycle
+  int ndone;           // pairs whose cycle has ended
+  int skip_all_apply;  // set when napply_left reaches 0: whole-batch kernels return at once
+  int all_done;        // set when ndone reaches the number of pairs
+};
+
+// A contiguous piece (at most kTileElems entries) of one (system, rhs) pair's
+// unknowns in the global vector layout.
+struct Tile {
+  int64_t start;
+  int32_t len;
+  int32_t pair;
+};
+
+// Coarsest level of one system solved with its dense inverse.
+struct DenseDesc {
+  int32_t row;      // first row in the level vector
+  int32_t n;        // size
+  int64_t inv_off;  // offset of its row-major inverse in the concatenated store
 };
 
 // Per-step coefficients written by the finalise kernel for the update pass.
