@@ -181,17 +181,30 @@ int mdp_level_aggregates(const mdp_handle *h, int32_t block, int32_t level, int3
 
 /* ---- serving: continuous batching over resident hierarchies -------------- */
 
-/* A server owns a progress thread and a device stream.  mem_budget_bytes
- * bounds the Krylov workspace of admitted requests (0 = no bound);
- * max_slots bounds how many requests are on the device at once. */
+/* A server owns max_slots worker threads (1..64), each with its own
+ * non-blocking device stream at the default priority; up to max_slots
+ * requests run on the device at once, on different handles (requests on a
+ * handle that is already being solved wait).  Requests start in arrival order
+ * as soon as they can be admitted: a free slot, an idle handle, and its Krylov
+ * workspace (a handle's V and Z bases and step arrays, allocated on first use)
+ * within mem_budget_bytes together with the workspaces of all registered
+ * handles (0 = no bound).  To admit a request the server frees workspaces of
+ * idle handles, least recently used first; a request whose workspace alone
+ * exceeds the budget runs when no other request is running.  Results do not
+ * depend on what else runs: every request executes the kernels of mdp_solve,
+ * whose reductions have a fixed order.  Returns EINVAL for bad arguments. */
 int mdp_server_create(size_t mem_budget_bytes, int32_t max_slots, mdp_server **out);
 
-/* Make a handle servable.  Its hierarchy stays resident in device memory. */
+/* Make a handle servable.  Its hierarchy stays resident in device memory.
+ * The handle must outlive the server (destroy the server first). */
 int mdp_server_register(mdp_server *srv, mdp_handle *h);
 
-/* Enqueue one solve (nrhs columns, leading dimension n).  Returns at once
- * with a ticket; b/x must stay valid and untouched until mdp_poll reports a
- * final code.  EBUSY if the queue is full. */
+/* Enqueue one solve (nrhs columns, leading dimension n, caller order, as in
+ * mdp_solve).  Returns at once with a ticket.  b must already hold its values
+ * when the call is made (synchronise the stream that wrote it first); b/x must
+ * stay valid and untouched until mdp_poll reports a final code, after which x
+ * is complete on the device.  EINVAL for an unregistered handle or after
+ * destroy has begun, EBUSY if 2^20 requests are queued. */
 int mdp_submit(mdp_server *srv, mdp_handle *h, const double *b_dev, double *x_dev,
                int32_t nrhs, uint64_t *ticket);
 
@@ -200,8 +213,9 @@ int mdp_submit(mdp_server *srv, mdp_handle *h, const double *b_dev, double *x_de
  * completion once. */
 int mdp_poll(mdp_server *srv, uint64_t ticket, mdp_stats *stats);
 
-/* Stop the progress thread after draining admitted requests; frees the
- * server (handles stay owned by the caller). */
+/* Runs every queued request to completion, joins the workers and frees the
+ * server; uncollected tickets are dropped.  Handles stay owned by the caller
+ * (their workspaces may have been freed; they are re-created on demand). */
 int mdp_server_destroy(mdp_server *srv);
 
 /* ---- measurement ------------------------------------------------------ */

@@ -135,6 +135,23 @@ def _dptr(t) -> int:
     return t.data_ptr()
 
 
+def _rhs_pair(h: int, b, x) -> int:
+    """Check that b and x are contiguous float64 device tensors of shape (n,)
+    or (nrhs, n) for the system of handle h (the library cannot check the
+    size of a raw device pointer); return nrhs."""
+    import torch
+
+    n = mdp_info(h)["n"]
+    for name, t in (("b", b), ("x", x)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 device tensor")
+        if t.dim() not in (1, 2) or t.shape[-1] != n:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}; the system has {n} unknowns")
+    if b.shape != x.shape:
+        raise ValueError(f"b {tuple(b.shape)} and x {tuple(x.shape)} differ in shape")
+    return 1 if b.dim() == 1 else b.shape[0]
+
+
 def mdp_options_default(**overrides) -> mdp_options:
     o = mdp_options()
     _check(lib.mdp_options_default(C.byref(o)), "mdp_options_default")
@@ -189,7 +206,7 @@ def mdp_destroy(h: int) -> None:
 def mdp_solve(h: int, b, x, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
     """b, x: CUDA float64 tensors of shape (n,) or (nrhs, n) (each row one
     right-hand side, contiguous).  Returns (code, [stats dicts])."""
-    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    nrhs = _rhs_pair(h, b, x)
     ld = b.shape[-1]
     st = (mdp_stats * nrhs)()
     rc = lib.mdp_solve(h, _dptr(b), _dptr(x), nrhs, ld, _stream_ptr(stream), st)
@@ -200,7 +217,9 @@ def mdp_solve(h: int, b, x, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
 def mdp_solve_batch(hs: Sequence[int], bs, xs, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
     """hs: handles; bs/xs: per-system CUDA float64 tensors (n,) or (nrhs, n)."""
     ns = len(hs)
-    nrhs = [1 if b.dim() == 1 else b.shape[0] for b in bs]
+    if len(bs) != ns or len(xs) != ns:
+        raise ValueError("hs, bs and xs differ in length")
+    nrhs = [_rhs_pair(h, b, x) for h, b, x in zip(hs, bs, xs)]
     harr = (_vp * ns)(*hs)
     barr = (_vp * ns)(*[_dptr(b) for b in bs])
     xarr = (_vp * ns)(*[_dptr(x) for x in xs])
@@ -251,25 +270,38 @@ def mdp_server_register(srv: int, h: int) -> None:
     _check(lib.mdp_server_register(srv, h), "mdp_server_register")
 
 
+# (server, ticket) -> (nrhs, b, x): the tensors stay referenced until the
+# request has been collected, so their memory cannot be reused meanwhile.
+_inflight: dict = {}
+
+
 def mdp_submit(srv: int, h: int, b, x) -> int:
-    nrhs = 1 if b.dim() == 1 else b.shape[0]
+    """Enqueue a solve; b must be written (stream synchronised) already."""
+    nrhs = _rhs_pair(h, b, x)
     t = C.c_uint64()
     _check(lib.mdp_submit(srv, h, _dptr(b), _dptr(x), nrhs, C.byref(t)), "mdp_submit")
+    _inflight[(srv, t.value)] = (nrhs, b, x)
     return t.value
 
 
-def mdp_poll(srv: int, ticket: int, nrhs: int = 1):
+def mdp_poll(srv: int, ticket: int):
     """Return (code, stats list or None while pending)."""
-    st = (mdp_stats * nrhs)()
+    key = (srv, ticket)
+    if key not in _inflight:
+        raise ValueError(f"mdp_poll: unknown or already collected ticket {ticket}")
+    st = (mdp_stats * _inflight[key][0])()
     rc = lib.mdp_poll(srv, ticket, st)
     if rc == MDP_PENDING:
         return rc, None
+    del _inflight[key]
     _check(rc, "mdp_poll", ok=(MDP_OK, MDP_NOT_CONVERGED))
     return rc, [s.as_dict() for s in st]
 
 
 def mdp_server_destroy(srv: int) -> None:
     _check(lib.mdp_server_destroy(srv), "mdp_server_destroy")
+    for key in [k for k in _inflight if k[0] == srv]:
+        del _inflight[key]
 
 
 def mdp_set_allocator(alloc=None, free=None, ctx=None) -> None:

@@ -710,11 +710,45 @@ void Workspace::alloc(int64_t n, int m_, int np, int ntiles, size_t tsz, hipStre
   MDP_HIP(hipStreamSynchronize(s));
 }
 
-Workspace::~Workspace() {
+void Workspace::release() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  ev.clear();
   if (host_ctl) (void)hipHostFree(host_ctl);
   if (host_state) (void)hipHostFree(host_state);
   if (host_norms) (void)hipHostFree(host_norms);
+  host_ctl = nullptr;
+  host_state = nullptr;
+  host_norms = nullptr;
+  for (DevMem *d : {&V, &Z, &w, &rin, &bp, &xp, &Hr, &cs, &sn, &g, &y, &hist, &hprev, &coef, &sums, &partial, &npart,
+                    &state, &ctl, &kmaxp, &tolp, &active, &norms})
+    d->reset();
+}
+
+size_t Workspace::device_bytes() const {
+  size_t b = 0;
+  for (const DevMem *d : {&V, &Z, &w, &rin, &bp, &xp, &Hr, &cs, &sn, &g, &y, &hist, &hprev, &coef, &sums, &partial,
+                          &npart, &state, &ctl, &kmaxp, &tolp, &active, &norms})
+    b += d->bytes();
+  return b;
+}
+
+size_t Solver::workspace_bytes_needed() const {
+  const size_t ld = static_cast<size_t>(padded_ld(n));
+  const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
+  const size_t m = static_cast<size_t>(opt.restart);
+  size_t b = ld * 8 * (m + 1) + ld * tsz * m + ld * 8 + ld * tsz;  // V, Z, w, rin
+  if (!host.identity) b += 2 * ld * 8;
+  return b + (size_t{1} << 20);  // small per-pair arrays
+}
+
+void Solver::ensure_workspace(hipStream_t s) {
+  if (ws.allocated()) return;
+  const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
+  ws.alloc(n, opt.restart, 1, layout.ntiles, tsz, s);
+  if (!host.identity) {
+    ws.bp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+    ws.xp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+  }
 }
 
 void Solver::upload(hipStream_t s) {
@@ -745,6 +779,7 @@ void Solver::upload(hipStream_t s) {
 
 int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
+  ensure_workspace(s);
   const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
   const double *bp = b;
   double *xp = x;
@@ -779,6 +814,7 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
 
 void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
   const int64_t nn = n;
+  ensure_workspace(s);
   switch (op) {
     case MDP_OP_A:
       spmv<kPlain>(A, x, cnull<double>(), cnull<double>(), y, mnull<double>(), nullptr, s);

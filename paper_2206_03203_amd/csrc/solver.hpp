@@ -102,7 +102,10 @@ struct Workspace {
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
   void alloc(int64_t n, int m, int npairs, int ntiles, size_t tsz, hipStream_t s);
-  ~Workspace();
+  void release();           // free everything (alloc may be called again)
+  size_t device_bytes() const;
+  bool allocated() const { return V.get() != nullptr; }
+  ~Workspace() { release(); }
 };
 
 struct PairIO {
@@ -124,6 +127,8 @@ struct Solver {
   double setup_ms = 0.0;
 
   void upload(hipStream_t s);
+  void ensure_workspace(hipStream_t s);  // (re)allocate the Krylov workspace if released
+  size_t workspace_bytes_needed() const;
   int solve(const double *b, double *x, hipStream_t s, mdp_stats *st);
   void apply(int op, const double *x, double *y, hipStream_t s);
 };

@@ -183,3 +183,24 @@ def test_host_only_handle_refuses_solve():
         assert rc == L.MDP_EINVAL
     finally:
         L.mdp_destroy(h)
+
+
+def test_server_lifecycle_without_device_work():
+    """A server starts and stops its slots with no request; bad slot counts
+    and host-only handles are refused (no device call is made)."""
+    import ctypes
+    out = ctypes.c_void_p()
+    assert L.lib.mdp_server_create(0, 0, ctypes.byref(out)) == L.MDP_EINVAL
+    assert L.lib.mdp_server_create(0, 65, ctypes.byref(out)) == L.MDP_EINVAL
+    srv = L.mdp_server_create(1 << 20, 3)
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part)
+    try:
+        assert L.lib.mdp_server_register(srv, h) == L.MDP_EINVAL
+        t = ctypes.c_uint64()
+        assert L.lib.mdp_submit(srv, h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, ctypes.byref(t)) == L.MDP_EINVAL
+        assert L.lib.mdp_poll(srv, 1, None) == L.MDP_EINVAL
+    finally:
+        L.mdp_destroy(h)
+        L.mdp_server_destroy(srv)
