@@ -13,6 +13,20 @@ mixed mode (FP32 preconditioner, FP64 outer loop and coarse solve) on the
 same systems, per-solve latency percentiles, the roofline position of the
 dominant kernel (timed with HIP events inside the library on the launch
 stream) and the CPU oracle timed on a bounded sample on this host.
+
+Two more workloads, each printing its own JSON line:
+
+``--mode batch``: 256 uneven 2D systems (side uniform in 64..512, 1..20
+random fracture segments with log-uniform permeabilities in [1e-4, 1e4]),
+four right-hand sides each (Dirichlet data plus a uniform host source field),
+mixed precision, solved by mdp_solve_batch; one step = the whole batch.
+Beside it: the same pairs solved one system at a time with mdp_solve, mixed
+and plain FP64.
+
+``--mode serve``: a pool of 64 resident systems (32 2D as above, 32 3D with
+side 40..160 and 3..9 random planes), mixed precision, served by
+mdp_submit/mdp_poll under open-loop Poisson arrivals at 0.5, 0.8 and 0.95 of
+the measured saturated throughput; latency is submit to final poll.
 """
 
 from __future__ import annotations
@@ -45,12 +59,20 @@ def parse():
     p.add_argument("--seeds", type=int, default=1, help="log-normal seeds per (K_par, kappa) pair")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-iters", type=int, default=10, help="oracle FGMRES iterations in the CPU sample")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="only run a device-to-device copy of this many MiB (5 times) and exit; used to "
                         "calibrate hardware traffic counters against a copy of known size")
     p.add_argument("--kernel-class", default="auto",
                    help="kernel class for the roofline object (auto = largest total time)")
+    p.add_argument("--mode", choices=["solve", "batch", "serve"], default="solve")
+    p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
+    p.add_argument("--rhs", type=int, default=4, help="batch mode: right-hand sides per system")
+    p.add_argument("--pool", type=int, default=64, help="serve mode: resident systems (half 2D, half 3D)")
+    p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per arrival rate")
+    p.add_argument("--slots", type=int, default=4, help="serve mode: server slots")
+    p.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: workspace memory budget")
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
+                   help="solve time after which the CPU oracle sample stops taking further systems")
     return p.parse_args()
 
 
@@ -74,10 +96,14 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
         return
 
+    if args.mode == "batch":
+        return mode_batch(args)
+    if args.mode == "serve":
+        return mode_serve(args)
+
     import synth
     from paper_2206_03203_amd import _lib as L
     from paper_2206_03203_amd import tpfa
-    from paper_2206_03203_amd import ktimer
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -135,31 +161,16 @@ def main():
     # library around every launch of each kernel class on its launch stream
     # (kept out of the timed passes above: the events lengthen the gaps
     # between kernels, not the kernels).
-    torch.cuda.synchronize()
-    ktimer.begin_all()
-    t0 = time.perf_counter()
-    run("fp64", args.steps)
-    torch.cuda.synchronize()
-    t_ev = time.perf_counter() - t0
-    kt = ktimer.end_all()
-    single = {c: v for c, v in kt.items() if c in ktimer.SINGLE_KERNEL}
-    kclass = max(single, key=lambda c: single[c]["ms"]) if args.kernel_class == "auto" else args.kernel_class
-    k = kt[kclass]
-    achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kclass, "kernel_symbol": ktimer.SINGLE_KERNEL.get(kclass), "launches": k["launches"],
-                "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 2),
-                "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1)),
-                "timed_region": f"the {args.steps} FP64 steps repeated with per-launch HIP events "
-                                f"({t_ev:.3f}s with events vs {fp['seconds']:.3f}s without)"}
-    classes = {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                   "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
-               for c, v in kt.items()}
+    roofline, classes = roofline_pass(lambda: run("fp64", args.steps), args.kernel_class,
+                                      f"the {args.steps} FP64 steps repeated", fp["seconds"])
+    if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1:
+        roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{args.n}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, float(np.mean(fp["iters"])))
+        import synth
+        items = [(synth.regular_3d(n=args.n, k_par=kp, kappa=ka, seed=0), None) for kp, ka in PAIRS]
+        cpu = cpu_full_solves(args, items, "seed 0")
 
     for s in systems:
         for h in s["h"].values():
@@ -200,34 +211,329 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(args, gpu_iters_per_solve):
-    """The FP64 oracle on this host: set up the first system of the workload
-    (untimed), time ``cpu_iters`` FGMRES iterations of its solve, and scale
-    to solves/s with the GPU's mean iteration count per solve."""
-    import synth
-    from oracle import assembly as oa, solve as osv
+def roofline_pass(fn, kernel_class, what, seconds_plain):
+    """Run fn() once more with per-launch HIP events in the library and
+    return (roofline object of the dominant single-symbol kernel class,
+    per-class summary)."""
+    import torch
+    from paper_2206_03203_amd import ktimer
 
-    kp, ka = PAIRS[0]
-    sc = synth.regular_3d(n=args.n, k_par=kp, kappa=ka, seed=0)
-    log("[bench] cpu oracle: assembling and setting up (untimed)")
+    torch.cuda.synchronize()
+    ktimer.begin_all()
     t0 = time.perf_counter()
-    A, b, part = oa.assemble(sc)
-    M = osv.setup(A, part)
-    t1 = time.perf_counter()
-    log(f"[bench] cpu oracle setup {t1 - t0:.1f}s; timing {args.cpu_iters} iterations")
-    opts = osv.SolveOptions(maxiter=args.cpu_iters)
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
+    fn()
+    torch.cuda.synchronize()
+    t_ev = time.perf_counter() - t0
+    kt = ktimer.end_all()
+    single = {c: v for c, v in kt.items() if c in ktimer.SINGLE_KERNEL}
+    kclass = max(single, key=lambda c: single[c]["ms"]) if kernel_class == "auto" else kernel_class
+    k = kt[kclass]
+    achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kclass, "kernel_symbol": ktimer.SINGLE_KERNEL.get(kclass), "launches": k["launches"],
+                "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 2),
+                "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1)),
+                "timed_region": f"{what} with per-launch HIP events "
+                                f"({t_ev:.3f}s with events vs {seconds_plain:.3f}s without)"}
+    classes = {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                   "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+               for c, v in kt.items()}
+    return roofline, classes
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the device kernel sources (kernel bodies and the tile and
+    block constants their launches use)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "types.hpp"):
+        with open(os.path.join(ROOT, "paper_2206_03203_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(symbol: str, workload: str):
+    """HBM bytes per launch of kernel `symbol` on `workload` from the
+    committed hardware-counter summary (FETCH_SIZE and WRITE_SIZE passes,
+    scaled by a copy of known size), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{symbol}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _pct(a, q):
+    return round(1e3 * float(np.percentile(a, q)), 3) if len(a) else None
+
+
+def _setup_pool(scs, sources_per_sys, precisions, stream, tag):
+    """Assemble and set up every scenario; returns a list of dicts holding the
+    handles (one per precision, sharing the host setup), the right-hand sides
+    as a (nrhs, n) device tensor and the sizes."""
+    import torch
+    from paper_2206_03203_amd import _lib as L
+    from paper_2206_03203_amd import tpfa
+
+    out = []
+    t_asm = t_set = 0.0
+    t_last = time.perf_counter()
+    for i, (sc, fs) in enumerate(zip(scs, sources_per_sys)):
+        t0 = time.perf_counter()
+        A, B, part = tpfa.assemble(sc, sources=fs)
+        t1 = time.perf_counter()
+        hs = {}
+        first = None
+        for prec in precisions:
+            o = L.mdp_options_default(precision={"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[prec])
+            hs[prec] = L.mdp_setup(A, part, o, stream) if first is None else L.mdp_setup_like(first, o, stream)
+            first = first or hs[prec]
         t2 = time.perf_counter()
-        res, _, _ = osv.solve(A, b, part, opts, M=M)
-        t3 = time.perf_counter()
-    per_iter = (t3 - t2) / max(res.iters, 1)
-    per_solve = per_iter * gpu_iters_per_solve
-    return {"value": round(1.0 / per_solve, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle FGMRES on {sc.name} ({A.shape[0]} unknowns): first {res.iters} "
-                      f"iterations timed ({t3 - t2:.1f}s), scaled by the GPU's mean "
-                      f"{gpu_iters_per_solve:.1f} iterations per solve; oracle setup "
-                      f"({t1 - t0:.1f}s) not timed",
+        t_asm += t1 - t0
+        t_set += t2 - t1
+        b = torch.tensor(np.ascontiguousarray(B.T), dtype=torch.float64, device="cuda:0")
+        out.append({"sc": sc, "h": hs, "b": b, "n": A.shape[0], "nnz": A.nnz, "fs": fs})
+        if time.perf_counter() - t_last > 10 or i + 1 == len(scs):
+            t_last = time.perf_counter()
+            log(f"[bench] {tag}: set up {i + 1}/{len(scs)} systems")
+    torch.cuda.synchronize()
+    return out, t_asm, t_set
+
+
+def _destroy_pool(pool):
+    from paper_2206_03203_amd import _lib as L
+    for s in pool:
+        for h in s["h"].values():
+            L.mdp_destroy(h)
+
+
+def mode_batch(args):
+    """Uneven 2D batch with several right-hand sides per system."""
+    import torch
+    import synth
+    from paper_2206_03203_amd import _lib as L
+
+    stream = torch.cuda.current_stream()
+    scs = [synth.random_2d(s) for s in range(args.systems)]
+    srcs = [[synth.host_sources(sc, 4 * s + k) for k in range(args.rhs)] for s, sc in enumerate(scs)]
+    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch")
+    pairs = sum(p["b"].shape[0] for p in pool)
+    unknowns = sum(p["n"] * p["b"].shape[0] for p in pool)
+    xs = [torch.zeros_like(p["b"]) for p in pool]
+
+    def batch():
+        rc, st = L.mdp_solve_batch([p["h"]["mixed"] for p in pool], [p["b"] for p in pool], xs, stream)
+        if rc != L.MDP_OK:
+            raise RuntimeError(f"batch did not converge: rc={rc}")
+        return st
+
+    def seq(prec):
+        st_all = []
+        for p, x in zip(pool, xs):
+            rc, st = L.mdp_solve(p["h"][prec], p["b"], x, stream)
+            if rc != L.MDP_OK:
+                raise RuntimeError(f"{p['sc'].name} {prec} did not converge")
+            st_all += st
+        return st_all
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, st
+
+    log(f"[bench] batch: {len(pool)} systems, {pairs} pairs, {unknowns} unknowns in all")
+    t_batch, st_b = timed(batch, args.steps, args.warmup)
+    log(f"[bench] batch: {1e3 * t_batch:.1f} ms per batch")
+    t_seq, st_s = timed(lambda: seq("mixed"), max(1, args.steps // 2), 1)
+    log(f"[bench] sequential mixed: {1e3 * t_seq:.1f} ms per batch")
+    t_seq64, st_64 = timed(lambda: seq("fp64"), max(1, args.steps // 2), 1)
+    log(f"[bench] sequential fp64: {1e3 * t_seq64:.1f} ms per batch")
+    roofline, classes = roofline_pass(batch, args.kernel_class, "one batch repeated", t_batch)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
+    _destroy_pool(pool)
+    its_b = [s["iters"] for s in st_b]
+    its_s = [s["iters"] for s in st_s]
+    line = {
+        "metric": "solves/s to 1e-8 rel residual (batched, mixed precision)",
+        "value": round(pairs / t_batch, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_batch, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
+        "config": {"workload": f"2d-uneven-batch-{args.systems}x{args.rhs}", "systems": len(pool),
+                   "pairs": pairs, "unknowns_total": unknowns,
+                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8},
+        "iters_mean": round(float(np.mean(its_b)), 2), "iters_max": int(max(its_b)),
+        "max_rel_res": max(s["rel_res_true"] for s in st_b),
+        "sequential_mixed": {"value": round(pairs / t_seq, 2), "unit": "solves/s",
+                             "iters_mean": round(float(np.mean(its_s)), 2)},
+        "sequential_fp64": {"value": round(pairs / t_seq64, 2), "unit": "solves/s",
+                            "iters_mean": round(float(np.mean([s["iters"] for s in st_64])), 2)},
+        "speedup_vs_sequential_fp64": round(t_seq64 / t_batch, 3),
+        "speedup_vs_sequential_mixed": round(t_seq / t_batch, 3),
+        "roofline": roofline, "kernel_classes": classes,
+        "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_set, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def mode_serve(args):
+    """Open-loop Poisson arrivals over a pool of resident systems."""
+    import torch
+    import synth
+    from paper_2206_03203_amd import _lib as L
+
+    stream = torch.cuda.current_stream()
+    half = args.pool // 2
+    scs = [synth.random_2d(1000 + s) for s in range(half)]
+    scs += [synth.random_3d(2000 + s) for s in range(args.pool - half)]
+    nb = 4  # right-hand sides per system to draw requests from
+    srcs = [[synth.host_sources(sc, 4 * (3000 + s) + k) for k in range(nb)] for s, sc in enumerate(scs)]
+    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed",), stream, "serve")
+    budget = int(args.budget_gb * (1 << 30))
+    srv = L.mdp_server_create(budget, args.slots)
+    for p in pool:
+        L.mdp_server_register(srv, p["h"]["mixed"])
+    rng = np.random.default_rng(12345)
+
+    def draw(k):
+        ids = rng.integers(0, len(pool), size=k)
+        cols = rng.integers(0, nb, size=k)
+        return list(zip(ids.tolist(), cols.tolist()))
+
+    def serve(reqs, arrivals):
+        """Submit request i at arrivals[i] (seconds from start; None = all at
+        once); return per-request latency (s), makespan (s), iterations."""
+        xs = [torch.empty(pool[i]["n"], dtype=torch.float64, device="cuda:0") for i, _ in reqs]
+        torch.cuda.synchronize()
+        lat = [0.0] * len(reqs)
+        iters = [0] * len(reqs)
+        t_sub = [0.0] * len(reqs)
+        inflight = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        t_log = t0
+        while nxt < len(reqs) or inflight:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and (arrivals is None or arrivals[nxt] <= now):
+                i, c = reqs[nxt]
+                t_sub[nxt] = time.perf_counter()
+                inflight[L.mdp_submit(srv, pool[i]["h"]["mixed"], pool[i]["b"][c], xs[nxt])] = nxt
+                nxt += 1
+            for t in list(inflight):
+                rc, st = L.mdp_poll(srv, t)
+                if rc == L.MDP_PENDING:
+                    continue
+                j = inflight.pop(t)
+                lat[j] = time.perf_counter() - t_sub[j]
+                iters[j] = st[0]["iters"]
+                if rc != L.MDP_OK:
+                    raise RuntimeError(f"request {j} failed: rc={rc}")
+            if time.perf_counter() - t_log > 20:
+                t_log = time.perf_counter()
+                log(f"[bench] serve: {nxt}/{len(reqs)} submitted, {len(inflight)} in flight")
+            time.sleep(0.0002)
+        return lat, time.perf_counter() - t0, iters
+
+    # warm-up and saturated throughput (everything submitted at once)
+    serve(draw(min(2 * len(pool), args.requests)), None)
+    nsat = min(args.requests, 4 * len(pool))
+    lat_sat, mk, it_sat = serve(draw(nsat), None)
+    sat = nsat / mk
+    log(f"[bench] serve: saturated {sat:.1f} solves/s")
+    rates = {}
+    for f in (0.5, 0.8, 0.95):
+        lam = f * sat
+        gaps = rng.exponential(1.0 / lam, size=args.requests)
+        arr = np.cumsum(gaps) - gaps[0]
+        lat, mk, its = serve(draw(args.requests), arr.tolist())
+        rates[str(f)] = {"offered": round(lam, 2), "solves_per_s": round(args.requests / mk, 2),
+                         "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                         "mean_ms": round(1e3 * float(np.mean(lat)), 3),
+                         "iters_mean": round(float(np.mean(its)), 2)}
+        log(f"[bench] serve: rate {f}: {rates[str(f)]}")
+    L.mdp_server_destroy(srv)
+
+    # alone: each pool system solved once by itself (service time without queueing)
+    alone = []
+    for p in pool:
+        x = torch.zeros(p["n"], dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.mdp_solve(p["h"]["mixed"], p["b"][0], x, stream)
+        alone.append(time.perf_counter() - t0)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
+    _destroy_pool(pool)
+    line = {
+        "metric": "served solves/s to 1e-8 rel residual with p50/p99 latency (mixed precision)",
+        "value": round(sat, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": nsat, "warmup": min(2 * len(pool), args.requests),
+        "ms_per_step": round(1e3 / sat, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
+        "config": {"workload": f"serving-pool-{len(pool)}-2d64-512-3d40-160", "slots": args.slots,
+                   "budget_gb": args.budget_gb, "requests_per_rate": args.requests,
+                   "unknowns_range": [min(p["n"] for p in pool), max(p["n"] for p in pool)]},
+        "saturated": {"solves_per_s": round(sat, 2), "p50_ms": _pct(lat_sat, 50), "p99_ms": _pct(lat_sat, 99),
+                      "iters_mean": round(float(np.mean(it_sat)), 2)},
+        "poisson": rates,
+        "alone_service_ms": {"p50": _pct(alone, 50), "p99": _pct(alone, 99),
+                             "sequential_solves_per_s": round(len(alone) / sum(alone), 2)},
+        "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_set, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_full_solves(args, items, which):
+    """The FP64 oracle on this host, one core: full solves of the listed
+    (scenario, source) items in order, each set up untimed, until
+    ``cpu_seconds`` of solve time has been spent; returns solves/s."""
+    from oracle import assembly as oa, solve as osv
+    from threadpoolctl import threadpool_limits
+
+    spent, done, names = 0.0, 0, []
+    for sc, f in items:
+        A, b, part = oa.assemble(sc.with_source(f))
+        M = osv.setup(A, part)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            res, _, _ = osv.solve(A, b, part, osv.SolveOptions(), M=M)
+            spent += time.perf_counter() - t0
+        done += 1
+        names.append(f"{sc.name}({A.shape[0]})")
+        log(f"[bench] cpu oracle: {sc.name} solved in {res.iters} iterations; {spent:.1f}s so far")
+        if spent >= args.cpu_seconds:
+            break
+    return {"value": round(done / spent, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, full solves of the first {done} systems ({which}): "
+                      f"{', '.join(names)}; {spent:.1f}s of solve time, setup not timed",
             "host_cpu_count": os.cpu_count()}
 
 

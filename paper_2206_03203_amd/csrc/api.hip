@@ -25,6 +25,7 @@ AllocHook g_hook;
 struct BatchCache {
   std::vector<const mdp_handle *> handles;
   std::vector<int32_t> nrhs;
+  Workspace shared;  // Krylov workspace sized for the largest chunk (chunks run one after another)
   std::vector<std::unique_ptr<Batch>> chunks;
   std::vector<int> first_pair;  // per chunk
 };
@@ -269,11 +270,23 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
       int64_t tot = 0;
       while (p1 < pairs.size() && (p1 == p0 || tot + pairs[p1]->n <= cap)) tot += pairs[p1++]->n;
       auto bt = std::make_unique<Batch>();
-      bt->build(std::vector<const Solver *>(pairs.begin() + p0, pairs.begin() + p1), s);
+      bt->build(std::vector<const Solver *>(pairs.begin() + p0, pairs.begin() + p1), s, false);
       bc->first_pair.push_back(static_cast<int>(p0));
       bc->chunks.push_back(std::move(bt));
       p0 = p1;
     }
+    int64_t nmax = 0;
+    int pmax = 0, tmax = 0;
+    for (const auto &bt : bc->chunks) {
+      nmax = std::max<int64_t>(nmax, bt->n);
+      pmax = std::max(pmax, bt->npairs);
+      tmax = std::max(tmax, bt->layout.ntiles);
+    }
+    const mdp_options &o = bc->chunks[0]->opt;
+    bc->shared.alloc(nmax, o.restart, pmax, tmax, o.precision == MDP_MIXED ? sizeof(float) : sizeof(double), s);
+    bc->shared.bp.alloc(static_cast<size_t>(bc->shared.ld) * sizeof(double));
+    bc->shared.xp.alloc(static_cast<size_t>(bc->shared.ld) * sizeof(double));
+    for (auto &bt : bc->chunks) bt->wsp = &bc->shared;
     g_batch = std::move(bc);
   }
   int worst = MDP_OK;

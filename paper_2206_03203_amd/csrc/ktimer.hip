@@ -39,6 +39,12 @@ void ktimer_restore_bytes(const KtBytes &s) {
     if (r.on[k]) r.bytes[k] = s.b[k];
 }
 
+void ktimer_add_bytes(int kind, double delta) {
+  Registry &r = reg();
+  std::lock_guard<std::mutex> lk(r.mu);
+  if (r.on[kind]) r.bytes[kind] += delta;
+}
+
 void ktimer_pair(int kind, double bytes, hipEvent_t *start, hipEvent_t *stop) {
   Registry &r = reg();
   std::lock_guard<std::mutex> lk(r.mu);

@@ -30,6 +30,8 @@ struct KtBytes {
 };
 KtBytes ktimer_bytes();
 void ktimer_restore_bytes(const KtBytes &s);
+// Correct the bytes of class `kind` once the work its launches skipped is known.
+void ktimer_add_bytes(int kind, double delta);
 // Returns the event pair to record around the next launch of `kind`.
 void ktimer_pair(int kind, double bytes, hipEvent_t *start, hipEvent_t *stop);
 

@@ -551,8 +551,10 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     // V[:, 0] holds every pair's residual at the cycle start, unnormalised.
     // Steps 0..kmax-1 apply the preconditioner; step kmax (if reached) only
     // finalises the last Hessenberg column.
+    int counted = 0;  // steps whose algorithmic bytes were counted
     for (int j = 0; j <= kmax_all; ++j) {
       const KtBytes kt_before = ktimer_bytes();
+      ++counted;
       T *zj = Z + std::min(j, kmax_all - 1) * ld;
       const double *uj = V + j * ld;
       const T *pin;
@@ -602,6 +604,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
         MDP_HIP(hipEventSynchronize(ws.ev[j - 1]));
         if (ws.host_ctl[j - 1].all_done) {
           ktimer_restore_bytes(kt_before);  // step j was queued after the cycle ended: a no-op
+          --counted;
           break;
         }
       }
@@ -617,6 +620,25 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     });
     spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), nullptr, s);
     pair_norms(ws, L, V, s);  // synchronises: host_state is valid too
+    if (np > 1 && (ktimer_on(kKcArnoldiDot) || ktimer_on(kKcArnoldiAxpy))) {
+      // The Arnoldi passes were counted as if every pair ran every step;
+      // pairs that had finished skip their tiles.  Pair p (k steps in this
+      // cycle) reduces at steps 0..k and updates at steps 0..k-1.
+      double over_dot = 0.0, over_axpy = 0.0;
+      for (int j = 0; j < counted; ++j) {
+        int64_t red = 0, upd = 0;
+        for (int p = 0; p < np; ++p) {
+          if (!active[p]) continue;
+          const int k = ws.host_state[p].k;
+          if (k >= j) red += L.rows[p];
+          if (k > j) upd += L.rows[p];
+        }
+        over_dot += 8.0 * (j + 2) * static_cast<double>(n - red);
+        over_axpy += 8.0 * (j + 4) * static_cast<double>(n - upd);
+      }
+      ktimer_add_bytes(kKcArnoldiDot, -over_dot);
+      ktimer_add_bytes(kKcArnoldiAxpy, -over_axpy);
+    }
     for (int p = 0; p < np; ++p) {
       if (!active[p]) continue;
       const GmresState &gs = ws.host_state[p];
@@ -662,7 +684,9 @@ void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &
   n = n_total;
   std::vector<Tile> tl;
   std::vector<int32_t> off(static_cast<size_t>(npairs) + 1, 0);
+  rows.assign(static_cast<size_t>(npairs), 0);
   for (int p = 0; p < npairs; ++p) {
+    for (const auto &r : ranges[p]) rows[p] += r.second;
     for (const auto &r : ranges[p])
       for (int64_t o = 0; o < r.second; o += kTileElems)
         tl.push_back(Tile{r.first + o, static_cast<int32_t>(std::min<int64_t>(kTileElems, r.second - o)), p});
@@ -674,9 +698,10 @@ void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &
   MDP_HIP(hipStreamSynchronize(s));
 }
 
-void Workspace::alloc(int64_t n, int m_, int np, int ntiles, size_t tsz, hipStream_t s) {
+void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t s) {
   m = m_;
   npairs = np;
+  ntiles = std::max(nt, 1);
   ld = padded_ld(n);
   ldv = m + 2;
   sstride = 2 * (m + 1) + 4;
@@ -694,8 +719,8 @@ void Workspace::alloc(int64_t n, int m_, int np, int ntiles, size_t tsz, hipStre
   Hr.alloc(static_cast<size_t>(np) * (m + 1) * m * sizeof(double));
   coef.alloc(static_cast<size_t>(np) * sizeof(DcgsCoef));
   sums.alloc(static_cast<size_t>(np) * sstride * sizeof(double));
-  partial.alloc(static_cast<size_t>(2 * (m + 1) + 3) * std::max(ntiles, 1) * sizeof(double));
-  npart.alloc(static_cast<size_t>(std::max(ntiles, 1)) * sizeof(double));
+  partial.alloc(static_cast<size_t>(2 * (m + 1) + 3) * ntiles * sizeof(double));
+  npart.alloc(static_cast<size_t>(ntiles) * sizeof(double));
   state.alloc(static_cast<size_t>(np) * sizeof(GmresState));
   ctl.alloc(sizeof(BatchCtl));
   kmaxp.alloc(static_cast<size_t>(np) * sizeof(int));
@@ -857,7 +882,7 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Batches
 
-void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s) {
+void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool alloc_ws) {
   sys = pairs;
   npairs = static_cast<int>(pairs.size());
   opt = pairs[0]->opt;
@@ -925,16 +950,22 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s) {
   else
     pc64 = upload_precond<double>(hsys, po, pg, gpairs, opt.vcycles, s);
   layout.build(ranges, n, s);
-  const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
-  ws.alloc(n, opt.restart, npairs, layout.ntiles, tsz, s);
-  ws.bp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
-  ws.xp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+  if (alloc_ws) {
+    const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
+    ws.alloc(n, opt.restart, npairs, layout.ntiles, tsz, s);
+    ws.bp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+    ws.xp.alloc(static_cast<size_t>(ws.ld) * sizeof(double));
+  }
   MDP_HIP(hipStreamSynchronize(s));
 }
 
 int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
   const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
+  Workspace &W = wsp ? *wsp : ws;
+  if (!W.allocated() || W.ld < n || W.npairs < npairs || W.ntiles < layout.ntiles || W.m != opt.restart ||
+      !W.bp.get())
+    raise(MDP_EINVAL, "batch workspace missing or too small");
   std::vector<const double *> bptr(static_cast<size_t>(npairs));
   std::vector<double *> xptr(static_cast<size_t>(npairs));
   for (int p = 0; p < npairs; ++p) {
@@ -945,7 +976,7 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   MDP_HIP(hipMemcpyAsync(bdev.get(), bptr.data(), sizeof(void *) * npairs, hipMemcpyHostToDevice, s));
   MDP_HIP(hipMemcpyAsync(xdev.get(), xptr.data(), sizeof(void *) * npairs, hipMemcpyHostToDevice, s));
   const int g = grid_for(n);
-  double *bg = dptr<double>(ws.bp), *xg = dptr<double>(ws.xp);
+  double *bg = dptr<double>(W.bp), *xg = dptr<double>(W.xp);
   hipLaunchKernelGGL(gather_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
                      dptr<const int>(gpair), dptr<const int>(gidx), dptr<const double *const>(bdev), bg);
   if (use_x0)
@@ -953,10 +984,10 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
                        dptr<const int>(gpair), dptr<const int>(gidx), dptr<const double *const>(xdev), xg);
   int rc;
   if (opt.precision == MDP_MIXED) {
-    Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt};
+    Problem<float> pb{&A, pc32.get(), &layout, &W, &opt};
     rc = fgmres<float>(pb, bg, xg, use_x0, s, st);
   } else {
-    Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt};
+    Problem<double> pb{&A, pc64.get(), &layout, &W, &opt};
     rc = fgmres<double>(pb, bg, xg, use_x0, s, st);
   }
   hipLaunchKernelGGL(scatter_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),

@@ -82,6 +82,7 @@ struct Layout {
   int ntiles = 0;
   DevMem tiles;     // Tile[ntiles], grouped by pair
   DevMem tile_off;  // npairs + 1
+  std::vector<int64_t> rows;  // unknowns per pair (host)
   // ranges[p] = the (start, length) pieces of pair p in the global vector
   void build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges, int64_t n_total,
              hipStream_t s);
@@ -90,7 +91,8 @@ struct Layout {
 struct Workspace {
   int64_t ld = 0;  // leading dimension of V / Z columns
   int m = 0;       // restart length
-  int npairs = 0;
+  int npairs = 0;   // pairs the per-pair arrays hold
+  int ntiles = 0;   // tiles the per-tile partial sums hold
   int ldv = 0;     // per-pair stride of length-(m+1) arrays
   int sstride = 0; // per-pair stride of the step sums
   DevMem V, Z, w, rin, bp, xp;
@@ -145,8 +147,10 @@ struct Batch {
   std::unique_ptr<Precond<double>> pc64;
   std::unique_ptr<Precond<float>> pc32;
   Layout layout;
-  Workspace ws;
-  void build(const std::vector<const Solver *> &pairs, hipStream_t s);
+  Workspace ws;              // own workspace (left empty when `wsp` is set)
+  Workspace *wsp = nullptr;  // shared workspace of at least this batch's sizes
+  // alloc_ws = false: leave the workspace to the caller (set wsp before solve)
+  void build(const std::vector<const Solver *> &pairs, hipStream_t s, bool alloc_ws = true);
   int solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st);
 };
 

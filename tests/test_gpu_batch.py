@@ -81,3 +81,43 @@ def test_batch_rejects_mixed_precisions():
     finally:
         s1.close()
         s2.close()
+
+
+def test_batch_split_into_chunks(monkeypatch):
+    """A batch larger than the chunk bound is solved as several block-diagonal
+    chunks, one after another, on one shared workspace sized for the largest;
+    every pair still converges and agrees with the one-chunk batch."""
+    scs = _systems()
+    solvers, bs = [], []
+    for i, sc in enumerate(scs):
+        fs = [None, synth.host_sources(sc, 500 + i)]
+        A, B, part = tpfa.assemble(sc, sources=fs)
+        solvers.append(Solver(A, part, precision="mixed"))
+        bs.append(dev(B.T.copy()))
+    hs = [s.handle for s in solvers]
+    try:
+        one = [torch.zeros_like(b) for b in bs]
+        rc, st1 = L.mdp_solve_batch(hs, bs, one)
+        assert rc == L.MDP_OK
+        nmax = max(s.n for s in solvers)
+        for cap in (nmax, 3 * nmax):  # one pair per chunk at most / a few pairs per chunk
+            monkeypatch.setenv("MDP_BATCH_MAX_UNKNOWNS", str(cap))
+            xs = [torch.zeros_like(b) for b in bs]
+            rc, st = L.mdp_solve_batch(hs, bs, xs)
+            say(f"[batch-chunks] cap={cap} iters={[s['iters'] for s in st]}")
+            assert rc == L.MDP_OK
+            for a, b in zip(st, st1):
+                assert a["converged"] == 1 and a["rel_res_true"] <= 1e-8
+                assert abs(a["iters"] - b["iters"]) <= 1
+            for a, b in zip(xs, one):
+                assert relerr(host(a), host(b)) <= 1e-6
+        # a smaller batch afterwards rebuilds the plan
+        monkeypatch.delenv("MDP_BATCH_MAX_UNKNOWNS")
+        xs = [torch.zeros_like(b) for b in bs[:2]]
+        rc, st = L.mdp_solve_batch(hs[:2], bs[:2], xs)
+        assert rc == L.MDP_OK
+        for a, b in zip(xs, one[:2]):
+            assert relerr(host(a), host(b)) <= 1e-6
+    finally:
+        for s in solvers:
+            s.close()
