@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--kernel-class", default="auto",
                    help="kernel class for the roofline object (auto = largest total time)")
     p.add_argument("--mode", choices=["solve", "batch", "serve"], default="solve")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the fixed rule for sparse formats instead of timing candidates at setup")
     p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
     p.add_argument("--rhs", type=int, default=4, help="batch mode: right-hand sides per system")
     p.add_argument("--pool", type=int, default=64, help="serve mode: resident systems (half 2D, half 3D)")
@@ -115,8 +117,9 @@ def main():
             t0 = time.perf_counter()
             A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
-            o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles)
-            o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles)
+            fl = L.MDP_NO_AUTOTUNE if args.no_autotune else 0
+            o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl)
+            o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl)
             hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
@@ -194,7 +197,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
-                   "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles},
+                   "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
+                   "autotune": not args.no_autotune},
         "p50_ms": pct(fp["lat"], 50),
         "p99_ms": pct(fp["lat"], 99),
         "iters": sorted(set(fp["iters"])),
@@ -279,7 +283,7 @@ def _pct(a, q):
     return round(1e3 * float(np.percentile(a, q)), 3) if len(a) else None
 
 
-def _setup_pool(scs, sources_per_sys, precisions, stream, tag):
+def _setup_pool(scs, sources_per_sys, precisions, stream, tag, flags=0):
     """Assemble and set up every scenario; returns a list of dicts holding the
     handles (one per precision, sharing the host setup), the right-hand sides
     as a (nrhs, n) device tensor and the sizes."""
@@ -297,7 +301,7 @@ def _setup_pool(scs, sources_per_sys, precisions, stream, tag):
         hs = {}
         first = None
         for prec in precisions:
-            o = L.mdp_options_default(precision={"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[prec])
+            o = L.mdp_options_default(precision={"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[prec], flags=flags)
             hs[prec] = L.mdp_setup(A, part, o, stream) if first is None else L.mdp_setup_like(first, o, stream)
             first = first or hs[prec]
         t2 = time.perf_counter()
@@ -328,7 +332,8 @@ def mode_batch(args):
     stream = torch.cuda.current_stream()
     scs = [synth.random_2d(s) for s in range(args.systems)]
     srcs = [[synth.host_sources(sc, 4 * s + k) for k in range(args.rhs)] for s, sc in enumerate(scs)]
-    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch")
+    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch",
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
     pairs = sum(p["b"].shape[0] for p in pool)
     unknowns = sum(p["n"] * p["b"].shape[0] for p in pool)
     xs = [torch.zeros_like(p["b"]) for p in pool]
@@ -411,7 +416,8 @@ def mode_serve(args):
     scs += [synth.random_3d(2000 + s) for s in range(args.pool - half)]
     nb = 4  # right-hand sides per system to draw requests from
     srcs = [[synth.host_sources(sc, 4 * (3000 + s) + k) for k in range(nb)] for s, sc in enumerate(scs)]
-    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed",), stream, "serve")
+    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed",), stream, "serve",
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
     budget = int(args.budget_gb * (1 << 30))
     srv = L.mdp_server_create(budget, args.slots)
     for p in pool:
@@ -531,9 +537,10 @@ def cpu_full_solves(args, items, which):
         log(f"[bench] cpu oracle: {sc.name} solved in {res.iters} iterations; {spent:.1f}s so far")
         if spent >= args.cpu_seconds:
             break
+    shown = ", ".join(names[:4]) + (f", ... ({done - 4} more)" if done > 4 else "")
     return {"value": round(done / spent, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle, full solves of the first {done} systems ({which}): "
-                      f"{', '.join(names)}; {spent:.1f}s of solve time, setup not timed",
+                      f"{shown}; {spent:.1f}s of solve time, setup not timed",
             "host_cpu_count": os.cpu_count()}
 
 

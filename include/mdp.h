@@ -55,6 +55,13 @@ extern "C" {
 #define MDP_HOST_ONLY 2u   /* mdp_setup: build the hierarchy on the host only
                               (no device upload); for inspection on machines
                               without a GPU.  Solve calls then return EINVAL. */
+#define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
+                              device format instead of timing the candidates
+                              (CSR with 2..64 lanes per row, one thread per
+                              row, sliced ELL) on the device and keeping the
+                              fastest.  The format changes only the order of
+                              the additions in each row; equal matrices get
+                              equal formats within a process. */
 
 /* ---- operators for mdp_apply ---------------------------------------------- */
 #define MDP_OP_A 0    /* y = A x, the full system matrix (FP64)                     */
@@ -93,7 +100,7 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length m (64, at most 64)                  */
   int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
-  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY                                */
+  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE              */
 } mdp_options;
 
 typedef struct {

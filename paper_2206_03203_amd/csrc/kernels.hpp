@@ -145,19 +145,21 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
   const int o0 = soff[slice], o1 = soff[slice + 1];
   const int row = slice * 64 + lane;
   Acc sum = 0;
-  int o = o0 + lane;
-  for (; o + (kSellBatch - 1) * 64 < o1; o += kSellBatch * 64) {
+  // kSellBatch entries per step, the last step predicated (past the slice
+  // width: value 0 and this lane's first column), so that all index and
+  // value loads of a short row are in flight together
+  for (int o = o0 + lane; o < o1; o += kSellBatch * 64) {
     int c[kSellBatch];
     Acc v[kSellBatch];
 #pragma unroll
     for (int k = 0; k < kSellBatch; ++k) {
-      c[k] = col[o + k * 64];
-      v[k] = static_cast<Acc>(val[o + k * 64]);
+      const int q = o + k * 64;
+      c[k] = q < o1 ? col[q] : col[o];
+      v[k] = q < o1 ? static_cast<Acc>(val[q]) : Acc(0);
     }
 #pragma unroll
     for (int k = 0; k < kSellBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
   }
-  for (; o < o1; o += 64) sum += static_cast<Acc>(val[o]) * spmv_gather<MODE, Acc>(col[o], x, b, dinv);
   if (row < nr) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
 }
 

@@ -19,8 +19,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <tuple>
 #include <type_traits>
 
@@ -75,37 +79,61 @@ struct Keep {
   }
 };
 
-// Upload a host CSR in the device format that suits it: sliced ELL when the
-// 64-row slices carry little padding, one thread per row for other short
-// rows, LPR lanes per row otherwise.
-template <typename T>
-void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
-  d.nr = h.nr;
-  d.nc = h.nc;
-  d.nnz = h.nnz();
-  d.lpr = choose_lpr(d.nnz, d.nr);
-  const int32_t ns = (h.nr + 63) / 64;
-  int64_t padded = 0;
+// Device formats of a sparse matrix, and the setup-time autotuner that picks
+// one per matrix by timing the candidates on the device.
+struct FormatChoice {
+  bool sell = false;
+  bool scalar = false;
+  int lpr = 8;
+};
+
+struct SliceStats {
+  int64_t padded = 0;  // entries of the sliced-ELL layout (64-row slices)
   int32_t maxlen = 0;
+};
+
+SliceStats slice_stats(const HCsr &h) {
+  SliceStats st;
+  const int32_t ns = (h.nr + 63) / 64;
   for (int32_t sl = 0; sl < ns; ++sl) {
     int32_t w = 0;
     for (int32_t r = sl * 64; r < std::min(h.nr, sl * 64 + 64); ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
-    padded += 64 * static_cast<int64_t>(w);
-    maxlen = std::max(maxlen, w);
+    st.padded += 64 * static_cast<int64_t>(w);
+    st.maxlen = std::max(st.maxlen, w);
   }
-  const double avg = h.nr > 0 ? static_cast<double>(d.nnz) / h.nr : 0.0;
-  d.sell = h.nr > 0 && maxlen <= 64 && padded <= 23 * std::max<int64_t>(d.nnz, 1) / 20 &&
-           padded < std::numeric_limits<int32_t>::max();
-  d.scalar = !d.sell && avg <= 12.0;
-  if (!d.sell) {
-    upload_vec(d.ptr, h.ptr, s);
-    upload_vec(d.col, h.col, s);
-    upload_vec(d.val, keep.put(std::vector<T>(h.val.begin(), h.val.end())), s);
-    return;
-  }
+  return st;
+}
+
+bool sell_possible(const SliceStats &st, int64_t nnz, double max_padding) {
+  return st.maxlen <= 64 && static_cast<double>(st.padded) <= max_padding * static_cast<double>(std::max<int64_t>(nnz, 1)) &&
+         st.padded < std::numeric_limits<int32_t>::max();
+}
+
+// Fixed rule (also the autotuner's fallback): sliced ELL when the slices
+// carry at most 15% padding, one thread per row for other short rows, else
+// enough lanes per row for kCsrBatch entries each.
+FormatChoice heuristic_format(const HCsr &h, const SliceStats &st) {
+  FormatChoice f;
+  const int64_t nnz = h.nnz();
+  f.lpr = choose_lpr(nnz, h.nr);
+  f.sell = h.nr > 0 && sell_possible(st, nnz, 1.15);
+  f.scalar = !f.sell && (h.nr > 0 ? static_cast<double>(nnz) / h.nr : 0.0) <= 12.0;
+  return f;
+}
+
+template <typename T>
+void upload_csr_arrays(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
+  upload_vec(d.ptr, h.ptr, s);
+  upload_vec(d.col, h.col, s);
+  upload_vec(d.val, keep.put(std::vector<T>(h.val.begin(), h.val.end())), s);
+}
+
+template <typename T>
+void upload_sell_arrays(const HCsr &h, DCsr<T> &d, const SliceStats &st, hipStream_t s, Keep &keep) {
+  const int32_t ns = (h.nr + 63) / 64;
   d.nslices = ns;
-  std::vector<int32_t> soff(static_cast<size_t>(ns) + 1, 0), col(static_cast<size_t>(padded));
-  std::vector<T> val(static_cast<size_t>(padded), T(0));
+  std::vector<int32_t> soff(static_cast<size_t>(ns) + 1, 0), col(static_cast<size_t>(st.padded));
+  std::vector<T> val(static_cast<size_t>(st.padded), T(0));
   int64_t o = 0;
   for (int32_t sl = 0; sl < ns; ++sl) {
     const int32_t r0 = sl * 64, r1 = std::min(h.nr, r0 + 64);
@@ -133,6 +161,54 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   upload_vec(d.ptr, keep.put(std::move(soff)), s);
   upload_vec(d.col, keep.put(std::move(col)), s);
   upload_vec(d.val, keep.put(std::move(val)), s);
+}
+
+// Autotuning is on while an AutotuneScope with on = true is alive on this
+// thread (the setup paths open one from their options).
+thread_local bool t_autotune = false;
+
+struct AutotuneScope {
+  bool saved;
+  explicit AutotuneScope(bool on) : saved(t_autotune) { t_autotune = on; }
+  ~AutotuneScope() { t_autotune = saved; }
+};
+
+// Choices already made in this process, by matrix signature, so that equal
+// matrices get the same format (and so the same rounding) every time.
+struct TuneKey {
+  int vsize;
+  int32_t nr, nc, maxlen;
+  int64_t nnz, padded;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(vsize, nr, nc, maxlen, nnz, padded) < std::tie(o.vsize, o.nr, o.nc, o.maxlen, o.nnz, o.padded);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, FormatChoice> g_tune;
+
+template <typename T>
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s, Keep &keep);
+
+// Upload a host CSR in the device format that suits it.  With autotuning
+// on, matrices of at least kTuneMinNnz entries are timed on the device in
+// every candidate format and the fastest is kept.
+constexpr int64_t kTuneMinNnz = 1 << 15;
+
+template <typename T>
+void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
+  d.nr = h.nr;
+  d.nc = h.nc;
+  d.nnz = h.nnz();
+  const SliceStats st = slice_stats(h);
+  FormatChoice f = heuristic_format(h, st);
+  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, s, keep);
+  d.sell = f.sell;
+  d.scalar = f.scalar;
+  d.lpr = f.lpr;
+  if (f.sell)
+    upload_sell_arrays(h, d, st, s, keep);
+  else
+    upload_csr_arrays(h, d, s, keep);
 }
 
 using Piece = std::tuple<const HCsr *, int32_t, int32_t>;  // matrix, row offset, column offset
@@ -322,6 +398,7 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     return;
   }
   switch (A.lpr) {
+    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
     case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
@@ -337,6 +414,79 @@ const T *cnull() {
 template <typename T>
 T *mnull() {
   return static_cast<T *>(nullptr);
+}
+
+// Time every candidate format of one matrix (kTuneReps residual products
+// each, after two untimed ones) and return the fastest.  Candidates: CSR
+// with 2..64 lanes per row, CSR with one thread per row, and sliced ELL when
+// its padding stays within 2x.
+constexpr int kTuneReps = 10;
+
+template <typename T>
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s, Keep &keep) {
+  const TuneKey key{static_cast<int>(sizeof(T)), h.nr, h.nc, st.maxlen, h.nnz(), st.padded};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  DCsr<T> csr;
+  csr.nr = h.nr;
+  csr.nc = h.nc;
+  csr.nnz = h.nnz();
+  upload_csr_arrays(h, csr, s, keep);
+  DCsr<T> sell;
+  const bool has_sell = sell_possible(st, h.nnz(), 2.0);
+  if (has_sell) {
+    sell.nr = h.nr;
+    sell.nc = h.nc;
+    sell.nnz = h.nnz();
+    sell.sell = true;
+    upload_sell_arrays(h, sell, st, s, keep);
+  }
+  DevMem xv(sizeof(T) * std::max<int32_t>(h.nc, 1)), bv(sizeof(T) * h.nr), yv(sizeof(T) * h.nr);
+  MDP_HIP(hipMemsetAsync(xv.get(), 0, xv.bytes(), s));
+  MDP_HIP(hipMemsetAsync(bv.get(), 0, bv.bytes(), s));
+  const T *x = dptr<const T>(xv), *b = dptr<const T>(bv);
+  T *y = dptr<T>(yv);
+  hipEvent_t e0, e1;
+  MDP_HIP(hipEventCreate(&e0));
+  MDP_HIP(hipEventCreate(&e1));
+  auto time_one = [&](const DCsr<T> &d) {
+    for (int i = 0; i < 2; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), nullptr, s);
+    MDP_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < kTuneReps; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), nullptr, s);
+    MDP_HIP(hipEventRecord(e1, s));
+    MDP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  FormatChoice best = heuristic_format(h, st);
+  float tbest = std::numeric_limits<float>::max();
+  std::vector<FormatChoice> cand;
+  for (int l : {2, 4, 8, 16, 32, 64}) cand.push_back(FormatChoice{false, false, l});
+  cand.push_back(FormatChoice{false, true, 4});
+  for (const FormatChoice &c : cand) {
+    csr.scalar = c.scalar;
+    csr.lpr = c.lpr;
+    const float t = time_one(csr);
+    if (t < tbest) tbest = t, best = c;
+  }
+  if (has_sell) {
+    const float t = time_one(sell);
+    if (t < tbest) tbest = t, best = FormatChoice{true, false, 8};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  MDP_HIP(hipStreamSynchronize(s));
+  if (std::getenv("MDP_SETUP_VERBOSE"))
+    std::fprintf(stderr, "[mdp] autotune %s n=%d nnz=%lld: %s lpr=%d (%.2f us)\n", sizeof(T) == 8 ? "f64" : "f32",
+                 h.nr, static_cast<long long>(h.nnz()), best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
+                 best.lpr, 1e3 * tbest / kTuneReps);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.emplace(key, best);
+  return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +927,7 @@ void Solver::ensure_workspace(hipStream_t s) {
 }
 
 void Solver::upload(hipStream_t s) {
+  const AutotuneScope tune((opt.flags & MDP_NO_AUTOTUNE) == 0);
   n = host.n;
   n_o = host.n_o;
   n_g = host.n_g;
@@ -883,6 +1034,7 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
 // Batches
 
 void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool alloc_ws) {
+  const AutotuneScope tune(!pairs.empty() && (pairs[0]->opt.flags & MDP_NO_AUTOTUNE) == 0);
   sys = pairs;
   npairs = static_cast<int>(pairs.size());
   opt = pairs[0]->opt;

@@ -204,3 +204,12 @@ def test_server_lifecycle_without_device_work():
     finally:
         L.mdp_destroy(h)
         L.mdp_server_destroy(srv)
+
+
+def test_unknown_flag_bits_rejected():
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | 64)
+    with pytest.raises(L.MdpError) as e:
+        L.mdp_setup(A, part, o)
+    assert e.value.code == L.MDP_EINVAL
