@@ -57,8 +57,9 @@ extern "C" {
                               without a GPU.  Solve calls then return EINVAL. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
-                              (CSR with 2..64 lanes per row, one thread per
-                              row, sliced ELL) on the device and keeping the
+                              (CSR with 2..64 lanes per row and 4 or 8
+                              entries in flight per lane, one thread per row,
+                              sliced ELL) on the device and keeping the
                               fastest.  The format changes only the order of
                               the additions in each row; equal matrices get
                               equal formats within a process. */

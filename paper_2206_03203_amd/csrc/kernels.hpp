@@ -90,11 +90,11 @@ __device__ __forceinline__ Acc spmv_gather(int c, const TX *__restrict__ x, cons
     return static_cast<Acc>(x[c]);
 }
 
-// CSR-vector kernel for long rows: LPR lanes per row, each lane keeps
-// kCsrBatch entries in flight (indices and values loaded before the gathers).
-constexpr int kCsrBatch = 4;
+// CSR-vector kernel for long rows: LPR lanes per row, each lane keeps BATCH
+// entries in flight (indices and values loaded before the gathers).
+constexpr int kCsrBatch = 4;  // the fixed rule's batch
 
-template <int LPR, int MODE, typename TA, typename TX, typename TY>
+template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void spmv_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
@@ -107,18 +107,18 @@ __global__ __launch_bounds__(kThreads) void spmv_kernel(
   if (row >= nr) return;  // whole LPR groups leave together
   const int s = ptr[row], e = ptr[row + 1];
   Acc sum = 0;
-  for (int p0 = s + lane; p0 < e; p0 += kCsrBatch * LPR) {
-    int c[kCsrBatch];
-    Acc v[kCsrBatch];
+  for (int p0 = s + lane; p0 < e; p0 += BATCH * LPR) {
+    int c[BATCH];
+    Acc v[BATCH];
 #pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k) {
+    for (int k = 0; k < BATCH; ++k) {
       const int p = p0 + k * LPR;
       // past the row end: value 0 and a column of this row (always in range)
       c[k] = p < e ? col[p] : col[s];
       v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
     }
 #pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
+    for (int k = 0; k < BATCH; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
   }
   sum = group_sum<LPR>(sum);
   if (lane == 0) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
@@ -161,6 +161,41 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
     for (int k = 0; k < kSellBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
   }
   if (row < nr) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+}
+
+// Diagonal storage for stencil matrices: entry (i, i + off[d]) is stored at
+// val[d * nr + i] (zero where the matrix has no entry), with the offsets
+// ascending, so each row is summed in column order as in the other formats.
+// One thread per row; no column indices are read and the gathers of a
+// wavefront are contiguous.
+constexpr int kMaxDiag = 16;
+constexpr int kDiaBatch = 8;
+
+template <int MODE, typename TA, typename TX, typename TY>
+__global__ __launch_bounds__(kThreads) void dia_kernel(
+    int nr, int nc, int ndiag, const int *__restrict__ off, const TA *__restrict__ val,
+    const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TX>::type;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk * kThreads + static_cast<int>(threadIdx.x);
+  if (row >= nr) return;
+  Acc sum = 0;
+  for (int d0 = 0; d0 < ndiag; d0 += kDiaBatch) {
+    Acc v[kDiaBatch], xv[kDiaBatch];
+#pragma unroll
+    for (int k = 0; k < kDiaBatch; ++k) {
+      const int d = d0 + k;
+      const int c = d < ndiag ? row + off[d] : row;
+      const bool in = d < ndiag && c >= 0 && c < nc;
+      v[k] = in ? static_cast<Acc>(val[static_cast<int64_t>(d) * nr + row]) : Acc(0);
+      xv[k] = in ? spmv_gather<MODE, Acc>(c, x, b, dinv) : Acc(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kDiaBatch; ++k) sum += v[k] * xv[k];
+  }
+  spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
 }
 
 // CSR with one thread per row, for short rows of uneven length (where slices

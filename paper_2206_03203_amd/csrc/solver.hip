@@ -85,6 +85,8 @@ struct FormatChoice {
   bool sell = false;
   bool scalar = false;
   int lpr = 8;
+  int batch = kCsrBatch;  // CSR-vector entries in flight per lane (4 or 8)
+  bool dia = false;
 };
 
 struct SliceStats {
@@ -109,11 +111,33 @@ bool sell_possible(const SliceStats &st, int64_t nnz, double max_padding) {
          st.padded < std::numeric_limits<int32_t>::max();
 }
 
-// Fixed rule (also the autotuner's fallback): sliced ELL when the slices
-// carry at most 15% padding, one thread per row for other short rows, else
-// enough lanes per row for kCsrBatch entries each.
-FormatChoice heuristic_format(const HCsr &h, const SliceStats &st) {
+// The distinct diagonal offsets (column - row) of a matrix, ascending, when
+// there are at most kMaxDiag of them and the diagonal layout pads the
+// entries by at most 20%; empty otherwise.
+std::vector<int32_t> dia_offsets(const HCsr &h) {
+  std::vector<int32_t> offs;
+  for (int32_t i = 0; i < h.nr; ++i)
+    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+      const int32_t d = h.col[k] - i;
+      const auto it = std::lower_bound(offs.begin(), offs.end(), d);
+      if (it != offs.end() && *it == d) continue;
+      if (static_cast<int>(offs.size()) == kMaxDiag) return {};
+      offs.insert(it, d);
+    }
+  if (static_cast<double>(offs.size()) * h.nr > 1.2 * static_cast<double>(std::max<int64_t>(h.nnz(), 1))) return {};
+  return offs;
+}
+
+// Fixed rule (also the autotuner's fallback): diagonal storage for stencil
+// matrices, sliced ELL when the slices carry at most 15% padding, one thread
+// per row for other short rows, else enough lanes per row for kCsrBatch
+// entries each.
+FormatChoice heuristic_format(const HCsr &h, const SliceStats &st, bool dia_ok) {
   FormatChoice f;
+  if (dia_ok) {
+    f.dia = true;
+    return f;
+  }
   const int64_t nnz = h.nnz();
   f.lpr = choose_lpr(nnz, h.nr);
   f.sell = h.nr > 0 && sell_possible(st, nnz, 1.15);
@@ -163,6 +187,19 @@ void upload_sell_arrays(const HCsr &h, DCsr<T> &d, const SliceStats &st, hipStre
   upload_vec(d.val, keep.put(std::move(val)), s);
 }
 
+template <typename T>
+void upload_dia_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &offs, hipStream_t s, Keep &keep) {
+  d.ndiag = static_cast<int32_t>(offs.size());
+  std::vector<T> val(offs.size() * static_cast<size_t>(h.nr), T(0));
+  for (int32_t i = 0; i < h.nr; ++i)
+    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+      const size_t di = std::lower_bound(offs.begin(), offs.end(), h.col[k] - i) - offs.begin();
+      val[di * h.nr + i] = static_cast<T>(h.val[k]);
+    }
+  upload_vec(d.ptr, keep.put(std::vector<int32_t>(offs)), s);
+  upload_vec(d.val, keep.put(std::move(val)), s);
+}
+
 // Autotuning is on while an AutotuneScope with on = true is alive on this
 // thread (the setup paths open one from their options).
 thread_local bool t_autotune = false;
@@ -187,7 +224,8 @@ std::mutex g_tune_mu;
 std::map<TuneKey, FormatChoice> g_tune;
 
 template <typename T>
-FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s, Keep &keep);
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs, hipStream_t s,
+                             Keep &keep);
 
 // Upload a host CSR in the device format that suits it.  With autotuning
 // on, matrices of at least kTuneMinNnz entries are timed on the device in
@@ -200,12 +238,17 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   d.nc = h.nc;
   d.nnz = h.nnz();
   const SliceStats st = slice_stats(h);
-  FormatChoice f = heuristic_format(h, st);
-  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, s, keep);
+  const std::vector<int32_t> offs = h.nr > 0 ? dia_offsets(h) : std::vector<int32_t>{};
+  FormatChoice f = heuristic_format(h, st, !offs.empty());
+  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, offs, s, keep);
+  d.dia = f.dia;
   d.sell = f.sell;
   d.scalar = f.scalar;
   d.lpr = f.lpr;
-  if (f.sell)
+  d.batch = f.batch;
+  if (f.dia)
+    upload_dia_arrays(h, d, offs, s, keep);
+  else if (f.sell)
     upload_sell_arrays(h, d, st, s, keep);
   else
     upload_csr_arrays(h, d, s, keep);
@@ -355,7 +398,10 @@ int grid_for(int64_t n) {
 // row pointers once, each vector entry read or written once.
 template <int MODE, typename TA, typename TX, typename TY>
 double spmv_bytes(const DCsr<TA> &A) {
-  double b = (sizeof(TA) + 4.0) * A.nnz + 4.0 * (A.nr + 1.0);
+  // every stored value and index once: diagonal storage keeps ndiag values
+  // per row (zeros included) and no indices
+  double b = A.dia ? static_cast<double>(sizeof(TA)) * A.ndiag * A.nr + 4.0 * A.ndiag
+                   : (sizeof(TA) + 4.0) * A.nnz + 4.0 * (A.nr + 1.0);
   const double sx = sizeof(TX), sy = sizeof(TY);
   if (MODE == kPlain) b += sx * A.nc + sy * A.nr;
   if (MODE == kResid) b += sx * A.nc + 2 * sy * A.nr;
@@ -366,13 +412,13 @@ double spmv_bytes(const DCsr<TA> &A) {
   return b;
 }
 
-template <int LPR, int MODE, typename TA, typename TX, typename TY>
+template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
 void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2,
                  const int *gate, hipStream_t s, int kind) {
   const int64_t rows_per_blk = kThreads / LPR;
   const int blocks = static_cast<int>((A.nr + rows_per_blk - 1) / rows_per_blk);
   timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
-    hipLaunchKernelGGL((spmv_kernel<LPR, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
+    hipLaunchKernelGGL((spmv_kernel<LPR, BATCH, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
                        A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
   });
 }
@@ -381,6 +427,14 @@ template <int MODE, typename TA, typename TX, typename TY>
 void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, const int *gate,
           hipStream_t s, int kind = kKcOther) {
   if (A.nr == 0) return;
+  if (A.dia) {
+    const int blocks = (A.nr + kThreads - 1) / kThreads;
+    timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+      hipLaunchKernelGGL((dia_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc, A.ndiag,
+                         A.p(), A.v(), x, b, dinv, y, y2, gate);
+    });
+    return;
+  }
   if (A.sell) {
     const int blocks = (A.nslices + (kThreads / 64) - 1) / (kThreads / 64);
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
@@ -397,13 +451,23 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     });
     return;
   }
+  const bool b8 = A.batch == 8;
   switch (A.lpr) {
-    case 2: spmv_launch<2, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
-    case 4: spmv_launch<4, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
-    case 8: spmv_launch<8, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
-    case 16: spmv_launch<16, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
-    case 32: spmv_launch<32, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
-    default: spmv_launch<64, MODE>(A, x, b, dinv, y, y2, gate, s, kind); break;
+#define MDP_LPR_CASE(L)                                                  \
+  case L:                                                                \
+    if (b8)                                                              \
+      spmv_launch<L, 8, MODE>(A, x, b, dinv, y, y2, gate, s, kind);      \
+    else                                                                 \
+      spmv_launch<L, kCsrBatch, MODE>(A, x, b, dinv, y, y2, gate, s, kind); \
+    break;
+    MDP_LPR_CASE(2)
+    MDP_LPR_CASE(4)
+    MDP_LPR_CASE(8)
+    MDP_LPR_CASE(16)
+    MDP_LPR_CASE(32)
+    MDP_LPR_CASE(64)
+#undef MDP_LPR_CASE
+    default: raise(MDP_EINVAL, "unsupported lanes per row");
   }
 }
 
@@ -417,13 +481,14 @@ T *mnull() {
 }
 
 // Time every candidate format of one matrix (kTuneReps residual products
-// each, after two untimed ones) and return the fastest.  Candidates: CSR
-// with 2..64 lanes per row, CSR with one thread per row, and sliced ELL when
-// its padding stays within 2x.
+// each, after two untimed ones) and return the fastest.  Candidates: CSR with 2..64 lanes per row and 4 or 8
+// entries in flight per lane, CSR with one thread per row, and sliced ELL
+// when its padding stays within 2x.
 constexpr int kTuneReps = 10;
 
 template <typename T>
-FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s, Keep &keep) {
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs, hipStream_t s,
+                             Keep &keep) {
   const TuneKey key{static_cast<int>(sizeof(T)), h.nr, h.nc, st.maxlen, h.nnz(), st.padded};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -444,6 +509,14 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s,
     sell.sell = true;
     upload_sell_arrays(h, sell, st, s, keep);
   }
+  DCsr<T> dia;
+  if (!offs.empty()) {
+    dia.nr = h.nr;
+    dia.nc = h.nc;
+    dia.nnz = h.nnz();
+    dia.dia = true;
+    upload_dia_arrays(h, dia, offs, s, keep);
+  }
   DevMem xv(sizeof(T) * std::max<int32_t>(h.nc, 1)), bv(sizeof(T) * h.nr), yv(sizeof(T) * h.nr);
   MDP_HIP(hipMemsetAsync(xv.get(), 0, xv.bytes(), s));
   MDP_HIP(hipMemsetAsync(bv.get(), 0, bv.bytes(), s));
@@ -462,28 +535,39 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, hipStream_t s,
     MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
     return ms;
   };
-  FormatChoice best = heuristic_format(h, st);
+  FormatChoice best = heuristic_format(h, st, !offs.empty());
   float tbest = std::numeric_limits<float>::max();
+  // CSR-vector shapes whose lanes are neither mostly idle (more lanes than
+  // twice the average row) nor too few (a row needing more than four steps)
+  const double avg = static_cast<double>(h.nnz()) / h.nr;
   std::vector<FormatChoice> cand;
-  for (int l : {2, 4, 8, 16, 32, 64}) cand.push_back(FormatChoice{false, false, l});
-  cand.push_back(FormatChoice{false, true, 4});
+  for (int l : {2, 4, 8, 16, 32, 64})
+    for (int bt : {kCsrBatch, 8})
+      if (l <= std::max(2.0, 2.0 * avg) && 4.0 * l * bt >= avg) cand.push_back(FormatChoice{false, false, l, bt});
+  cand.push_back(FormatChoice{false, true, 4, kCsrBatch});
   for (const FormatChoice &c : cand) {
     csr.scalar = c.scalar;
     csr.lpr = c.lpr;
+    csr.batch = c.batch;
     const float t = time_one(csr);
     if (t < tbest) tbest = t, best = c;
   }
   if (has_sell) {
     const float t = time_one(sell);
-    if (t < tbest) tbest = t, best = FormatChoice{true, false, 8};
+    if (t < tbest) tbest = t, best = FormatChoice{true, false, 8, kCsrBatch};
+  }
+  if (!offs.empty()) {
+    const float t = time_one(dia);
+    if (t < tbest) tbest = t, best = FormatChoice{false, false, 8, kCsrBatch, true};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   MDP_HIP(hipStreamSynchronize(s));
   if (std::getenv("MDP_SETUP_VERBOSE"))
-    std::fprintf(stderr, "[mdp] autotune %s n=%d nnz=%lld: %s lpr=%d (%.2f us)\n", sizeof(T) == 8 ? "f64" : "f32",
-                 h.nr, static_cast<long long>(h.nnz()), best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
-                 best.lpr, 1e3 * tbest / kTuneReps);
+    std::fprintf(stderr, "[mdp] autotune %s n=%d nnz=%lld: %s lpr=%d batch=%d (%.2f us)\n",
+                 sizeof(T) == 8 ? "f64" : "f32", h.nr, static_cast<long long>(h.nnz()),
+                 best.dia ? "dia" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector", best.lpr, best.batch,
+                 1e3 * tbest / kTuneReps);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.emplace(key, best);
   return best;

@@ -19,14 +19,18 @@
 
 namespace mdp {
 
-// A device sparse matrix: sliced ELL (`sell`, 64-row slices, `ptr` = slice
-// offsets), CSR with one thread per row (`scalar`), or CSR with `lpr` lanes
-// per row.
+// A device sparse matrix: diagonal storage (`dia`, `ptr` = the ndiag
+// offsets, `val` = ndiag x nr), sliced ELL (`sell`, 64-row slices, `ptr` =
+// slice offsets), CSR with one thread per row (`scalar`), or CSR with `lpr`
+// lanes per row and `batch` entries in flight per lane.
 template <typename T>
 struct DCsr {
   int32_t nr = 0, nc = 0;
   int64_t nnz = 0;
   int lpr = 8;
+  int batch = 4;  // CSR-vector: entries in flight per lane
+  bool dia = false;
+  int32_t ndiag = 0;
   bool sell = false;
   bool scalar = false;
   int32_t nslices = 0;
