@@ -4,13 +4,20 @@
   applied exactly as Algorithm 1: solve on the host domain with Q_OO
   (V-cycles on S~ of eq. (7)), update the fracture residual with A_GO, solve
   on the fracture block with Q_GG (V-cycles on A_GG), concatenate.
+* ``MD`` / ``MU``  the other two block preconditioners that Section 3.2
+  derives from the factorisation eq. (5), B_D = D^{-1} and B_U = (U D)^{-1},
+  made inexact with the same Q_OO and Q_GG: blocks solved independently, or
+  interface first with the domain residual updated by A_OG.
 * ``exact_block_lower_dense``  B_L = (D L)^{-1} of Section 3.2 (exact Schur
   complement, exact inverses), and ``approx_block_lower_dense`` B~_L (S~
   with exact inverses), both dense, for the spectral checks of Section 3.2.
 * ``block_diag_dense`` / ``block_upper_dense``  B_D = D^{-1} and
   B_U = (U D)^{-1} of Section 3.2, dense.
 
-Pins: M_L equals the dense block lower-triangular solve with the same Q's;
+Pins: M_L, M_D and M_U equal the dense block lower-triangular, diagonal and
+upper-triangular solves with the same Q's; with exact blocks (one-level
+hierarchies, diagonal fracture block so that S~ = S) M_D and M_U equal the
+LAPACK inverses B_D and B_U;
 with exact blocks, GMRES converges in at most two iterations because
 A B_L = U is unipotent with (U - I)^2 = 0 (Section 3.2 states its
 eigenvalues are all one); with a diagonal fracture block the same holds for
@@ -55,6 +62,40 @@ class ML:
             r_g = r[self.gamma] - self.Ago @ z_o     # update the interface residual
             z[self.gamma] = self.q_gamma(r_g)        # solve on the interface
         return z
+
+
+class MD(ML):
+    """Inexact block-diagonal preconditioner: B_D = D^{-1} of Section 3.2
+    (D = diag(S, A_GG) from the factorisation eq. (5)) with S^{-1} and
+    A_GG^{-1} replaced by the same Q_OO (V-cycles on S~) and Q_GG as M_L.
+    The two blocks are solved independently."""
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        z = np.empty_like(r)
+        z[self.omega] = self.q_omega(r[self.omega])
+        if self.gamma.size:
+            z[self.gamma] = self.q_gamma(r[self.gamma])
+        return z
+
+
+class MU(ML):
+    """Inexact block upper-triangular preconditioner: B_U = (U D)^{-1} of
+    Section 3.2, U D = [[S, A_OG], [0, A_GG]], with the same Q_OO and Q_GG as
+    M_L.  Back substitution: solve on the interface, update the domain
+    residual with A_OG, solve in the domain."""
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        z = np.empty_like(r)
+        r_o = r[self.omega]
+        if self.gamma.size:
+            z_g = self.q_gamma(r[self.gamma])        # solve on the interface
+            z[self.gamma] = z_g
+            r_o = r_o - self.Aog @ z_g               # update the domain residual
+        z[self.omega] = self.q_omega(r_o)            # solve in the domain
+        return z
+
+
+FORMS = {"lower": ML, "diag": MD, "upper": MU}
 
 
 def _dense(M):

@@ -30,11 +30,12 @@ class SolveOptions:
     restart: int = 64
     maxiter: int = 1000
     amg: Optional[amg.AMGOptions] = None
+    form: str = "lower"  # block preconditioner: "lower" (M_L), "diag" (M_D) or "upper" (M_U)
 
 
 def setup(A, part, opts: Optional[SolveOptions] = None) -> precond.ML:
     opts = opts or SolveOptions()
-    return precond.ML(sp.csr_matrix(A), part, opts.cycles, opts.amg)
+    return precond.FORMS[opts.form](sp.csr_matrix(A), part, opts.cycles, opts.amg)
 
 
 def solve(A, b, part, opts: Optional[SolveOptions] = None, M: Optional[precond.ML] = None,

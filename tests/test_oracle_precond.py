@@ -106,3 +106,55 @@ def test_whole_solve_matches_lapack(make):
     cond = np.linalg.cond(A.toarray())
     err = np.linalg.norm(res.x - x) / np.linalg.norm(x)
     assert err <= cond * 1e-8
+
+
+@pytest.mark.parametrize("make", [lambda: synth.tiny_2d(8, seed=1), lambda: synth.tiny_3d(5, seed=2)])
+def test_diag_and_upper_forms_equal_their_block_solves(make):
+    """M_D^{-1} = blockdiag(Q_OO^{-1}, Q_GG^{-1}) and
+    M_U^{-1} = [[Q_OO^{-1}, A_OG], [0, Q_GG^{-1}]] (Section 3.2 with the
+    inexact blocks of eq. (8)); checked densely with the Q's as operators."""
+    A, b, part = oa.assemble(make())
+    opts = amg.AMGOptions(max_coarse=8)
+    MD = precond.MD(A, part, amg_opts=opts)
+    MU = precond.MU(A, part, amg_opts=opts)
+    n = A.shape[0]
+    no = MD.omega.size
+    Qo, Qg = _op(MD.q_omega, no), _op(MD.q_gamma, n - no)
+    perm = np.concatenate([MD.omega, MD.gamma])
+    Dinv = np.zeros((n, n))
+    Dinv[:no, :no] = np.linalg.inv(Qo)
+    Dinv[no:, no:] = np.linalg.inv(Qg)
+    Uinv = Dinv.copy()
+    Uinv[:no, no:] = MU.Aog.toarray()
+    for M, Minv in ((MD, Dinv), (MU, Uinv)):
+        Z = _op(M.apply, n)[np.ix_(perm, perm)]
+        assert np.allclose(Z, np.linalg.inv(Minv), atol=1e-10 * np.abs(Z).max())
+
+
+def test_diag_and_upper_forms_exact_blocks():
+    """With one-level hierarchies (Q = exact inverses) and no tangential
+    fracture flow (A_GG diagonal, so S~ = S), M_D and M_U are exactly the
+    B_D = D^{-1} and B_U = (U D)^{-1} of Section 3.2, computed by LAPACK;
+    B_U then needs at most two GMRES steps."""
+    n = 8
+    fr = [Fracture(0, 2, (1,), (2,), 3.0, 0.5, 1e-2), Fracture(1, 5, (4,), (5,), 1.0, 4.0, 1e-3)]
+    sc = Scenario(2, n, np.ones(n * n), fr, {(0, 0): 1.0, (0, 1): 0.0})
+    A, b, part = oa.assemble(sc)
+    exact = amg.AMGOptions(max_coarse=10 ** 6)
+    N = A.shape[0]
+    for cls, dense in ((precond.MD, precond.block_diag_dense), (precond.MU, precond.block_upper_dense)):
+        M = cls(A, part, amg_opts=exact)
+        assert len(M.H_omega.levels) == 1
+        B = dense(A, part)
+        assert np.allclose(_op(M.apply, N), B, atol=1e-10 * np.abs(B).max())
+    res = fgmres(lambda v: A @ v, b, precond.MU(A, part, amg_opts=exact).apply, tol=1e-10)
+    assert res.converged and res.iters <= 2
+
+
+@pytest.mark.parametrize("form", ["diag", "upper"])
+def test_diag_and_upper_solves_match_lapack(form):
+    A, b, part = oa.assemble(synth.regular_3d(n=8, seed=1))
+    res, _, _ = osv.solve(A, b, part, osv.SolveOptions(form=form))
+    x = osv.solve_dense(A, b)
+    assert res.converged and res.rel_res_true <= 1e-8
+    assert np.linalg.norm(res.x - x) <= 1e-6 * np.linalg.norm(x)
