@@ -64,9 +64,18 @@ extern "C" {
                               the additions in each row; equal matrices get
                               equal formats within a process. */
 
+/* ---- block preconditioner (Section 3.2: the factorisation eq. (5) gives
+ *      B_L = (D L)^-1, B_D = D^-1 and B_U = (U D)^-1; each is made inexact
+ *      with the same Q_OO, V-cycles on S~ of eq. (7), and Q_GG, V-cycles on
+ *      A_GG) ------------------------------------------------------------------ */
+#define MDP_BLOCK_LOWER 0 /* M_L of eq. (8), Algorithm 1: Q_OO, A_GO update, Q_GG */
+#define MDP_BLOCK_DIAG 1  /* M_D: Q_OO and Q_GG on their blocks, independently     */
+#define MDP_BLOCK_UPPER 2 /* M_U: Q_GG, then r_O - A_OG z_G, then Q_OO             */
+
 /* ---- operators for mdp_apply ---------------------------------------------- */
 #define MDP_OP_A 0    /* y = A x, the full system matrix (FP64)                     */
-#define MDP_OP_ML 1   /* y = M_L x, one preconditioner application (Algorithm 1)    */
+#define MDP_OP_ML 1   /* y = M x, one application of the handle's block preconditioner
+                         (M_L of Algorithm 1 unless block_form says otherwise)     */
 #define MDP_OP_QOO 2  /* y = Q_OO x on the Omega block (x, y of length n_Omega)     */
 #define MDP_OP_QGG 3  /* y = Q_GG x on the Gamma block (x, y of length n_Gamma)     */
 
@@ -102,6 +111,7 @@ typedef struct {
   int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
   uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE              */
+  int32_t block_form;     /* MDP_BLOCK_LOWER (default), MDP_BLOCK_DIAG, MDP_BLOCK_UPPER */
 } mdp_options;
 
 typedef struct {

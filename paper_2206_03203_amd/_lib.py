@@ -45,6 +45,7 @@ MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING = 0, 1, 2
 MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP_EBUSY = -1, -2, -3, -4, -5, -6, -7
 MDP_FP64, MDP_MIXED = 0, 1
 MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE = 1, 2, 4
+MDP_BLOCK_LOWER, MDP_BLOCK_DIAG, MDP_BLOCK_UPPER = 0, 1, 2
 MDP_OP_A, MDP_OP_ML, MDP_OP_QOO, MDP_OP_QGG = 0, 1, 2, 3
 MDP_BLOCK_OMEGA, MDP_BLOCK_GAMMA = 0, 1
 MDP_MAT_A, MDP_MAT_P, MDP_MAT_R = 0, 1, 2
@@ -63,7 +64,8 @@ class mdp_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("vcycles", C.c_int32), ("pre_sweeps", C.c_int32),
                 ("post_sweeps", C.c_int32), ("strength_theta", C.c_double), ("max_coarse", C.c_int32),
                 ("max_dense", C.c_int32), ("max_levels", C.c_int32), ("restart", C.c_int32),
-                ("max_iter", C.c_int32), ("rtol", C.c_double), ("flags", C.c_uint32)]
+                ("max_iter", C.c_int32), ("rtol", C.c_double), ("flags", C.c_uint32),
+                ("block_form", C.c_int32)]
 
 
 class mdp_stats(C.Structure):

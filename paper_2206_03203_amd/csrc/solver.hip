@@ -662,16 +662,34 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStre
   }
 }
 
-// Algorithm 1: z = M_L r, with r and z laid out as [Omega; Gamma].  On entry
-// Ho.lv[0].t = D^-1 r_O (see start_smoother).
+// One application of the block preconditioner, r and z laid out as
+// [Omega; Gamma].  On entry Ho.lv[0].t = D^-1 r_O (see start_smoother).
+//  * M_L (eq. (8), Algorithm 1): z_O = Q_OO r_O; r_G - A_GO z_O; z_G = Q_GG of it.
+//  * M_D (B_D = D^-1 of Section 3.2 made inexact): z_O = Q_OO r_O, z_G = Q_GG r_G.
+//  * M_U (B_U = (U D)^-1 made inexact): z_G = Q_GG r_G; r_O - A_OG z_G; z_O = Q_OO of it.
 template <typename T>
 void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
-  apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
-  if (P.n_g == 0) return;
-  T *rg = dptr<T>(P.rg);
-  spmv<kResidScale>(P.Ago, static_cast<const T *>(z), r + P.n_o, dptr<const T>(P.Hg.lv[0].dinv), rg,
-                    dptr<T>(P.Hg.lv[0].t), gate, s, kKcVcycleOther);  // r_G - A_GO z_O (and D^-1 of it)
-  apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
+  if (P.n_g == 0 || P.form == MDP_BLOCK_LOWER) {
+    apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
+    if (P.n_g == 0) return;
+    T *rg = dptr<T>(P.rg);
+    spmv<kResidScale>(P.Ago, static_cast<const T *>(z), r + P.n_o, dptr<const T>(P.Hg.lv[0].dinv), rg,
+                      dptr<T>(P.Hg.lv[0].t), gate, s, kKcVcycleOther);  // r_G - A_GO z_O (and D^-1 of it)
+    apply_q(P.Hg, P.vcycles, static_cast<const T *>(rg), z + P.n_o, gate, s);  // z_G = Q_GG r_G
+    return;
+  }
+  if (P.form == MDP_BLOCK_DIAG) {
+    apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
+    start_smoother(P.Hg, r + P.n_o, gate, s);
+    apply_q(P.Hg, P.vcycles, r + P.n_o, z + P.n_o, gate, s);  // z_G = Q_GG r_G
+    return;
+  }
+  start_smoother(P.Hg, r + P.n_o, gate, s);
+  apply_q(P.Hg, P.vcycles, r + P.n_o, z + P.n_o, gate, s);  // z_G = Q_GG r_G
+  T *ro = dptr<T>(P.rg);
+  spmv<kResidScale>(P.Aog, static_cast<const T *>(z + P.n_o), r, dptr<const T>(P.Ho.lv[0].dinv), ro,
+                    dptr<T>(P.Ho.lv[0].t), gate, s, kKcVcycleOther);  // r_O - A_OG z_G (and D^-1 of it)
+  apply_q(P.Ho, P.vcycles, static_cast<const T *>(ro), z, gate, s);  // z_O = Q_OO of it
 }
 
 // Preconditioner for a list of pairs' host systems, laid out block-diagonally
@@ -680,10 +698,11 @@ void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
 template <typename T>
 std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *> &sys, const LevelPlan &plan_o,
                                            const LevelPlan &plan_g, const std::vector<int> &gpairs, int vcycles,
-                                           hipStream_t s) {
+                                           int form, hipStream_t s) {
   auto p = std::make_unique<Precond<T>>();
   Keep keep;
   p->vcycles = vcycles;
+  p->form = form;
   std::vector<const HHier *> ho, hg;
   for (const HostSystem *h : sys) ho.push_back(&h->Ho);
   for (int q : gpairs) hg.push_back(&sys[q]->Hg);
@@ -699,8 +718,18 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
       pieces.emplace_back(&sys[q]->Ago, static_cast<int32_t>(plan_g.off[0][k]),
                           static_cast<int32_t>(plan_o.off[0][q]));
     }
-    upload_csr(concat_blocks(p->n_g, p->n_o, pieces), p->Ago, s, keep);
-    p->rg.alloc(static_cast<size_t>(p->n_g) * sizeof(T));
+    if (form == MDP_BLOCK_LOWER) {
+      upload_csr(concat_blocks(p->n_g, p->n_o, pieces), p->Ago, s, keep);
+      p->rg.alloc(static_cast<size_t>(p->n_g) * sizeof(T));
+    } else if (form == MDP_BLOCK_UPPER) {
+      std::vector<Piece> up;
+      for (size_t k = 0; k < gpairs.size(); ++k) {
+        const int q = gpairs[k];
+        up.emplace_back(&sys[q]->Aog, static_cast<int32_t>(plan_o.off[0][q]), static_cast<int32_t>(plan_g.off[0][k]));
+      }
+      upload_csr(concat_blocks(p->n_o, p->n_g, up), p->Aog, s, keep);
+      p->rg.alloc(static_cast<size_t>(p->n_o) * sizeof(T));
+    }
   }
   MDP_HIP(hipStreamSynchronize(s));  // host staging vectors die here
   return p;
@@ -1023,9 +1052,9 @@ void Solver::upload(hipStream_t s) {
   const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
   const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(sys, po, pg, gp, opt.vcycles, s);
+    pc32 = upload_precond<float>(sys, po, pg, gp, opt.vcycles, opt.block_form, s);
   else
-    pc64 = upload_precond<double>(sys, po, pg, gp, opt.vcycles, s);
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt.vcycles, opt.block_form, s);
   layout.build({{{0, n}}}, n, s);
   const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
   ws.alloc(n, opt.restart, 1, layout.ntiles, tsz, s);
@@ -1182,9 +1211,9 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
   upload_vec(gidx, keep.put(std::move(gidx_h)), s);
   upload_vec(gpair, keep.put(std::move(gpair_h)), s);
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(hsys, po, pg, gpairs, opt.vcycles, s);
+    pc32 = upload_precond<float>(hsys, po, pg, gpairs, opt.vcycles, opt.block_form, s);
   else
-    pc64 = upload_precond<double>(hsys, po, pg, gpairs, opt.vcycles, s);
+    pc64 = upload_precond<double>(hsys, po, pg, gpairs, opt.vcycles, opt.block_form, s);
   layout.build(ranges, n, s);
   if (alloc_ws) {
     const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);

@@ -69,14 +69,16 @@ struct DHier {
   bool dense_only() const { return lv.size() == 1 && lv[0].ncont == 0 && lv[0].sw_off == lv[0].n; }
 };
 
-// Preconditioner M_L in precision T (Algorithm 1).
+// Block preconditioner in precision T: M_L (Algorithm 1), M_D or M_U.
 template <typename T>
 struct Precond {
   DHier<T> Ho, Hg;
-  DCsr<T> Ago;
-  DevMem rg;  // r_Gamma - A_GO z_Omega
+  DCsr<T> Ago;  // A_GO (lower form)
+  DCsr<T> Aog;  // A_OG (upper form)
+  DevMem rg;    // r_Gamma - A_GO z_Omega (lower); r_Omega - A_OG z_Gamma (upper)
   int32_t n_o = 0, n_g = 0;
   int vcycles = 1;
+  int form = MDP_BLOCK_LOWER;
 };
 
 // Tile work list over the pairs' unknowns (global vector layout).

@@ -38,6 +38,7 @@ def test_options_default_values():
     assert (o.precision, o.vcycles, o.pre_sweeps, o.post_sweeps) == (L.MDP_FP64, 1, 1, 1)
     assert (o.strength_theta, o.max_coarse, o.max_dense, o.max_levels) == (0.08, 400, 2000, 10)
     assert (o.restart, o.max_iter, o.rtol, o.flags) == (64, 1000, 1e-8, 0)
+    assert o.block_form == L.MDP_BLOCK_LOWER
     assert L.mdp_version().startswith("mdp")
 
 
@@ -204,6 +205,15 @@ def test_server_lifecycle_without_device_work():
     finally:
         L.mdp_destroy(h)
         L.mdp_server_destroy(srv)
+
+
+def test_unknown_block_form_rejected():
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY, block_form=7)
+    with pytest.raises(L.MdpError) as e:
+        L.mdp_setup(A, part, o)
+    assert e.value.code == L.MDP_EINVAL
 
 
 def test_unknown_flag_bits_rejected():
