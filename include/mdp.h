@@ -150,6 +150,23 @@ int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt,
 int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stream,
                    mdp_handle **out);
 
+/* Write the complete host setup of h (the [Omega; Gamma] permutation, the
+ * blocks of eq. (4), S~ of eq. (7) and both SA-AMG hierarchies of Section
+ * 3.3, with the AMG options they were built with) to the file `path`, so
+ * that mdp_load can re-create the handle without repeating the setup.
+ * Binary, little-endian, with a tag, a format version and a 64-bit FNV-1a
+ * checksum.  EINVAL if the file cannot be written. */
+int mdp_save(const mdp_handle *h, const char *path);
+
+/* Re-create a handle from a file written by mdp_save and upload it as
+ * mdp_setup would (MDP_HOST_ONLY in opt skips the upload).  opt may be NULL
+ * (defaults, with the file's AMG options); otherwise its AMG options
+ * (strength_theta, max_coarse, max_dense, max_levels) must equal the file's.
+ * The solve options (precision, vcycles, restart, ...) are free.  A file that
+ * is missing, truncated, altered or inconsistent returns EINVAL with *out =
+ * NULL. */
+int mdp_load(const char *path, const mdp_options *opt, void *hip_stream, mdp_handle **out);
+
 /* Release the handle and its device memory (NULL is a no-op). */
 int mdp_destroy(mdp_handle *h);
 

@@ -99,6 +99,8 @@ _sig = {
     "mdp_level_shape": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_int64)]),
     "mdp_level_export": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_double)]),
     "mdp_level_aggregates": (C.c_int, [_vp, C.c_int32, C.c_int32, _ip]),
+    "mdp_save": (C.c_int, [_vp, C.c_char_p]),
+    "mdp_load": (C.c_int, [C.c_char_p, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
     "mdp_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.POINTER(_vp)]),
     "mdp_server_register": (C.c_int, [_vp, _vp]),
     "mdp_submit": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32, C.POINTER(C.c_uint64)]),
@@ -260,6 +262,20 @@ def mdp_level_aggregates(h: int, block: int, level: int) -> np.ndarray:
     agg = np.zeros(r.value, dtype=np.int32)
     _check(lib.mdp_level_aggregates(h, block, level, agg.ctypes.data_as(_ip)), "mdp_level_aggregates")
     return agg
+
+
+def mdp_save(h: int, path: str) -> None:
+    _check(lib.mdp_save(h, os.fsencode(path)), "mdp_save")
+
+
+def mdp_load(path: str, opts: Optional[mdp_options] = None, stream=None) -> int:
+    """Re-create a handle from a hierarchy file (see mdp_save)."""
+    out = _vp()
+    host_only = opts is not None and bool(opts.flags & MDP_HOST_ONLY)
+    sp = None if host_only else _stream_ptr(stream)
+    _check(lib.mdp_load(os.fsencode(path), C.byref(opts) if opts is not None else None, sp, C.byref(out)),
+           "mdp_load")
+    return out.value
 
 
 def mdp_server_create(mem_budget_bytes: int = 0, max_slots: int = 64) -> int:

@@ -192,6 +192,51 @@ int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stre
   API_END
 }
 
+int mdp_save(const mdp_handle *h, const char *path) {
+  API_BEGIN
+  if (!h || !path) {
+    set_last_error("NULL argument");
+    return MDP_EINVAL;
+  }
+  save_host_system(h->s.host, h->s.opt, path);
+  return MDP_OK;
+  API_END
+}
+
+int mdp_load(const char *path, const mdp_options *opt, void *hip_stream, mdp_handle **out) {
+  API_BEGIN
+  if (!path || !out) {
+    set_last_error("NULL argument");
+    return MDP_EINVAL;
+  }
+  *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto h = std::make_unique<mdp_handle>();
+  mdp_options saved;
+  mdp_options_default(&saved);
+  load_host_system(path, h->s.host, saved);
+  mdp_options o = saved;
+  if (opt) {
+    o = *opt;
+    if (o.strength_theta != saved.strength_theta || o.max_coarse != saved.max_coarse ||
+        o.max_dense != saved.max_dense || o.max_levels != saved.max_levels) {
+      set_last_error("AMG options differ from the ones the hierarchy file was built with");
+      return MDP_EINVAL;
+    }
+  }
+  const int rc = check_options(o);
+  if (rc != MDP_OK) return rc;
+  h->s.opt = o;
+  h->s.n = h->s.host.n;
+  h->s.n_o = h->s.host.n_o;
+  h->s.n_g = h->s.host.n_g;
+  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h.release();
+  return MDP_OK;
+  API_END
+}
+
 int mdp_destroy(mdp_handle *h) {
   API_BEGIN
   if (h) {

@@ -53,6 +53,11 @@ struct SetupError {
 void build_host_system(const mdp_csr *A, const int32_t *part, const mdp_options &opt,
                        HostSystem &out);
 
+// Write / read the complete host setup (hierarchy file).  `amg` receives the
+// AMG options the file was built with.  Both throw SetupError (MDP_EINVAL).
+void save_host_system(const HostSystem &s, const mdp_options &o, const char *path);
+void load_host_system(const char *path, HostSystem &out, mdp_options &amg);
+
 // SA-AMG setup on one block (exposed for testing through the C ABI).
 HHier amg_setup(const HCsr &A, const AmgParams &prm);
 

@@ -223,3 +223,91 @@ def test_unknown_flag_bits_rejected():
     with pytest.raises(L.MdpError) as e:
         L.mdp_setup(A, part, o)
     assert e.value.code == L.MDP_EINVAL
+
+
+def _all_levels(h):
+    info = L.mdp_info(h)
+    out = []
+    for block, nl in ((0, info["levels_omega"]), (1, info["levels_gamma"])):
+        for lvl in range(nl):
+            for mat in (L.MDP_MAT_A, L.MDP_MAT_P, L.MDP_MAT_R):
+                try:
+                    out.append(L.mdp_level_export(h, block, lvl, mat))
+                except L.MdpError:
+                    out.append(None)
+            if lvl + 1 < nl:
+                out.append(L.mdp_level_aggregates(h, block, lvl))
+    return info, out
+
+
+def test_hierarchy_file_round_trip(tmp_path):
+    """mdp_save / mdp_load reproduce the whole host setup bit for bit."""
+    sc = synth.regular_3d(n=10, k_par=1e4, kappa=1e-4, seed=3)
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part, max_coarse=30)
+    path = str(tmp_path / "h.mdph")
+    try:
+        L.mdp_save(h, path)
+        o = L.mdp_options_default(flags=L.MDP_HOST_ONLY, max_coarse=30, precision=L.MDP_MIXED)
+        h2 = L.mdp_load(path, o)
+        try:
+            i1, l1 = _all_levels(h)
+            i2, l2 = _all_levels(h2)
+            assert i1 == i2 and i1["levels_omega"] >= 2
+            for a, c in zip(l1, l2):
+                if a is None or c is None:
+                    assert a is None and c is None
+                elif isinstance(a, tuple):
+                    assert all(np.array_equal(x, y) for x, y in zip(a[:3], c[:3])) and a[3] == c[3]
+                else:
+                    assert np.array_equal(a, c)
+        finally:
+            L.mdp_destroy(h2)
+        # AMG options must match the file's
+        with pytest.raises(L.MdpError) as e:
+            L.mdp_load(path, L.mdp_options_default(flags=L.MDP_HOST_ONLY, max_coarse=31))
+        assert e.value.code == L.MDP_EINVAL
+    finally:
+        L.mdp_destroy(h)
+
+
+def test_hierarchy_file_rejects_damage(tmp_path):
+    sc = synth.tiny_2d(9, seed=2)
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part)
+    path = tmp_path / "h.mdph"
+    try:
+        L.mdp_save(h, str(path))
+    finally:
+        L.mdp_destroy(h)
+    data = path.read_bytes()
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY)
+    cases = {"truncated": data[: len(data) // 2], "empty": b"", "flipped": bytearray(data),
+             "tag": b"XXXXXXXX" + data[8:]}
+    cases["flipped"][len(data) // 3] ^= 0x40
+    for name, blob in cases.items():
+        p = tmp_path / f"bad_{name}"
+        p.write_bytes(bytes(blob))
+        with pytest.raises(L.MdpError) as e:
+            L.mdp_load(str(p), o)
+        assert e.value.code == L.MDP_EINVAL, name
+    with pytest.raises(L.MdpError):
+        L.mdp_load(str(tmp_path / "missing"), o)
+    # a consistent checksum over inconsistent contents: n changed (the field
+    # after the tag, version and AMG options) and the checksum recomputed
+    def fnv(b):
+        h = 1469598103934665603
+        for c in b:
+            h = ((h ^ c) * 1099511628211) & (2 ** 64 - 1)
+        return h
+    body = bytearray(data[:-8])
+    off = 8 + 4 + 8 + 3 * 4
+    body[off:off + 4] = (int.from_bytes(body[off:off + 4], "little") + 1).to_bytes(4, "little")
+    p = tmp_path / "bad_sizes"
+    p.write_bytes(bytes(body) + fnv(bytes(body)).to_bytes(8, "little"))
+    with pytest.raises(L.MdpError) as e:
+        L.mdp_load(str(p), o)
+    assert e.value.code == L.MDP_EINVAL and "not a valid" in str(e.value)
+    good = tmp_path / "good"
+    good.write_bytes(data[:-8] + fnv(data[:-8]).to_bytes(8, "little"))
+    L.mdp_destroy(L.mdp_load(str(good), o))  # the checksum is FNV-1a 64 over the body
