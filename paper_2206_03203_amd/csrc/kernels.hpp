@@ -55,6 +55,14 @@ enum SpmvMode : int {
   kResidScale = 6,  // y = b - A x ; y2 = dinv .* y     (residual that also starts the next smoother)
 };
 
+// Batched solves: a row whose pair has stopped applying the preconditioner is
+// skipped (its output is no longer read).  rpair maps rows to pairs and pst
+// holds the pairs' states; either is NULL when rows are not gated.
+__device__ __forceinline__ bool row_stopped(int row, const int *__restrict__ rpair,
+                                            const GmresState *__restrict__ pst) {
+  return rpair && pst && pst[rpair[row]].skip_apply;
+}
+
 // Per-row epilogue shared by the sparse kernels.
 template <int MODE, typename Acc, typename TX, typename TY>
 __device__ __forceinline__ void spmv_store(int row, Acc sum, const TX *__restrict__ x, const TY *__restrict__ b,
@@ -98,13 +106,14 @@ template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void spmv_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
-    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * (kThreads / LPR) + static_cast<int>(threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  if (row >= nr) return;  // whole LPR groups leave together
+  if (row >= nr || row_stopped(row, rpair, pst)) return;  // whole LPR groups leave together
   const int s = ptr[row], e = ptr[row + 1];
   Acc sum = 0;
   for (int p0 = s + lane; p0 < e; p0 += BATCH * LPR) {
@@ -135,7 +144,8 @@ template <int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void sell_kernel(
     int nr, int nslices, const int *__restrict__ soff, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
-    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -144,6 +154,7 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
   if (slice >= nslices) return;
   const int o0 = soff[slice], o1 = soff[slice + 1];
   const int row = slice * 64 + lane;
+  if (row < nr && row_stopped(row, rpair, pst)) return;
   Acc sum = 0;
   // kSellBatch entries per step, the last step predicated (past the slice
   // width: value 0 and this lane's first column), so that all index and
@@ -175,12 +186,13 @@ template <int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void dia_kernel(
     int nr, int nc, int ndiag, const int *__restrict__ off, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
-    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * kThreads + static_cast<int>(threadIdx.x);
-  if (row >= nr) return;
+  if (row >= nr || row_stopped(row, rpair, pst)) return;
   Acc sum = 0;
   for (int d0 = 0; d0 < ndiag; d0 += kDiaBatch) {
     Acc v[kDiaBatch], xv[kDiaBatch];
@@ -207,12 +219,13 @@ template <int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
-    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate) {
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int row = blk * kThreads + static_cast<int>(threadIdx.x);
-  if (row >= nr) return;
+  if (row >= nr || row_stopped(row, rpair, pst)) return;
   const int s = ptr[row], e = ptr[row + 1];
   Acc sum = 0;
   for (int p0 = s; p0 < e; p0 += kScalarBatch) {

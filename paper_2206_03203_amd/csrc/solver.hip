@@ -333,7 +333,8 @@ LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
 }
 
 template <typename T>
-void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep) {
+void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep,
+                 const std::vector<int> *pair_of = nullptr) {
   const size_t L = pl.order.size();
   d.lv.clear();
   d.lv.resize(L);
@@ -384,6 +385,28 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
   const size_t n0 = static_cast<size_t>(std::max(d.n(), 1)) * sizeof(T);
   d.tmp_res.alloc(n0);
   d.tmp_dz.alloc(n0);
+  if (pair_of) {
+    // per level, the pair owning each row (hierarchy p belongs to pair pair_of[p])
+    d.rowpair.clear();
+    d.rowpair.resize(L);
+    for (size_t l = 0; l < L; ++l) {
+      std::vector<int32_t> m(static_cast<size_t>(pl.n[l]), -1);
+      for (int p : pl.order[l]) {
+        const int64_t o = pl.off[l][p];
+        std::fill(m.begin() + o, m.begin() + o + hs[p]->lv[l].A.nr, (*pair_of)[p]);
+      }
+      if (std::find(m.begin(), m.end(), -1) != m.end()) raise(MDP_EINVAL, "batch level row without a pair");
+      upload_vec(d.rowpair[l], keep.put(std::move(m)), s);
+    }
+    for (size_t l = 0; l < L; ++l) {
+      DLevel<T> &dl = d.lv[l];
+      const int *m = dptr<const int>(d.rowpair[l]);
+      dl.A.rowpair = m;  // rows: the continuing systems' rows of level l
+      dl.P.rowpair = m;
+      if (l + 1 < L) dl.R.rowpair = dptr<const int>(d.rowpair[l + 1]);  // rows: level l + 1
+      dl.Asw.rowpair = m + dl.sw_off;
+    }
+  }
 }
 
 int grid_for(int64_t n) {
@@ -393,6 +416,15 @@ int grid_for(int64_t n) {
 
 // ---------------------------------------------------------------------------
 // Sparse products
+
+// Launch gating.  `all` (a device flag) retires a whole launch once every
+// pair has stopped applying the preconditioner; with `st` (batched solves)
+// the sparse products also skip the rows of pairs that have stopped, through
+// each matrix's row-to-pair map.
+struct Gate {
+  const int *all = nullptr;
+  const GmresState *st = nullptr;
+};
 
 // Algorithmic bytes of one sparse product: matrix values, column indices and
 // row pointers once, each vector entry read or written once.
@@ -414,24 +446,24 @@ double spmv_bytes(const DCsr<TA> &A) {
 
 template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
 void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2,
-                 const int *gate, hipStream_t s, int kind) {
+                 Gate gate, hipStream_t s, int kind) {
   const int64_t rows_per_blk = kThreads / LPR;
   const int blocks = static_cast<int>((A.nr + rows_per_blk - 1) / rows_per_blk);
   timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
     hipLaunchKernelGGL((spmv_kernel<LPR, BATCH, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
-                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
   });
 }
 
 template <int MODE, typename TA, typename TX, typename TY>
-void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, const int *gate,
+void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
           hipStream_t s, int kind = kKcOther) {
   if (A.nr == 0) return;
   if (A.dia) {
     const int blocks = (A.nr + kThreads - 1) / kThreads;
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
       hipLaunchKernelGGL((dia_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc, A.ndiag,
-                         A.p(), A.v(), x, b, dinv, y, y2, gate);
+                         A.p(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
     });
     return;
   }
@@ -439,7 +471,7 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     const int blocks = (A.nslices + (kThreads / 64) - 1) / (kThreads / 64);
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
       hipLaunchKernelGGL((sell_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nslices,
-                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate);
+                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
     });
     return;
   }
@@ -447,7 +479,7 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
     const int blocks = (A.nr + kThreads - 1) / kThreads;
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
       hipLaunchKernelGGL((csr_scalar_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.p(),
-                         A.c(), A.v(), x, b, dinv, y, y2, gate);
+                         A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
     });
     return;
   }
@@ -526,9 +558,9 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   MDP_HIP(hipEventCreate(&e0));
   MDP_HIP(hipEventCreate(&e1));
   auto time_one = [&](const DCsr<T> &d) {
-    for (int i = 0; i < 2; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), nullptr, s);
+    for (int i = 0; i < 2; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), Gate{}, s);
     MDP_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < kTuneReps; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), nullptr, s);
+    for (int i = 0; i < kTuneReps; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), Gate{}, s);
     MDP_HIP(hipEventRecord(e1, s));
     MDP_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -583,24 +615,24 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
 // smoother's residual needs one gather per nonzero.
 
 template <typename T>
-void start_smoother(DHier<T> &H, const T *b, const int *gate, hipStream_t s) {
+void start_smoother(DHier<T> &H, const T *b, Gate gate, hipStream_t s) {
   const int n = H.n();
   if (n == 0 || H.dense_only()) return;
   timed_launch(kKcVcycleOther, s, 3.0 * sizeof(T) * n, [&] {
     hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
-                       dptr<const T>(H.lv[0].dinv), dptr<T>(H.lv[0].t), gate);
+                       dptr<const T>(H.lv[0].dinv), dptr<T>(H.lv[0].t), gate.all);
   });
 }
 
 // Systems whose coarsest level is l: dense inverses, or four l1-Jacobi sweeps
 // from zero (the first, D^-1 b, is already in t).
 template <typename T>
-void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, const int *gate, hipStream_t s) {
+void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, Gate gate, hipStream_t s) {
   if (L.ndense > 0) {
     const dim3 grid((L.max_dense_n + (kThreads / 64) - 1) / (kThreads / 64), L.ndense);
     timed_launch(kKcVcycleOther, s, 0.0, [&] {
       hipLaunchKernelGGL(dense_gemv_batched_kernel<T>, grid, dim3(kThreads), 0, s, dptr<const DenseDesc>(L.dense),
-                         dptr<const double>(H.cinv), b, x, gate);
+                         dptr<const double>(H.cinv), b, x, gate.all);
     });
   }
   const int nsw = L.n - L.sw_off;
@@ -617,7 +649,7 @@ void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, const int *gate, 
 }
 
 template <typename T>
-void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_t s) {
+void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
   DLevel<T> &L = H.lv[l];
   if (L.ncont > 0) {
     DLevel<T> &C = H.lv[l + 1];
@@ -641,7 +673,7 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, const int *gate, hipStream_
 
 // Q = `cycles` V-cycles as a stationary iteration from zero (lv[0].t = D^-1 r on entry).
 template <typename T>
-void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStream_t s) {
+void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s) {
   vcycle(H, 0, r, z, gate, s);
   const int n = H.n();
   DLevel<T> &L0 = H.lv[0];
@@ -658,7 +690,7 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStre
     if (L0.ncont < o) MDP_HIP(hipMemsetAsync(dptr<T>(H.tmp_res) + L0.ncont, 0, sizeof(T) * (o - L0.ncont), s));
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
-                       gate);
+                       gate.all);
   }
 }
 
@@ -668,7 +700,7 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, const int *gate, hipStre
 //  * M_D (B_D = D^-1 of Section 3.2 made inexact): z_O = Q_OO r_O, z_G = Q_GG r_G.
 //  * M_U (B_U = (U D)^-1 made inexact): z_G = Q_GG r_G; r_O - A_OG z_G; z_O = Q_OO of it.
 template <typename T>
-void apply_ml(Precond<T> &P, const T *r, T *z, const int *gate, hipStream_t s) {
+void apply_ml(Precond<T> &P, const T *r, T *z, Gate gate, hipStream_t s) {
   if (P.n_g == 0 || P.form == MDP_BLOCK_LOWER) {
     apply_q(P.Ho, P.vcycles, r, z, gate, s);  // z_O = Q_OO r_O
     if (P.n_g == 0) return;
@@ -706,11 +738,15 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
   std::vector<const HHier *> ho, hg;
   for (const HostSystem *h : sys) ho.push_back(&h->Ho);
   for (int q : gpairs) hg.push_back(&sys[q]->Hg);
-  upload_hier(ho, plan_o, p->Ho, s, keep);
+  // batches: row-to-pair maps so that stopped pairs' rows are skipped
+  std::vector<int> pair_o(sys.size());
+  for (size_t q = 0; q < sys.size(); ++q) pair_o[q] = static_cast<int>(q);
+  const bool batched = sys.size() > 1;
+  upload_hier(ho, plan_o, p->Ho, s, keep, batched ? &pair_o : nullptr);
   p->Ho.is_omega = true;
   p->n_o = p->Ho.n();
   if (!gpairs.empty()) {
-    upload_hier(hg, plan_g, p->Hg, s, keep);
+    upload_hier(hg, plan_g, p->Hg, s, keep, batched ? &gpairs : nullptr);
     p->n_g = p->Hg.n();
     std::vector<Piece> pieces;
     for (size_t k = 0; k < gpairs.size(); ++k) {
@@ -720,6 +756,7 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
     }
     if (form == MDP_BLOCK_LOWER) {
       upload_csr(concat_blocks(p->n_g, p->n_o, pieces), p->Ago, s, keep);
+      if (batched) p->Ago.rowpair = dptr<const int>(p->Hg.rowpair[0]);
       p->rg.alloc(static_cast<size_t>(p->n_g) * sizeof(T));
     } else if (form == MDP_BLOCK_UPPER) {
       std::vector<Piece> up;
@@ -728,6 +765,7 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
         up.emplace_back(&sys[q]->Aog, static_cast<int32_t>(plan_o.off[0][q]), static_cast<int32_t>(plan_g.off[0][k]));
       }
       upload_csr(concat_blocks(p->n_o, p->n_g, up), p->Aog, s, keep);
+      if (batched) p->Aog.rowpair = dptr<const int>(p->Ho.rowpair[0]);
       p->rg.alloc(static_cast<size_t>(p->n_o) * sizeof(T));
     }
   }
@@ -774,6 +812,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   GmresState *dst = dptr<GmresState>(ws.state);
   BatchCtl *ctl = dptr<BatchCtl>(ws.ctl);
   const int *gate_apply = &ctl->skip_all_apply;
+  // batches also skip, row by row, the pairs that have stopped
+  const Gate g_apply{gate_apply, np > 1 ? static_cast<const GmresState *>(dst) : nullptr};
   const Tile *tiles = dptr<const Tile>(L.tiles);
 
   std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0);
@@ -786,7 +826,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   }
   if (!use_x0) MDP_HIP(hipMemsetAsync(xg, 0, n * sizeof(double), s));
   if (use_x0) {
-    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), nullptr, s);
+    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), Gate{}, s);
     pair_norms(ws, L, V, s);
     for (int p = 0; p < np; ++p) beta[p] = ws.host_norms[p];
   } else {
@@ -823,7 +863,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
       const T *pin;
       if constexpr (std::is_same<T, double>::value) {
         pin = uj;
-        start_smoother(P.Ho, pin, gate_apply, s);
+        start_smoother(P.Ho, pin, g_apply, s);
       } else {
         T *rin = dptr<T>(ws.rin);
         const int no = P.n_o;
@@ -835,8 +875,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
         });
         pin = rin;
       }
-      apply_ml(P, pin, zj, gate_apply, s);
-      spmv<kPlain>(A, static_cast<const T *>(zj), cnull<double>(), cnull<double>(), w, mnull<double>(), gate_apply,
+      apply_ml(P, pin, zj, g_apply, s);
+      spmv<kPlain>(A, static_cast<const T *>(zj), cnull<double>(), cnull<double>(), w, mnull<double>(), g_apply,
                    s, kKcOuterSpmv);
       const int nv = 2 * j + 3;
       timed_launch(kKcArnoldiDot, s, 8.0 * n * (j + 2), [&] {
@@ -881,7 +921,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
                          static_cast<const T *>(Z), ld, dptr<const double>(ws.y), ws.ldv,
                          static_cast<const GmresState *>(dst), dptr<const int>(ws.active), xg);
     });
-    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), nullptr, s);
+    spmv<kResid>(A, static_cast<const double *>(xg), bg, cnull<double>(), V, mnull<double>(), Gate{}, s);
     pair_norms(ws, L, V, s);  // synchronises: host_state is valid too
     if (np > 1 && (ktimer_on(kKcArnoldiDot) || ktimer_on(kKcArnoldiAxpy))) {
       // The Arnoldi passes were counted as if every pair ran every step;
@@ -1106,7 +1146,7 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
   ensure_workspace(s);
   switch (op) {
     case MDP_OP_A:
-      spmv<kPlain>(A, x, cnull<double>(), cnull<double>(), y, mnull<double>(), nullptr, s);
+      spmv<kPlain>(A, x, cnull<double>(), cnull<double>(), y, mnull<double>(), Gate{}, s);
       break;
     case MDP_OP_ML:
     case MDP_OP_QOO:
@@ -1119,20 +1159,20 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
         hipLaunchKernelGGL((scale_copy_kernel<double, float>), dim3(grid_for(len)), dim3(kThreads), 0, s, len, x,
                            cnull<double>(), in, nullptr);
         auto &H = op == MDP_OP_QGG ? pc32->Hg : pc32->Ho;
-        start_smoother(H, static_cast<const float *>(in), nullptr, s);
+        start_smoother(H, static_cast<const float *>(in), Gate{}, s);
         if (op == MDP_OP_ML)
-          apply_ml(*pc32, static_cast<const float *>(in), out, nullptr, s);
+          apply_ml(*pc32, static_cast<const float *>(in), out, Gate{}, s);
         else
-          apply_q(H, pc32->vcycles, static_cast<const float *>(in), out, nullptr, s);
+          apply_q(H, pc32->vcycles, static_cast<const float *>(in), out, Gate{}, s);
         hipLaunchKernelGGL((scale_copy_kernel<float, double>), dim3(grid_for(len)), dim3(kThreads), 0, s, len,
                            static_cast<const float *>(out), cnull<double>(), y, nullptr);
       } else {
         auto &H = op == MDP_OP_QGG ? pc64->Hg : pc64->Ho;
-        start_smoother(H, x, nullptr, s);
+        start_smoother(H, x, Gate{}, s);
         if (op == MDP_OP_ML)
-          apply_ml(*pc64, x, y, nullptr, s);
+          apply_ml(*pc64, x, y, Gate{}, s);
         else
-          apply_q(H, pc64->vcycles, x, y, nullptr, s);
+          apply_q(H, pc64->vcycles, x, y, Gate{}, s);
       }
       break;
     }
@@ -1210,6 +1250,7 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
   upload_csr(Ag, A, s, keep);
   upload_vec(gidx, keep.put(std::move(gidx_h)), s);
   upload_vec(gpair, keep.put(std::move(gpair_h)), s);
+  if (npairs > 1) A.rowpair = dptr<const int>(gpair);
   if (opt.precision == MDP_MIXED)
     pc32 = upload_precond<float>(hsys, po, pg, gpairs, opt.vcycles, opt.block_form, s);
   else

@@ -35,7 +35,9 @@ struct DCsr {
   bool scalar = false;
   int32_t nslices = 0;
   DevMem ptr, col, val;
+  const int *rowpair = nullptr;  // batched: pair of each row (not owned), else NULL
   const int *p() const { return dptr<const int>(ptr); }
+  const int *rp() const { return rowpair; }
   const int *c() const { return dptr<const int>(col); }
   const T *v() const { return dptr<const T>(val); }
 };
@@ -61,6 +63,7 @@ struct DLevel {
 template <typename T>
 struct DHier {
   std::vector<DLevel<T>> lv;
+  std::vector<DevMem> rowpair;  // batched: per level, the pair of each row
   DevMem cinv;            // dense FP64 inverses of the coarsest levels
   DevMem tmp_res, tmp_dz; // extra cycles: residual and correction at level 0
   bool is_omega = false;  // hierarchy on S~ (its finest level is timed separately)
@@ -149,7 +152,7 @@ struct Batch {
   mdp_options opt{};
   DCsr<double> A;
   DevMem gidx;  // per global row: caller index within its pair's system
-  DevMem gpair; // per global row: pair
+  DevMem gpair; // per global row: pair (also the row-to-pair map of A)
   std::unique_ptr<Precond<double>> pc64;
   std::unique_ptr<Precond<float>> pc32;
   Layout layout;
