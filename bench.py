@@ -67,6 +67,8 @@ def parse():
     p.add_argument("--mode", choices=["solve", "batch", "serve"], default="solve")
     p.add_argument("--block", choices=["lower", "diag", "upper"], default="lower",
                    help="block preconditioner: M_L (eq. 8, the paper's), or the inexact B_D / B_U of Section 3.2")
+    p.add_argument("--graphs", action="store_true",
+                   help="replay each Arnoldi step from a captured HIP graph instead of launching its kernels")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the fixed rule for sparse formats instead of timing candidates at setup")
     p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
@@ -119,7 +121,7 @@ def main():
             t0 = time.perf_counter()
             A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
-            fl = L.MDP_NO_AUTOTUNE if args.no_autotune else 0
+            fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
             o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf)
             o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf)
@@ -205,7 +207,8 @@ def main():
         "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
-                   "autotune": not args.no_autotune, "block_preconditioner": args.block},
+                   "autotune": not args.no_autotune, "graphs": args.graphs,
+                   "block_preconditioner": args.block},
         "p50_ms": pct(fp["lat"], 50),
         "p99_ms": pct(fp["lat"], 99),
         "iters": sorted(set(fp["iters"])),

@@ -81,7 +81,7 @@ int check_options(const mdp_options &o) {
   if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
   if (o.max_iter < 0) return bad("max_iter must be >= 0");
   if (!(o.rtol > 0.0)) return bad("rtol must be > 0");
-  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE)) return bad("unknown bits in flags");
+  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS)) return bad("unknown bits in flags");
   if (o.block_form != MDP_BLOCK_LOWER && o.block_form != MDP_BLOCK_DIAG && o.block_form != MDP_BLOCK_UPPER)
     return bad("block_form must be MDP_BLOCK_LOWER, MDP_BLOCK_DIAG or MDP_BLOCK_UPPER");
   return MDP_OK;
@@ -294,7 +294,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     if (si.opt.precision != s0.opt.precision || si.opt.vcycles != s0.opt.vcycles ||
         si.opt.restart != s0.opt.restart || si.opt.max_iter != s0.opt.max_iter || si.opt.rtol != s0.opt.rtol ||
         si.opt.block_form != s0.opt.block_form ||
-        (si.opt.flags & MDP_USE_X0) != (s0.opt.flags & MDP_USE_X0)) {
+        (si.opt.flags & MDP_USE_X0) != (s0.opt.flags & MDP_USE_X0)) {  // graphs are not used in batches
       set_last_error("all handles of a batch need the same solve options");
       return MDP_EINVAL;
     }

@@ -344,6 +344,14 @@ __global__ __launch_bounds__(kThreads) void diag_scale_kernel(int n, const T *__
 }
 
 // y += x
+// y[0..n) = 0 (a kernel rather than a memset node, so that captured graphs
+// replay correctly).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void zero_kernel(int n, T *__restrict__ y, const int *__restrict__ gate) {
+  if (gate && *gate) return;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) y[i] = T(0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void add_kernel(int n, const T *__restrict__ x, T *__restrict__ y,
                                                        const int *__restrict__ gate) {

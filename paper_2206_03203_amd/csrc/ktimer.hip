@@ -24,6 +24,12 @@ Registry &reg() {
 
 bool ktimer_on(int kind) { return reg().on[kind]; }
 
+bool ktimer_any_on() {
+  for (int k = 0; k < kKcCount; ++k)
+    if (reg().on[k]) return true;
+  return false;
+}
+
 KtBytes ktimer_bytes() {
   Registry &r = reg();
   std::lock_guard<std::mutex> lk(r.mu);

@@ -21,6 +21,7 @@ enum KClass : int {
 };
 
 bool ktimer_on(int kind);
+bool ktimer_any_on();
 
 // Algorithmic-byte counters, saved before a batch of launches and restored
 // when those launches turn out to be retired no-ops (gated after

@@ -687,7 +687,11 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s
     if (L0.n > o)
       spmv<kResidScale>(L0.Asw, static_cast<const T *>(z) + o, r + o, dptr<const T>(L0.dinv) + o,
                         dptr<T>(H.tmp_res) + o, dptr<T>(L0.t) + o, gate, s, kKcVcycleOther);
-    if (L0.ncont < o) MDP_HIP(hipMemsetAsync(dptr<T>(H.tmp_res) + L0.ncont, 0, sizeof(T) * (o - L0.ncont), s));
+    if (L0.ncont < o) {
+      const int nz = o - L0.ncont;
+      hipLaunchKernelGGL(zero_kernel<T>, dim3(grid_for(nz)), dim3(kThreads), 0, s, nz, dptr<T>(H.tmp_res) + L0.ncont,
+                         gate.all);
+    }
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
                        gate.all);
@@ -776,6 +780,32 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
 // ---------------------------------------------------------------------------
 // FGMRES over a batch of pairs
 
+// Capture the launches that `enqueue` makes on stream s into an executable
+// graph; false (and no graph) if capture or instantiation fails.
+template <typename F>
+bool capture_step(hipGraphExec_t &out, hipStream_t s, F &&enqueue) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  try {
+    enqueue();
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  const bool ok = hipStreamEndCapture(s, &g) == hipSuccess && g != nullptr &&
+                  hipGraphInstantiate(&out, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    out = nullptr;
+    (void)hipGetLastError();
+  }
+  return ok;
+}
+
 template <typename T>
 struct Problem {
   const DCsr<double> *A;
@@ -834,6 +864,11 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     beta = bnorm;
   }
 
+  // With MDP_GRAPHS, single-system solves replay each step from a captured
+  // graph (not on the legacy stream, which cannot be captured, and not while
+  // timers run).
+  bool use_graphs = np == 1 && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed && s != nullptr;
+  if (use_graphs && ws.gexec.size() != static_cast<size_t>(2 * (m + 1))) ws.gexec.assign(2 * (m + 1), nullptr);
   while (true) {
     int nactive = 0, kmax_all = 0;
     for (int p = 0; p < np; ++p) {
@@ -855,10 +890,12 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     // Steps 0..kmax-1 apply the preconditioner; step kmax (if reached) only
     // finalises the last Hessenberg column.
     int counted = 0;  // steps whose algorithmic bytes were counted
-    for (int j = 0; j <= kmax_all; ++j) {
-      const KtBytes kt_before = ktimer_bytes();
-      ++counted;
-      T *zj = Z + std::min(j, kmax_all - 1) * ld;
+    // One Arnoldi step: preconditioner input, M z_j, w = A z_j, the fused
+    // reduction, the per-pair scalars and the update pass, then the control
+    // word to the host.  Every argument is fixed by (j, zcol) for a given
+    // workspace, so single-system solves capture the step once and replay it.
+    auto enqueue_step = [&](int j, int zcol) {
+      T *zj = Z + zcol * ld;
       const double *uj = V + j * ld;
       const T *pin;
       if constexpr (std::is_same<T, double>::value) {
@@ -902,6 +939,20 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
                            static_cast<const GmresState *>(dst));
       });
       MDP_HIP(hipMemcpyAsync(&ws.host_ctl[j], ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    };
+    for (int j = 0; j <= kmax_all; ++j) {
+      const KtBytes kt_before = ktimer_bytes();
+      ++counted;
+      const int zcol = std::min(j, kmax_all - 1);
+      if (use_graphs) {
+        hipGraphExec_t &ge = ws.gexec[(zcol == j ? 0 : m + 1) + j];
+        if (!ge && !capture_step(ge, s, [&] { enqueue_step(j, zcol); })) {
+          ws.graphs_failed = true;
+          use_graphs = false;
+        }
+        if (ge) MDP_HIP(hipGraphLaunch(ge, s));
+      }
+      if (!use_graphs) enqueue_step(j, zcol);
       MDP_HIP(hipEventRecord(ws.ev[j], s));
       if (j >= 1) {
         MDP_HIP(hipEventSynchronize(ws.ev[j - 1]));
@@ -1038,7 +1089,23 @@ void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t
   MDP_HIP(hipStreamSynchronize(s));
 }
 
+hipStream_t Workspace::own_stream() {
+  if (!own) {
+    MDP_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    MDP_HIP(hipEventCreateWithFlags(&handoff, hipEventDisableTiming));
+  }
+  return own;
+}
+
 void Workspace::release() {
+  for (hipGraphExec_t g : gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  gexec.clear();
+  graphs_failed = false;
+  if (handoff) (void)hipEventDestroy(handoff);
+  if (own) (void)hipStreamDestroy(own);
+  handoff = nullptr;
+  own = nullptr;
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   ev.clear();
   if (host_ctl) (void)hipHostFree(host_ctl);
@@ -1109,6 +1176,14 @@ void Solver::upload(hipStream_t s) {
 int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
   ensure_workspace(s);
+  // The legacy stream cannot be captured: a solve handed it runs on the
+  // workspace's own stream, after the caller's earlier work on s.
+  const hipStream_t caller = s;
+  if (s == nullptr && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed) {
+    s = ws.own_stream();
+    MDP_HIP(hipEventRecord(ws.handoff, caller));
+    MDP_HIP(hipStreamWaitEvent(s, ws.handoff, 0));
+  }
   const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
   const double *bp = b;
   double *xp = x;

@@ -112,6 +112,14 @@ struct Workspace {
   GmresState *host_state = nullptr;  // pinned, npairs
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
+  // With MDP_GRAPHS, single-system solves replay each Arnoldi step from a captured graph:
+  // gexec[j] for step j, gexec[m + 1 + j] for a cycle's last step j (which
+  // reuses preconditioned column j - 1).  Valid while the workspace lives.
+  std::vector<hipGraphExec_t> gexec;
+  bool graphs_failed = false;      // capture or instantiation failed once: launch directly
+  hipStream_t own = nullptr;       // non-blocking stream for solves handed the legacy stream
+  hipEvent_t handoff = nullptr;
+  hipStream_t own_stream();        // created on first use
   void alloc(int64_t n, int m, int npairs, int ntiles, size_t tsz, hipStream_t s);
   void release();           // free everything (alloc may be called again)
   size_t device_bytes() const;
