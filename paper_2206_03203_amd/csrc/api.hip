@@ -35,7 +35,7 @@ std::unique_ptr<BatchCache> g_batch;
 int64_t batch_max_unknowns() {
   const char *e = std::getenv("MDP_BATCH_MAX_UNKNOWNS");
   const long long v = e ? std::atoll(e) : 0;
-  return v > 0 ? v : (int64_t{24} << 20);
+  return v > 0 ? v : (int64_t{48} << 20);
 }
 }  // namespace
 

@@ -709,7 +709,12 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__res
                                                                double *__restrict__ V, int64_t ld,
                                                                const double *__restrict__ w,
                                                                const DcgsCoef *__restrict__ cf_all,
-                                                               const GmresState *__restrict__ st) {
+                                                               const GmresState *__restrict__ st,
+                                                               NextInput nin) {
+  if (nin.host_ctl && blockIdx.x == 0 && threadIdx.x == 0) {
+    *nin.host_ctl = *nin.ctl;  // final for this step: the finalise kernel ran before
+    __threadfence_system();
+  }
   const Tile tl = tiles[blockIdx.x];
   if (st[tl.pair].done) return;
   const DcgsCoef *cf = cf_all + tl.pair;
@@ -757,9 +762,18 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__res
 #pragma unroll
   for (int k = 0; k < kDotU; ++k) {
     if (k * kThreads < lim) {
+      const int64_t e = base + k * kThreads;
       const double qj = uu[k] * inv_r;
-      u[base + k * kThreads] = qj;
-      un[base + k * kThreads] = (ww[k] - hj * qj) * inv_nu;
+      u[e] = qj;
+      const double next = (ww[k] - hj * qj) * inv_nu;
+      un[e] = next;
+      if (nin.rin) {  // same arithmetic as cast_start_kernel
+        const float v = static_cast<float>(next);
+        nin.rin[e] = v;
+        if (nin.t32 && e < nin.n_o) nin.t32[e] = v * nin.dinv32[e];
+      } else if (nin.t64 && e < nin.n_o) {  // same arithmetic as diag_scale_kernel
+        nin.t64[e] = next * nin.dinv64[e];
+      }
     }
   }
 }

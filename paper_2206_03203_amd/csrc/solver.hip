@@ -898,19 +898,23 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
       T *zj = Z + zcol * ld;
       const double *uj = V + j * ld;
       const T *pin;
+      // The preconditioner input of step j > 0 was written by the update pass
+      // of step j - 1 (see NextInput); the first step of a cycle prepares it here.
       if constexpr (std::is_same<T, double>::value) {
         pin = uj;
-        start_smoother(P.Ho, pin, g_apply, s);
+        if (j == 0) start_smoother(P.Ho, pin, g_apply, s);
       } else {
-        T *rin = dptr<T>(ws.rin);
-        const int no = P.n_o;
-        const bool need_t = !P.Ho.dense_only();
-        timed_launch(kKcOther, s, 12.0 * n + 8.0 * no, [&] {
-          hipLaunchKernelGGL(cast_start_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, no, uj, rin,
-                             dptr<const float>(P.Ho.lv[0].dinv), need_t ? dptr<float>(P.Ho.lv[0].t) : nullptr,
-                             gate_apply);
-        });
-        pin = rin;
+        pin = dptr<T>(ws.rin);
+        if (j == 0) {
+          T *rin = dptr<T>(ws.rin);
+          const int no = P.n_o;
+          const bool need_t = !P.Ho.dense_only();
+          timed_launch(kKcOther, s, 12.0 * n + 8.0 * no, [&] {
+            hipLaunchKernelGGL(cast_start_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, no, uj, rin,
+                               dptr<const float>(P.Ho.lv[0].dinv), need_t ? dptr<float>(P.Ho.lv[0].t) : nullptr,
+                               gate_apply);
+          });
+        }
       }
       apply_ml(P, pin, zj, g_apply, s);
       spmv<kPlain>(A, static_cast<const T *>(zj), cnull<double>(), cnull<double>(), w, mnull<double>(), g_apply,
@@ -933,12 +937,34 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
                            m, dptr<double>(ws.cs), dptr<double>(ws.sn), dptr<double>(ws.g), dptr<double>(ws.hist),
                            ws.ldv);
       });
-      timed_launch(kKcArnoldiAxpy, s, 8.0 * n * (j + 4), [&] {
+      // the update pass also writes step j + 1's preconditioner input and
+      // sends this step's control word to the host
+      NextInput nin{};
+      double next_bytes = 0.0;
+      const bool need_t = !P.Ho.dense_only();
+      if constexpr (std::is_same<T, double>::value) {
+        if (need_t) {
+          nin.t64 = dptr<double>(P.Ho.lv[0].t);
+          nin.dinv64 = dptr<const double>(P.Ho.lv[0].dinv);
+          next_bytes = 16.0 * P.n_o;
+        }
+      } else {
+        nin.rin = dptr<float>(ws.rin);
+        next_bytes = 4.0 * n;
+        if (need_t) {
+          nin.t32 = dptr<float>(P.Ho.lv[0].t);
+          nin.dinv32 = dptr<const float>(P.Ho.lv[0].dinv);
+          next_bytes += 8.0 * P.n_o;
+        }
+      }
+      nin.n_o = P.n_o;
+      nin.host_ctl = ws.host_ctl_dev + j;
+      nin.ctl = ctl;
+      timed_launch(kKcArnoldiAxpy, s, 8.0 * n * (j + 4) + next_bytes, [&] {
         hipLaunchKernelGGL(dcgs_update_kernel, dim3(L.ntiles), dim3(kThreads), 0, s, tiles, j, V, ld,
                            static_cast<const double *>(w), dptr<const DcgsCoef>(ws.coef),
-                           static_cast<const GmresState *>(dst));
+                           static_cast<const GmresState *>(dst), nin);
       });
-      MDP_HIP(hipMemcpyAsync(&ws.host_ctl[j], ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     };
     for (int j = 0; j <= kmax_all; ++j) {
       const KtBytes kt_before = ktimer_bytes();
@@ -1081,7 +1107,10 @@ void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t
   tolp.alloc(static_cast<size_t>(np) * sizeof(double));
   active.alloc(static_cast<size_t>(np) * sizeof(int));
   norms.alloc(static_cast<size_t>(np) * sizeof(double));
-  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_ctl), (m + 2) * sizeof(BatchCtl), hipHostMallocDefault));
+  // written by the update kernel through its device address (mapped, coherent)
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_ctl), (m + 2) * sizeof(BatchCtl),
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  MDP_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&host_ctl_dev), host_ctl, 0));
   MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_state), np * sizeof(GmresState), hipHostMallocDefault));
   MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_norms), np * sizeof(double), hipHostMallocDefault));
   ev.resize(static_cast<size_t>(m) + 2);
@@ -1112,6 +1141,7 @@ void Workspace::release() {
   if (host_state) (void)hipHostFree(host_state);
   if (host_norms) (void)hipHostFree(host_norms);
   host_ctl = nullptr;
+  host_ctl_dev = nullptr;
   host_state = nullptr;
   host_norms = nullptr;
   for (DevMem *d : {&V, &Z, &w, &rin, &bp, &xp, &Hr, &cs, &sn, &g, &y, &hist, &hprev, &coef, &sums, &partial, &npart,

@@ -109,6 +109,7 @@ struct Workspace {
   DevMem partial, npart;
   DevMem state, ctl, kmaxp, tolp, active, norms;
   BatchCtl *host_ctl = nullptr;      // pinned, one slot per step
+  BatchCtl *host_ctl_dev = nullptr;  // its device address
   GmresState *host_state = nullptr;  // pinned, npairs
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;

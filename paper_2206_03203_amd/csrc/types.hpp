@@ -32,6 +32,22 @@ struct BatchCtl {
   int all_done;        // set when ndone reaches the number of pairs
 };
 
+// What the update pass of step j also writes for step j + 1 (all fields may
+// be NULL): the preconditioner input in mixed precision (FP32 copy of
+// u_{j+1}, and D^-1 of it on the first n_o rows, the host block), or in FP64
+// the first smoothing iterate D^-1 u_{j+1} on those rows; and the step's
+// control word, copied to the host (device-visible pinned memory).
+struct NextInput {
+  float *rin;
+  float *t32;
+  const float *dinv32;
+  double *t64;
+  const double *dinv64;
+  int64_t n_o;
+  BatchCtl *host_ctl;
+  const BatchCtl *ctl;
+};
+
 // A contiguous piece (at most kTileElems entries) of one (system, rhs) pair's
 // unknowns in the global vector layout.
 struct Tile {
