@@ -8,7 +8,9 @@
  * inexact block lower-triangular preconditioner M_L of eq. (8), applied as
  * Algorithm 1: Q_OO = smoothed-aggregation AMG V-cycles on the approximate
  * Schur complement S~ of eq. (7), the fracture residual update with A_GO,
- * and Q_GG = V-cycles on A_GG (Section 3.3).
+ * and Q_GG = V-cycles on A_GG (Section 3.3).  The other two block forms of
+ * Section 3.2 (block diagonal, block upper) are available with the same
+ * Q's (mdp_options.block_form).
  *
  * Conventions for every call:
  *  - Sparse inputs are 0-based CSR in HOST memory, int32 indices, FP64 values.
@@ -64,10 +66,10 @@ extern "C" {
                               on 100^3 systems: about 2% more. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
-                              (CSR with 2..64 lanes per row and 4 or 8
-                              entries in flight per lane, one thread per row,
-                              sliced ELL) on the device and keeping the
-                              fastest.  The format changes only the order of
+                              (diagonal storage for stencil matrices, sliced
+                              ELL, CSR with one thread per row, CSR with 2..64
+                              lanes per row and 4 or 8 entries in flight per
+                              lane) on the device and keeping the fastest.  The format changes only the order of
                               the additions in each row; equal matrices get
                               equal formats within a process. */
 
@@ -140,7 +142,9 @@ int mdp_options_default(mdp_options *opt);
  * unknown, 1 a fracture/interface (Gamma) unknown.  Setup (host C++):
  * stable [Omega; Gamma] permutation, the four blocks, S~ of eq. (7) with
  * diag(A_GG), SA-AMG hierarchies on S~ and A_GG (Section 3.3), dense inverse
- * of each coarsest level, then one upload to the device on hip_stream.
+ * of each coarsest level, then one upload to the device on hip_stream, where
+ * each matrix of at least 32k entries gets the fastest of its candidate
+ * device formats, timed there (see MDP_NO_AUTOTUNE).
  * n_Gamma = 0 is allowed (M_L is then the AMG on A_OO).  A nonsymmetric A is
  * accepted (the paper does not rely on A_OG = A_GO^T).
  * Errors: EINVAL (NULL, n <= 0, malformed CSR, part not 0/1, bad options),
@@ -189,10 +193,17 @@ int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
 
 /* Solve several independent systems together: system s has nrhs[s]
  * right-hand sides in b_dev[s] / x_dev[s] (column-major, leading dimension
- * its own n).  All handles must share one precision.  Every (system, rhs)
- * pair advances in lock step; each gets the same answer as a solve of its
- * own (per-pair reductions never mix pairs).  stats has sum(nrhs) entries in
- * system-major order.  Synchronises hip_stream. */
+ * its own n).  All handles must share precision, block form, V-cycles,
+ * restart, max_iter, rtol and MDP_USE_X0 (EINVAL otherwise).  The pairs
+ * (system, rhs) are concatenated block-diagonally and every sparse product
+ * runs once for all of them; each pair has its own Krylov process (per-pair
+ * reductions never mix pairs), so its iterates are those of a solve of its
+ * own up to the rounding of the sparse products, and a pair that has stopped
+ * is skipped row by row.  Batches above MDP_BATCH_MAX_UNKNOWNS unknowns (an
+ * environment variable, default 48 Mi) run as consecutive chunks on one
+ * workspace; the plan is kept while the same handles and counts come back.
+ * stats has sum(nrhs) entries in system-major order.  Synchronises
+ * hip_stream. */
 int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b_dev,
                     double *const *x_dev, const int32_t *nrhs, void *hip_stream,
                     mdp_stats *stats);
@@ -272,7 +283,8 @@ int mdp_server_destroy(mdp_server *srv);
 #define MDP_KC_FINE_RESID 6    /* finest S~ level: residual after the first sweep, whose
                                   iterate D^-1 b the producer of b has written already   */
 
-/* Start timing every launch of one kernel class (process-wide): HIP events
+/* Start timing every launch of one kernel class (process-wide; not for use
+ * while server slots are solving): HIP events
  * are recorded around each launch on the stream it is launched on, and the
  * launch's algorithmic bytes (each matrix value/index and each vector read
  * or written once) are accumulated.  Resets the class's counters. */
