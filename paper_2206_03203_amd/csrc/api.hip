@@ -282,7 +282,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
   std::vector<const Solver *> pairs;
   std::vector<PairIO> io;
   for (int32_t i = 0; i < nsys; ++i) {
-    if (!hs[i] || !b[i] || !x[i] || nrhs[i] < 0) {
+    if (!hs[i] || nrhs[i] < 0 || (nrhs[i] > 0 && (!b[i] || !x[i]))) {  // no vectors needed for nrhs 0
       set_last_error("bad batch entry " + std::to_string(i));
       return MDP_EINVAL;
     }

@@ -100,10 +100,11 @@ def assemble(sc, sources: Optional[List[np.ndarray]] = None):
         # move the face axis first, tangential axes after in increasing order
         perm = [npax] + [dim - 1 - a for a in tang]
         cells = np.transpose(idx, perm)          # [q][t1][t2]
-        left = cells[:-1].reshape(n - 1, -1)     # cells q-1 for q = 1..n-1
-        right = cells[1:].reshape(n - 1, -1)
+        per_face = n ** (dim - 1)                # cells per layer (explicit: n = 1 has no interior faces)
+        left = cells[:-1].reshape(n - 1, per_face)  # cells q-1 for q = 1..n-1
+        right = cells[1:].reshape(n - 1, per_face)
         # face_id is indexed [q][t1][t2] with t1 the first tangential axis
-        fid = face_id[axis][1:n].reshape(n - 1, -1)
+        fid = face_id[axis][1:n].reshape(n - 1, per_face)
         L, R, F = left.ravel(), right.ravel(), fid.ravel()
         plain = F < 0
         tl, tr = t[L[plain]], t[R[plain]]

@@ -18,6 +18,11 @@ CASES = [
     lambda: synth.random_2d(1, n_range=(20, 40)),
     lambda: synth.random_2d(7, n_range=(20, 40)),
     lambda: synth.random_3d(3, n_range=(8, 12)),
+    # degenerate grids: one cell (no interior face), one fracture cell
+    lambda: synth.Scenario(2, 1, np.ones(1), [], {(0, 0): 1.0, (0, 1): 0.0}),
+    lambda: synth.Scenario(3, 1, np.ones(1), [], {(0, 0): 1.0, (0, 1): 0.0}),
+    lambda: synth.Scenario(2, 2, np.ones(4), [synth.Fracture(0, 1, (0,), (1,), 10.0, 0.5, 1e-2)],
+                           {(0, 0): 1.0, (0, 1): 0.0}),
 ]
 
 

@@ -1,0 +1,114 @@
+"""Edge cases of the GPU path against the oracle (dense LAPACK solutions of
+the oracle's own assembly): the smallest systems (one host cell; one
+fracture cell), sizes on and just past a reduction-tile boundary, an empty
+batch and systems with no right-hand side in a batch, a batch mixing a zero
+right-hand side with others, and an exhausted iteration budget."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from synth import Fracture, Scenario
+from oracle import assembly as oa
+from oracle import solve as osv
+from paper_2206_03203_amd import _lib as L
+from paper_2206_03203_amd import tpfa
+from paper_2206_03203_amd.solver import Solver
+
+from gpu_common import dev, host, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+DIR = {(0, 0): 1.0, (0, 1): 0.0}
+
+
+def _tiny_cases():
+    return {
+        "one-host-cell": Scenario(2, 1, np.ones(1), [], DIR),
+        "one-fracture-cell": Scenario(2, 2, np.ones(4), [Fracture(0, 1, (0,), (1,), 10.0, 0.5, 1e-2)], DIR),
+        "tile-1024": Scenario(2, 32, np.ones(1024), [], DIR),
+        "tile-1024-plus-1": Scenario(2, 32, np.ones(1024), [Fracture(1, 9, (4,), (5,), 3.0, 2.0, 1e-3)], DIR),
+        "3d-one-cell": Scenario(3, 1, np.ones(1), [], DIR),
+    }
+
+
+@pytest.mark.parametrize("name", list(_tiny_cases()))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smallest_and_tile_boundary_systems(name, prec):
+    sc = _tiny_cases()[name]
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    x_ref = osv.solve_dense(Ao, bo)
+    say(f"[edges] {name} n={A.shape[0]} prec={prec}")
+    s = Solver(A, part, precision=prec)
+    try:
+        x, st = s.solve(dev(b))
+        assert st[0]["converged"] == 1
+        assert np.linalg.norm(bo - Ao @ host(x)) <= 1e-8 * np.linalg.norm(bo)
+        assert relerr(host(x), x_ref) <= 1e-6
+    finally:
+        s.close()
+
+
+def test_empty_batches():
+    sc = synth.grid_2d_four_lines(16)
+    A, b, part = tpfa.assemble(sc)
+    s1 = Solver(A, part)
+    s2 = Solver(A, part)
+    say("[edges] empty batches")
+    try:
+        rc = L.lib.mdp_solve_batch(None, 0, None, None, None, None, None)
+        assert rc == L.MDP_EINVAL  # NULL arrays are refused even when empty
+        bt = dev(b)
+        empty = torch.empty((0, A.shape[0]), dtype=torch.float64, device="cuda:0")
+        rc, st = L.mdp_solve_batch([s1.handle, s2.handle], [empty, empty], [empty.clone(), empty.clone()])
+        assert rc == L.MDP_OK and st == []  # nothing to solve
+        x = torch.zeros_like(bt)
+        rc, st = L.mdp_solve_batch([s1.handle, s2.handle], [empty, bt], [empty.clone(), x])
+        assert rc == L.MDP_OK and st[0]["converged"] == 1
+        x1, _ = s1.solve(bt)
+        assert relerr(host(x), host(x1)) <= 1e-6
+    finally:
+        s1.close()
+        s2.close()
+
+
+def test_batch_with_zero_right_hand_side():
+    scs = [synth.grid_2d_four_lines(16), synth.regular_3d(n=10, seed=2)]
+    solvers, bs = [], []
+    for sc in scs:
+        A, b, part = tpfa.assemble(sc)
+        solvers.append(Solver(A, part, precision="mixed"))
+        bs.append(dev(b))
+    bs[0] = torch.zeros_like(bs[0])
+    xs = [torch.full_like(b, 7.0) for b in bs]
+    say("[edges] batch with a zero rhs")
+    try:
+        rc, st = L.mdp_solve_batch([s.handle for s in solvers], bs, xs)
+        assert rc == L.MDP_OK
+        assert st[0]["iters"] == 0 and st[0]["converged"] == 1 and not host(xs[0]).any()
+        x1, _ = solvers[1].solve(bs[1])
+        assert st[1]["converged"] == 1 and relerr(host(xs[1]), host(x1)) <= 1e-6
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_iteration_budget_exhausted():
+    sc = synth.regular_3d(n=12, k_par=1e4, kappa=1e4, seed=1)
+    A, b, part = tpfa.assemble(sc)
+    say("[edges] max_iter 0 and 3")
+    for mi in (0, 3):
+        s = Solver(A, part, max_iter=mi)
+        try:
+            x, st = s.solve(dev(b))
+            assert st[0]["converged"] == 0 and st[0]["status"] == L.MDP_NOT_CONVERGED
+            assert st[0]["iters"] == mi
+            if mi == 0:
+                assert not host(x).any()
+            else:
+                r = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+                assert abs(r - st[0]["rel_res_true"]) <= 1e-12 and r < 1.0
+        finally:
+            s.close()
