@@ -635,11 +635,16 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
     const double nu = st->nu;
     for (int i = 0; i < j; ++i) col[i] += nu * a[i];
     col[j] = nu * r;
+    // apply the stored rotations; the rotated entry carried to the next
+    // rotation stays in a register
+    double cur = col[0];
     for (int i = 0; i + 1 < j; ++i) {
-      const double tt = sc[i] * col[i] + ss[i] * col[i + 1];
-      col[i + 1] = -ss[i] * col[i] + sc[i] * col[i + 1];
+      const double nxt = col[i + 1];
+      const double tt = sc[i] * cur + ss[i] * nxt;
+      cur = -ss[i] * cur + sc[i] * nxt;
       col[i] = tt;
     }
+    col[j - 1] = cur;
     double c, s, rr;
     givens(col[j - 1], col[j], c, s, rr);
     cs[j - 1] = c;
@@ -660,7 +665,8 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
       pair_finish(st, ctl, npairs);
       return;
     }
-    for (int i = 0; i < j; ++i) sc[i] = cs[i], ss[i] = sn[i];
+    sc[j - 1] = c;  // the rotations now include the one just formed
+    ss[j - 1] = s;
   }
   // provisional column j
   double sh = 0.0;
@@ -675,13 +681,11 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
   const bool brk = !(nu2 > 1e-24 * gamma);
   const double nu = sqrt(brk ? fmax(1e-24 * gamma, 1e-300) : nu2);
   for (int i = 0; i <= j; ++i) hprev[i] = col[i];
-  for (int i = 0; i < j; ++i) {
-    const double tt = sc[i] * col[i] + ss[i] * col[i + 1];
-    col[i + 1] = -ss[i] * col[i] + sc[i] * col[i + 1];
-    col[i] = tt;
-  }
+  // only the last entry of the rotated provisional column is needed: carry it
+  double cur = col[0];
+  for (int i = 0; i < j; ++i) cur = -ss[i] * cur + sc[i] * col[i + 1];
   double c, s, rr;
-  givens(col[j], nu, c, s, rr);
+  givens(cur, nu, c, s, rr);
   const double est_next = fabs(s * g[j]);
   bad = bad || !isfinite(hj) || !isfinite(nu) || !(r > 0.0);
   cf->inv_r = 1.0 / r;
