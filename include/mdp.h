@@ -199,11 +199,14 @@ int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
  * runs once for all of them; each pair has its own Krylov process (per-pair
  * reductions never mix pairs), so its iterates are those of a solve of its
  * own up to the rounding of the sparse products, and a pair that has stopped
- * is skipped row by row.  Batches above MDP_BATCH_MAX_UNKNOWNS unknowns (an
- * environment variable, default 48 Mi) run as consecutive chunks on one
- * workspace; the plan is kept while the same handles and counts come back.
- * stats has sum(nrhs) entries in system-major order.  Synchronises
- * hip_stream. */
+ * is skipped row by row.  When every system of a batch (or chunk) has
+ * exactly four right-hand sides, the preconditioner's matrices are stored
+ * once and each sparse product applies them to all four.  Batches above
+ * MDP_BATCH_MAX_UNKNOWNS unknowns (an environment variable, default 48 Mi)
+ * run as consecutive chunks on one workspace, cut between systems where a
+ * system's right-hand sides fit together; the plan is kept while the same
+ * handles, counts and bound come back.  stats has sum(nrhs) entries in
+ * system-major order.  Synchronises hip_stream. */
 int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b_dev,
                     double *const *x_dev, const int32_t *nrhs, void *hip_stream,
                     mdp_stats *stats);

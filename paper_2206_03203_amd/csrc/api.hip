@@ -21,10 +21,11 @@ AllocHook g_hook;
 
 // The most recent batch plan: block-diagonal concatenations of the pairs of
 // the last mdp_solve_batch call, split into chunks of bounded size.  Reused
-// while the same handles and right-hand-side counts come back.
+// while the same handles, right-hand-side counts and chunk bound come back.
 struct BatchCache {
   std::vector<const mdp_handle *> handles;
   std::vector<int32_t> nrhs;
+  int64_t cap = 0;
   Workspace shared;  // Krylov workspace sized for the largest chunk (chunks run one after another)
   std::vector<std::unique_ptr<Batch>> chunks;
   std::vector<int> first_pair;  // per chunk
@@ -308,22 +309,46 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
   std::lock_guard<std::mutex> lk(g_batch_mu);
   const std::vector<const mdp_handle *> key_h(hs, hs + nsys);
   const std::vector<int32_t> key_r(nrhs, nrhs + nsys);
-  if (!g_batch || g_batch->handles != key_h || g_batch->nrhs != key_r) {
+  const int64_t cap = batch_max_unknowns();
+  if (!g_batch || g_batch->handles != key_h || g_batch->nrhs != key_r || g_batch->cap != cap) {
     g_batch.reset();
     auto bc = std::make_unique<BatchCache>();
     bc->handles = key_h;
     bc->nrhs = key_r;
-    const int64_t cap = batch_max_unknowns();
-    size_t p0 = 0;
-    while (p0 < pairs.size()) {
-      size_t p1 = p0;
-      int64_t tot = 0;
-      while (p1 < pairs.size() && (p1 == p0 || tot + pairs[p1]->n <= cap)) tot += pairs[p1++]->n;
+    bc->cap = cap;
+    // Chunks of at most `cap` unknowns (or one pair), cut between systems
+    // where possible, so that a system's right-hand sides stay in one chunk
+    // and share its preconditioner's matrix reads; a system whose right-hand
+    // sides exceed `cap` together is split between them.
+    std::vector<std::pair<size_t, size_t>> cuts;
+    size_t p0 = 0, pi = 0;
+    int64_t tot = 0;
+    auto cut = [&] {
+      if (pi > p0) cuts.emplace_back(p0, pi);
+      p0 = pi;
+      tot = 0;
+    };
+    for (int32_t i = 0; i < nsys; ++i) {
+      if (nrhs[i] == 0) continue;
+      const int64_t ni = hs[i]->s.n, group = ni * nrhs[i];
+      if (tot + group > cap) cut();
+      if (group <= cap) {
+        tot += group;
+        pi += static_cast<size_t>(nrhs[i]);
+        continue;
+      }
+      for (int32_t k = 0; k < nrhs[i]; ++k) {
+        if (tot + ni > cap) cut();
+        tot += ni;
+        ++pi;
+      }
+    }
+    cut();
+    for (const auto &c : cuts) {
       auto bt = std::make_unique<Batch>();
-      bt->build(std::vector<const Solver *>(pairs.begin() + p0, pairs.begin() + p1), s, false);
-      bc->first_pair.push_back(static_cast<int>(p0));
+      bt->build(std::vector<const Solver *>(pairs.begin() + c.first, pairs.begin() + c.second), s, false);
+      bc->first_pair.push_back(static_cast<int>(c.first));
       bc->chunks.push_back(std::move(bt));
-      p0 = p1;
     }
     int64_t nmax = 0;
     int pmax = 0, tmax = 0;

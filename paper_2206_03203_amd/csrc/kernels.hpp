@@ -55,12 +55,28 @@ enum SpmvMode : int {
   kResidScale = 6,  // y = b - A x ; y2 = dinv .* y     (residual that also starts the next smoother)
 };
 
-// Batched solves: a row whose pair has stopped applying the preconditioner is
-// skipped (its output is no longer read).  rpair maps rows to pairs and pst
-// holds the pairs' states; either is NULL when rows are not gated.
-__device__ __forceinline__ bool row_stopped(int row, const int *__restrict__ rpair,
-                                            const GmresState *__restrict__ pst) {
-  return rpair && pst && pst[rpair[row]].skip_apply;
+// Vector blocks of a sparse product: KB right-hand-side blocks share one
+// matrix read; block r of x starts at r * xs, block r of b, dinv, y and y2
+// at r * ys.  Batched solves skip, per block, the rows of pairs that have
+// stopped applying the preconditioner (their output is no longer read): the
+// pair of row i in block r is r * nsys + rpair[i] (rpair maps rows to
+// systems; NULL means system 0).  Gating needs pst, and rpair or KB > 1.
+struct Blocks {
+  int64_t xs, ys;
+  int nsys;
+};
+
+template <int KB>
+__device__ __forceinline__ bool block_live(int row, int r, const int *__restrict__ rpair,
+                                           const GmresState *__restrict__ pst, const Blocks &bk) {
+  if (!pst || (!rpair && KB == 1)) return true;
+  const int rp = rpair ? rpair[row] : 0;
+  return !pst[r * bk.nsys + rp].skip_apply;
+}
+
+template <typename P>
+__device__ __forceinline__ P *blk(P *p, int64_t off) {
+  return p ? p + off : p;
 }
 
 // Per-row epilogue shared by the sparse kernels.
@@ -102,20 +118,26 @@ __device__ __forceinline__ Acc spmv_gather(int c, const TX *__restrict__ x, cons
 // entries in flight (indices and values loaded before the gathers).
 constexpr int kCsrBatch = 4;  // the fixed rule's batch
 
-template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
+template <int LPR, int BATCH, int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void spmv_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
     TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
-    const GmresState *__restrict__ pst) {
+    const GmresState *__restrict__ pst, Blocks bk) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int row = blk * (kThreads / LPR) + static_cast<int>(threadIdx.x) / LPR;
+  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk_id * (kThreads / LPR) + static_cast<int>(threadIdx.x) / LPR;
   const int lane = threadIdx.x % LPR;
-  if (row >= nr || row_stopped(row, rpair, pst)) return;  // whole LPR groups leave together
+  if (row >= nr) return;  // whole LPR groups leave together
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
   const int s = ptr[row], e = ptr[row + 1];
-  Acc sum = 0;
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
   for (int p0 = s + lane; p0 < e; p0 += BATCH * LPR) {
     int c[BATCH];
     Acc v[BATCH];
@@ -127,10 +149,20 @@ __global__ __launch_bounds__(kThreads) void spmv_kernel(
       v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
     }
 #pragma unroll
-    for (int k = 0; k < BATCH; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k)
+          sum[r] += v[k] * spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
   }
-  sum = group_sum<LPR>(sum);
-  if (lane == 0) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = group_sum<LPR>(sum[r]);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+        spmv_store<MODE, Acc>(row, sum[r], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                              blk(y2, r * bk.ys));
 }
 
 // Sliced ELL (slices of 64 rows = one wavefront, one thread per row): entry k
@@ -140,22 +172,28 @@ __global__ __launch_bounds__(kThreads) void spmv_kernel(
 // kSellBatch so that many gathers are in flight per thread.
 constexpr int kSellBatch = 8;
 
-template <int MODE, typename TA, typename TX, typename TY>
+template <int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void sell_kernel(
     int nr, int nslices, const int *__restrict__ soff, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
     TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
-    const GmresState *__restrict__ pst) {
+    const GmresState *__restrict__ pst, Blocks bk) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int slice = blk * (kThreads / 64) + static_cast<int>(threadIdx.x) / 64;
+  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
+  const int slice = blk_id * (kThreads / 64) + static_cast<int>(threadIdx.x) / 64;
   const int lane = threadIdx.x % 64;
   if (slice >= nslices) return;
   const int o0 = soff[slice], o1 = soff[slice + 1];
   const int row = slice * 64 + lane;
-  if (row < nr && row_stopped(row, rpair, pst)) return;
-  Acc sum = 0;
+  if (row >= nr) return;
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
   // kSellBatch entries per step, the last step predicated (past the slice
   // width: value 0 and this lane's first column), so that all index and
   // value loads of a short row are in flight together
@@ -169,9 +207,17 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
       v[k] = q < o1 ? static_cast<Acc>(val[q]) : Acc(0);
     }
 #pragma unroll
-    for (int k = 0; k < kSellBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < kSellBatch; ++k)
+          sum[r] += v[k] * spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
   }
-  if (row < nr) spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+#pragma unroll
+  for (int r = 0; r < KB; ++r)
+    if (live[r])
+      spmv_store<MODE, Acc>(row, sum[r], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                            blk(y2, r * bk.ys));
 }
 
 // Diagonal storage for stencil matrices: entry (i, i + off[d]) is stored at
@@ -182,32 +228,50 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
 constexpr int kMaxDiag = 16;
 constexpr int kDiaBatch = 8;
 
-template <int MODE, typename TA, typename TX, typename TY>
+template <int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void dia_kernel(
     int nr, int nc, int ndiag, const int *__restrict__ off, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
     TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
-    const GmresState *__restrict__ pst) {
+    const GmresState *__restrict__ pst, Blocks bk) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int row = blk * kThreads + static_cast<int>(threadIdx.x);
-  if (row >= nr || row_stopped(row, rpair, pst)) return;
-  Acc sum = 0;
+  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk_id * kThreads + static_cast<int>(threadIdx.x);
+  if (row >= nr) return;
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
   for (int d0 = 0; d0 < ndiag; d0 += kDiaBatch) {
-    Acc v[kDiaBatch], xv[kDiaBatch];
+    int c[kDiaBatch];
+    bool in[kDiaBatch];
+    Acc v[kDiaBatch];
 #pragma unroll
     for (int k = 0; k < kDiaBatch; ++k) {
       const int d = d0 + k;
-      const int c = d < ndiag ? row + off[d] : row;
-      const bool in = d < ndiag && c >= 0 && c < nc;
-      v[k] = in ? static_cast<Acc>(val[static_cast<int64_t>(d) * nr + row]) : Acc(0);
-      xv[k] = in ? spmv_gather<MODE, Acc>(c, x, b, dinv) : Acc(0);
+      c[k] = d < ndiag ? row + off[d] : row;
+      in[k] = d < ndiag && c[k] >= 0 && c[k] < nc;
+      v[k] = in[k] ? static_cast<Acc>(val[static_cast<int64_t>(d) * nr + row]) : Acc(0);
     }
 #pragma unroll
-    for (int k = 0; k < kDiaBatch; ++k) sum += v[k] * xv[k];
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < kDiaBatch; ++k) {
+          const Acc xv =
+              in[k] ? spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys)) : Acc(0);
+          sum[r] += v[k] * xv;
+        }
   }
-  spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+#pragma unroll
+  for (int r = 0; r < KB; ++r)
+    if (live[r])
+      spmv_store<MODE, Acc>(row, sum[r], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                            blk(y2, r * bk.ys));
 }
 
 // CSR with one thread per row, for short rows of uneven length (where slices
@@ -215,19 +279,25 @@ __global__ __launch_bounds__(kThreads) void dia_kernel(
 // predicated on the row length.
 constexpr int kScalarBatch = 4;
 
-template <int MODE, typename TA, typename TX, typename TY>
+template <int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
     int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
     TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
-    const GmresState *__restrict__ pst) {
+    const GmresState *__restrict__ pst, Blocks bk) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int row = blk * kThreads + static_cast<int>(threadIdx.x);
-  if (row >= nr || row_stopped(row, rpair, pst)) return;
+  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk_id * kThreads + static_cast<int>(threadIdx.x);
+  if (row >= nr) return;
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
   const int s = ptr[row], e = ptr[row + 1];
-  Acc sum = 0;
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
   for (int p0 = s; p0 < e; p0 += kScalarBatch) {
     int c[kScalarBatch];
     Acc v[kScalarBatch];
@@ -238,9 +308,17 @@ __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
       v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
     }
 #pragma unroll
-    for (int k = 0; k < kScalarBatch; ++k) sum += v[k] * spmv_gather<MODE, Acc>(c[k], x, b, dinv);
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < kScalarBatch; ++k)
+          sum[r] += v[k] * spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
   }
-  spmv_store<MODE, Acc>(row, sum, x, b, dinv, y, y2);
+#pragma unroll
+  for (int r = 0; r < KB; ++r)
+    if (live[r])
+      spmv_store<MODE, Acc>(row, sum[r], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                            blk(y2, r * bk.ys));
 }
 
 // Coarsest level: x = Ainv b with a dense FP64 inverse (row-major n x n); one

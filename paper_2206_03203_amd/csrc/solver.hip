@@ -332,20 +332,35 @@ LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
   return pl;
 }
 
+// Distance between the two ping-pong buffers of a level's swept coarsest
+// systems: their rows, or with kb blocks a whole level vector (block r of a
+// buffer starts r * n further on).
+template <typename T>
+int64_t sweep_stride(const DLevel<T> &L, int kb) {
+  return kb == 1 ? L.n - L.sw_off : static_cast<int64_t>(kb) * L.n;
+}
+
+// Upload a batch of hierarchies laid out by `pl`.  kb > 1: every level
+// vector holds kb blocks of that layout (one per right-hand side) and the
+// matrices, stored once, carry the blocks' strides.  pair_of (batches): the
+// system of each hierarchy, for the row-to-system maps that gate stopped
+// pairs' rows (pair of a row in block r = r * nsys + its system).
 template <typename T>
 void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep,
-                 const std::vector<int> *pair_of = nullptr) {
+                 const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
   const size_t L = pl.order.size();
   d.lv.clear();
   d.lv.resize(L);
+  d.kb = kb;
   std::vector<double> cinv;
   for (size_t l = 0; l < L; ++l) {
     DLevel<T> &dl = d.lv[l];
     dl.n = pl.n[l];
     dl.ncont = pl.ncont[l];
     dl.sw_off = pl.sw_off[l];
+    const size_t nfull = static_cast<size_t>(kb) * dl.n;
     std::vector<Piece> pa, pp, pr, psw;
-    std::vector<T> dinv(static_cast<size_t>(dl.n));
+    std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
     for (int p : pl.order[l]) {
       const HHier &h = *hs[p];
@@ -358,13 +373,15 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
         pp.emplace_back(&hl.P, o, oc);
         pr.emplace_back(&hl.R, oc, o);
       } else if (h.dense) {
-        desc.push_back(DenseDesc{o, hl.A.nr, static_cast<int64_t>(cinv.size())});
+        for (int r = 0; r < kb; ++r)
+          desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
         cinv.insert(cinv.end(), h.coarse_inv.begin(), h.coarse_inv.end());
         dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
       } else {
         psw.emplace_back(&hl.A, o - dl.sw_off, o - dl.sw_off);
       }
     }
+    for (int r = 1; r < kb; ++r) std::copy(dinv.begin(), dinv.begin() + dl.n, dinv.begin() + r * dl.n);
     upload_csr(concat_blocks(dl.ncont, dl.ncont, pa), dl.A, s, keep);
     if (l + 1 < L) {
       upload_csr(concat_blocks(dl.ncont, pl.n[l + 1], pp), dl.P, s, keep);
@@ -374,19 +391,32 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     dl.ndense = static_cast<int32_t>(desc.size());
     upload_vec(dl.dense, keep.put(std::move(desc)), s);
     upload_vec(dl.dinv, keep.put(std::move(dinv)), s);
-    const size_t nb = static_cast<size_t>(std::max(dl.n, 1)) * sizeof(T);
+    const size_t nb = std::max<size_t>(nfull, 1) * sizeof(T);
     dl.x.alloc(nb);
     dl.b.alloc(nb);
     dl.t.alloc(nb);
     dl.r.alloc(nb);
-    if (dl.n > dl.sw_off) dl.pp.alloc(2 * static_cast<size_t>(dl.n - dl.sw_off) * sizeof(T));
+    if (dl.n > dl.sw_off) dl.pp.alloc(2 * sweep_stride(dl, kb) * sizeof(T));
+    // block strides: x of A, P, R and Asw lives on levels l, l + 1, l and l;
+    // their b / dinv / y on levels l, l, l + 1 and l
+    const int64_t nl = dl.n, nc = l + 1 < L ? pl.n[l + 1] : 0;
+    auto blocks = [&](DCsr<T> &M, int64_t xs, int64_t ys) {
+      M.kb = kb;
+      M.bxs = xs;
+      M.bys = ys;
+      M.nsys = nsys;
+    };
+    blocks(dl.A, nl, nl);
+    blocks(dl.P, nc, nl);
+    blocks(dl.R, nl, nc);
+    blocks(dl.Asw, nl, nl);
   }
   upload_vec(d.cinv, keep.put(std::move(cinv)), s);
-  const size_t n0 = static_cast<size_t>(std::max(d.n(), 1)) * sizeof(T);
+  const size_t n0 = static_cast<size_t>(std::max<int64_t>(d.nfull(), 1)) * sizeof(T);
   d.tmp_res.alloc(n0);
   d.tmp_dz.alloc(n0);
   if (pair_of) {
-    // per level, the pair owning each row (hierarchy p belongs to pair pair_of[p])
+    // per level, the system owning each row (hierarchy p belongs to pair_of[p])
     d.rowpair.clear();
     d.rowpair.resize(L);
     for (size_t l = 0; l < L; ++l) {
@@ -434,7 +464,7 @@ double spmv_bytes(const DCsr<TA> &A) {
   // per row (zeros included) and no indices
   double b = A.dia ? static_cast<double>(sizeof(TA)) * A.ndiag * A.nr + 4.0 * A.ndiag
                    : (sizeof(TA) + 4.0) * A.nnz + 4.0 * (A.nr + 1.0);
-  const double sx = sizeof(TX), sy = sizeof(TY);
+  const double sx = sizeof(TX) * A.kb, sy = sizeof(TY) * A.kb;  // vectors once per block
   if (MODE == kPlain) b += sx * A.nc + sy * A.nr;
   if (MODE == kResid) b += sx * A.nc + 2 * sy * A.nr;
   if (MODE == kSmooth) b += sx * A.nc + 3 * sy * A.nr;      // x, b, dinv, y
@@ -444,53 +474,55 @@ double spmv_bytes(const DCsr<TA> &A) {
   return b;
 }
 
-template <int LPR, int BATCH, int MODE, typename TA, typename TX, typename TY>
-void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2,
-                 Gate gate, hipStream_t s, int kind) {
+template <int LPR, int BATCH, int KB, int MODE, typename TA, typename TX, typename TY>
+void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
+                 hipStream_t s, int kind) {
   const int64_t rows_per_blk = kThreads / LPR;
   const int blocks = static_cast<int>((A.nr + rows_per_blk - 1) / rows_per_blk);
+  const Blocks bk{A.bxs, A.bys, A.nsys};
   timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
-    hipLaunchKernelGGL((spmv_kernel<LPR, BATCH, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
-                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
+    hipLaunchKernelGGL((spmv_kernel<LPR, BATCH, KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
+                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st, bk);
   });
 }
 
-template <int MODE, typename TA, typename TX, typename TY>
-void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
-          hipStream_t s, int kind = kKcOther) {
-  if (A.nr == 0) return;
+template <int KB, int MODE, typename TA, typename TX, typename TY>
+void spmv_kb(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
+             hipStream_t s, int kind) {
+  const Blocks bk{A.bxs, A.bys, A.nsys};
+  const int *rp = gate.st ? A.rp() : nullptr;
   if (A.dia) {
     const int blocks = (A.nr + kThreads - 1) / kThreads;
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
-      hipLaunchKernelGGL((dia_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc, A.ndiag,
-                         A.p(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
+      hipLaunchKernelGGL((dia_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc,
+                         A.ndiag, A.p(), A.v(), x, b, dinv, y, y2, gate.all, rp, gate.st, bk);
     });
     return;
   }
   if (A.sell) {
     const int blocks = (A.nslices + (kThreads / 64) - 1) / (kThreads / 64);
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
-      hipLaunchKernelGGL((sell_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nslices,
-                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
+      hipLaunchKernelGGL((sell_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nslices,
+                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, rp, gate.st, bk);
     });
     return;
   }
   if (A.scalar) {
     const int blocks = (A.nr + kThreads - 1) / kThreads;
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
-      hipLaunchKernelGGL((csr_scalar_kernel<MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.p(),
-                         A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st);
+      hipLaunchKernelGGL((csr_scalar_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr,
+                         A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, rp, gate.st, bk);
     });
     return;
   }
   const bool b8 = A.batch == 8;
   switch (A.lpr) {
-#define MDP_LPR_CASE(L)                                                  \
-  case L:                                                                \
-    if (b8)                                                              \
-      spmv_launch<L, 8, MODE>(A, x, b, dinv, y, y2, gate, s, kind);      \
-    else                                                                 \
-      spmv_launch<L, kCsrBatch, MODE>(A, x, b, dinv, y, y2, gate, s, kind); \
+#define MDP_LPR_CASE(L)                                                         \
+  case L:                                                                       \
+    if (b8)                                                                     \
+      spmv_launch<L, 8, KB, MODE>(A, x, b, dinv, y, y2, gate, s, kind);         \
+    else                                                                        \
+      spmv_launch<L, kCsrBatch, KB, MODE>(A, x, b, dinv, y, y2, gate, s, kind); \
     break;
     MDP_LPR_CASE(2)
     MDP_LPR_CASE(4)
@@ -501,6 +533,19 @@ void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY
 #undef MDP_LPR_CASE
     default: raise(MDP_EINVAL, "unsupported lanes per row");
   }
+}
+
+// y = op(A) x over A.kb vector blocks (one matrix read for all of them).
+template <int MODE, typename TA, typename TX, typename TY>
+void spmv(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
+          hipStream_t s, int kind = kKcOther) {
+  if (A.nr == 0) return;
+  if (A.kb == kMultiRhs)
+    spmv_kb<kMultiRhs, MODE>(A, x, b, dinv, y, y2, gate, s, kind);
+  else if (A.kb == 1)
+    spmv_kb<1, MODE>(A, x, b, dinv, y, y2, gate, s, kind);
+  else
+    raise(MDP_EINVAL, "unsupported number of vector blocks");
 }
 
 template <typename T>
@@ -616,10 +661,10 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
 
 template <typename T>
 void start_smoother(DHier<T> &H, const T *b, Gate gate, hipStream_t s) {
-  const int n = H.n();
+  const int64_t n = H.nfull();
   if (n == 0 || H.dense_only()) return;
   timed_launch(kKcVcycleOther, s, 3.0 * sizeof(T) * n, [&] {
-    hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, b,
+    hipLaunchKernelGGL(diag_scale_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, static_cast<int>(n), b,
                        dptr<const T>(H.lv[0].dinv), dptr<T>(H.lv[0].t), gate.all);
   });
 }
@@ -638,7 +683,7 @@ void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, Gate gate, hipStr
   const int nsw = L.n - L.sw_off;
   if (nsw > 0) {
     const int o = L.sw_off;
-    T *pa = dptr<T>(L.pp), *pb = pa + nsw;
+    T *pa = dptr<T>(L.pp), *pb = pa + sweep_stride(L, H.kb);
     const T *t = dptr<const T>(L.t) + o;
     const T *dinv = dptr<const T>(L.dinv) + o;
     const int kc = kKcVcycleOther;
@@ -675,7 +720,7 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
 template <typename T>
 void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s) {
   vcycle(H, 0, r, z, gate, s);
-  const int n = H.n();
+  const int64_t n = H.nfull();
   DLevel<T> &L0 = H.lv[0];
   for (int c = 1; c < cycles; ++c) {
     // residual r - A z and its first smoothing iterate, for the continuing
@@ -689,12 +734,13 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s
                         dptr<T>(H.tmp_res) + o, dptr<T>(L0.t) + o, gate, s, kKcVcycleOther);
     if (L0.ncont < o) {
       const int nz = o - L0.ncont;
-      hipLaunchKernelGGL(zero_kernel<T>, dim3(grid_for(nz)), dim3(kThreads), 0, s, nz, dptr<T>(H.tmp_res) + L0.ncont,
-                         gate.all);
+      for (int r = 0; r < H.kb; ++r)
+        hipLaunchKernelGGL(zero_kernel<T>, dim3(grid_for(nz)), dim3(kThreads), 0, s, nz,
+                           dptr<T>(H.tmp_res) + static_cast<int64_t>(r) * L0.n + L0.ncont, gate.all);
     }
     vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
-    hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, dptr<const T>(H.tmp_dz), z,
-                       gate.all);
+    hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, static_cast<int>(n),
+                       dptr<const T>(H.tmp_dz), z, gate.all);
   }
 }
 
@@ -728,48 +774,60 @@ void apply_ml(Precond<T> &P, const T *r, T *z, Gate gate, hipStream_t s) {
   apply_q(P.Ho, P.vcycles, static_cast<const T *>(ro), z, gate, s);  // z_O = Q_OO of it
 }
 
-// Preconditioner for a list of pairs' host systems, laid out block-diagonally
-// with the level orders plan_o (all pairs) and plan_g (pairs gpairs, which
-// have fracture unknowns).
+// Preconditioner for a list of host systems, laid out block-diagonally with
+// the level orders plan_o (all systems) and plan_g (systems gsys, which have
+// fracture unknowns).  kb > 1: kb right-hand-side blocks of that layout share
+// the matrices; the preconditioner's vectors are [Omega blocks; Gamma blocks].
 template <typename T>
 std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *> &sys, const LevelPlan &plan_o,
-                                           const LevelPlan &plan_g, const std::vector<int> &gpairs, int vcycles,
-                                           int form, hipStream_t s) {
+                                           const LevelPlan &plan_g, const std::vector<int> &gsys, int vcycles,
+                                           int form, hipStream_t s, int kb = 1) {
   auto p = std::make_unique<Precond<T>>();
   Keep keep;
   p->vcycles = vcycles;
   p->form = form;
   std::vector<const HHier *> ho, hg;
   for (const HostSystem *h : sys) ho.push_back(&h->Ho);
-  for (int q : gpairs) hg.push_back(&sys[q]->Hg);
-  // batches: row-to-pair maps so that stopped pairs' rows are skipped
-  std::vector<int> pair_o(sys.size());
-  for (size_t q = 0; q < sys.size(); ++q) pair_o[q] = static_cast<int>(q);
-  const bool batched = sys.size() > 1;
-  upload_hier(ho, plan_o, p->Ho, s, keep, batched ? &pair_o : nullptr);
+  for (int q : gsys) hg.push_back(&sys[q]->Hg);
+  // batches: row-to-system maps so that stopped pairs' rows are skipped
+  std::vector<int> sys_o(sys.size());
+  for (size_t q = 0; q < sys.size(); ++q) sys_o[q] = static_cast<int>(q);
+  const int nsys = static_cast<int>(sys.size());
+  const bool maps = nsys > 1;
+  upload_hier(ho, plan_o, p->Ho, s, keep, maps ? &sys_o : nullptr, kb, nsys);
   p->Ho.is_omega = true;
-  p->n_o = p->Ho.n();
-  if (!gpairs.empty()) {
-    upload_hier(hg, plan_g, p->Hg, s, keep, batched ? &gpairs : nullptr);
-    p->n_g = p->Hg.n();
+  const int32_t no1 = p->Ho.n();
+  p->n_o = static_cast<int32_t>(p->Ho.nfull());
+  if (!gsys.empty()) {
+    upload_hier(hg, plan_g, p->Hg, s, keep, maps ? &gsys : nullptr, kb, nsys);
+    const int32_t ng1 = p->Hg.n();
+    p->n_g = static_cast<int32_t>(p->Hg.nfull());
+    auto blocks = [&](DCsr<T> &M, int64_t xs, int64_t ys) {
+      M.kb = kb;
+      M.bxs = xs;
+      M.bys = ys;
+      M.nsys = nsys;
+    };
     std::vector<Piece> pieces;
-    for (size_t k = 0; k < gpairs.size(); ++k) {
-      const int q = gpairs[k];
+    for (size_t k = 0; k < gsys.size(); ++k) {
+      const int q = gsys[k];
       pieces.emplace_back(&sys[q]->Ago, static_cast<int32_t>(plan_g.off[0][k]),
                           static_cast<int32_t>(plan_o.off[0][q]));
     }
     if (form == MDP_BLOCK_LOWER) {
-      upload_csr(concat_blocks(p->n_g, p->n_o, pieces), p->Ago, s, keep);
-      if (batched) p->Ago.rowpair = dptr<const int>(p->Hg.rowpair[0]);
+      upload_csr(concat_blocks(ng1, no1, pieces), p->Ago, s, keep);
+      if (maps) p->Ago.rowpair = dptr<const int>(p->Hg.rowpair[0]);
+      blocks(p->Ago, no1, ng1);  // x = z_Omega; b, dinv, y = Gamma-sized
       p->rg.alloc(static_cast<size_t>(p->n_g) * sizeof(T));
     } else if (form == MDP_BLOCK_UPPER) {
       std::vector<Piece> up;
-      for (size_t k = 0; k < gpairs.size(); ++k) {
-        const int q = gpairs[k];
+      for (size_t k = 0; k < gsys.size(); ++k) {
+        const int q = gsys[k];
         up.emplace_back(&sys[q]->Aog, static_cast<int32_t>(plan_o.off[0][q]), static_cast<int32_t>(plan_g.off[0][k]));
       }
-      upload_csr(concat_blocks(p->n_o, p->n_g, up), p->Aog, s, keep);
-      if (batched) p->Aog.rowpair = dptr<const int>(p->Ho.rowpair[0]);
+      upload_csr(concat_blocks(no1, ng1, up), p->Aog, s, keep);
+      if (maps) p->Aog.rowpair = dptr<const int>(p->Ho.rowpair[0]);
+      blocks(p->Aog, ng1, no1);  // x = z_Gamma; b, dinv, y = Omega-sized
       p->rg.alloc(static_cast<size_t>(p->n_o) * sizeof(T));
     }
   }
@@ -1291,62 +1349,99 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Batches
 
+// Vector blocks of a batch: kMultiRhs when every system in it has exactly
+// kMultiRhs right-hand sides, else 1 (every pair its own block).
+int batch_blocks(const std::vector<const Solver *> &pairs) {
+  std::map<const Solver *, int> count;
+  for (const Solver *p : pairs) ++count[p];
+  for (const auto &c : count)
+    if (c.second != kMultiRhs) return 1;
+  return kMultiRhs;
+}
+
 void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool alloc_ws) {
   const AutotuneScope tune(!pairs.empty() && (pairs[0]->opt.flags & MDP_NO_AUTOTUNE) == 0);
   sys = pairs;
   npairs = static_cast<int>(pairs.size());
   opt = pairs[0]->opt;
+  // The block's systems, and the internal pair order: pair r * nsys + k is
+  // the r-th right-hand side of system k (with kb = 1, every pair is a system).
+  kb = batch_blocks(pairs);
+  std::vector<const Solver *> bsys;
+  order.assign(static_cast<size_t>(npairs), -1);
+  if (kb == 1) {
+    bsys = pairs;
+    for (int q = 0; q < npairs; ++q) order[q] = q;
+  } else {
+    std::map<const Solver *, int> index;
+    std::vector<int> sys_of(static_cast<size_t>(npairs));
+    for (int p = 0; p < npairs; ++p) {
+      auto it = index.find(pairs[p]);
+      if (it == index.end()) {
+        it = index.emplace(pairs[p], static_cast<int>(bsys.size())).first;
+        bsys.push_back(pairs[p]);
+      }
+      sys_of[p] = it->second;
+    }
+    std::vector<int> seen(bsys.size(), 0);
+    const int ns = static_cast<int>(bsys.size());
+    for (int p = 0; p < npairs; ++p) order[seen[sys_of[p]]++ * ns + sys_of[p]] = p;
+  }
+  nsys = static_cast<int>(bsys.size());
   std::vector<const HostSystem *> hsys;
   std::vector<const HHier *> ho, hg;
-  std::vector<int> gpairs;
-  for (int p = 0; p < npairs; ++p) {
-    hsys.push_back(&pairs[p]->host);
-    ho.push_back(&pairs[p]->host.Ho);
-    if (pairs[p]->host.n_g > 0) {
-      gpairs.push_back(p);
-      hg.push_back(&pairs[p]->host.Hg);
+  std::vector<int> gsys;
+  for (int k = 0; k < nsys; ++k) {
+    hsys.push_back(&bsys[k]->host);
+    ho.push_back(&bsys[k]->host.Ho);
+    if (bsys[k]->host.n_g > 0) {
+      gsys.push_back(k);
+      hg.push_back(&bsys[k]->host.Hg);
     }
   }
   const LevelPlan po = plan_levels(ho);
-  const LevelPlan pg = gpairs.empty() ? LevelPlan{} : plan_levels(hg);
-  n_o = po.n[0];
-  n_g = gpairs.empty() ? 0 : pg.n[0];
-  if (static_cast<int64_t>(n_o) + n_g > std::numeric_limits<int32_t>::max())
-    raise(MDP_EINVAL, "batch exceeds int32 indexing");
+  const LevelPlan pg = gsys.empty() ? LevelPlan{} : plan_levels(hg);
+  const int64_t no1 = po.n[0], ng1 = gsys.empty() ? 0 : pg.n[0];
+  if (kb * (no1 + ng1) > std::numeric_limits<int32_t>::max()) raise(MDP_EINVAL, "batch exceeds int32 indexing");
+  n_o = static_cast<int32_t>(kb * no1);
+  n_g = static_cast<int32_t>(kb * ng1);
   n = n_o + n_g;
-  // global row of (pair, internal index): Omega rows in the S~ hierarchies'
-  // level-0 order, then Gamma rows in the A_GG hierarchies' level-0 order
-  std::vector<int64_t> goff_g(static_cast<size_t>(npairs), -1);
-  for (size_t k = 0; k < gpairs.size(); ++k) goff_g[gpairs[k]] = n_o + pg.off[0][k];
+  // global row of (internal pair q, internal index): Omega rows of block
+  // q / nsys in the S~ hierarchies' level-0 order, then Gamma rows of that
+  // block in the A_GG hierarchies' level-0 order
+  std::vector<int64_t> goff_g(static_cast<size_t>(nsys), -1);
+  for (size_t k = 0; k < gsys.size(); ++k) goff_g[gsys[k]] = pg.off[0][k];
+  auto omega_at = [&](int q) { return (q / nsys) * no1 + po.off[0][q % nsys]; };
+  auto gamma_at = [&](int q) { return n_o + (q / nsys) * ng1 + goff_g[q % nsys]; };
   std::vector<int32_t> gidx_h(static_cast<size_t>(n)), gpair_h(static_cast<size_t>(n));
   std::vector<std::vector<std::pair<int64_t, int64_t>>> ranges(static_cast<size_t>(npairs));
   HCsr Ag = HCsr::empty(n, n);
   {
     std::vector<int32_t> rowlen(static_cast<size_t>(n), 0);
-    for (int p = 0; p < npairs; ++p) {
-      const HostSystem &h = *hsys[p];
-      const int64_t oo = po.off[0][p], og = goff_g[p];
-      ranges[p].push_back({oo, h.n_o});
-      if (h.n_g > 0) ranges[p].push_back({og, h.n_g});
+    for (int q = 0; q < npairs; ++q) {
+      const HostSystem &h = *hsys[q % nsys];
+      const int64_t oo = omega_at(q), og = gamma_at(q);
+      ranges[q].push_back({oo, h.n_o});
+      if (h.n_g > 0) ranges[q].push_back({og, h.n_g});
       for (int32_t i = 0; i < h.n; ++i) {
         const int64_t g = i < h.n_o ? oo + i : og + (i - h.n_o);
         rowlen[g] = h.A.ptr[i + 1] - h.A.ptr[i];
         gidx_h[g] = h.perm[i];
-        gpair_h[g] = p;
+        gpair_h[g] = q;
       }
     }
     for (int32_t i = 0; i < n; ++i) Ag.ptr[i + 1] = Ag.ptr[i] + rowlen[i];
     Ag.col.resize(static_cast<size_t>(Ag.ptr[n]));
     Ag.val.resize(static_cast<size_t>(Ag.ptr[n]));
-    for (int p = 0; p < npairs; ++p) {
-      const HostSystem &h = *hsys[p];
-      const int64_t oo = po.off[0][p], og = goff_g[p];
+    for (int q = 0; q < npairs; ++q) {
+      const HostSystem &h = *hsys[q % nsys];
+      const int64_t oo = omega_at(q), og = gamma_at(q);
       auto gmap = [&](int32_t i) { return static_cast<int32_t>(i < h.n_o ? oo + i : og + (i - h.n_o)); };
       for (int32_t i = 0; i < h.n; ++i) {
-        int32_t q = Ag.ptr[gmap(i)];
-        for (int32_t k = h.A.ptr[i]; k < h.A.ptr[i + 1]; ++k, ++q) {
-          Ag.col[q] = gmap(h.A.col[k]);
-          Ag.val[q] = h.A.val[k];
+        int32_t k2 = Ag.ptr[gmap(i)];
+        for (int32_t k = h.A.ptr[i]; k < h.A.ptr[i + 1]; ++k, ++k2) {
+          Ag.col[k2] = gmap(h.A.col[k]);
+          Ag.val[k2] = h.A.val[k];
         }
       }
     }
@@ -1357,10 +1452,13 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
   upload_vec(gpair, keep.put(std::move(gpair_h)), s);
   if (npairs > 1) A.rowpair = dptr<const int>(gpair);
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(hsys, po, pg, gpairs, opt.vcycles, opt.block_form, s);
+    pc32 = upload_precond<float>(hsys, po, pg, gsys, opt.vcycles, opt.block_form, s, kb);
   else
-    pc64 = upload_precond<double>(hsys, po, pg, gpairs, opt.vcycles, opt.block_form, s);
+    pc64 = upload_precond<double>(hsys, po, pg, gsys, opt.vcycles, opt.block_form, s, kb);
   layout.build(ranges, n, s);
+  if (std::getenv("MDP_SETUP_VERBOSE"))
+    std::fprintf(stderr, "[mdp] batch: %d pairs, %d right-hand-side blocks of %d systems, n=%d\n", npairs, kb, nsys,
+                 n);
   if (alloc_ws) {
     const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
     ws.alloc(n, opt.restart, npairs, layout.ntiles, tsz, s);
@@ -1379,9 +1477,9 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
     raise(MDP_EINVAL, "batch workspace missing or too small");
   std::vector<const double *> bptr(static_cast<size_t>(npairs));
   std::vector<double *> xptr(static_cast<size_t>(npairs));
-  for (int p = 0; p < npairs; ++p) {
-    bptr[p] = io[p].b;
-    xptr[p] = io[p].x;
+  for (int q = 0; q < npairs; ++q) {  // internal order
+    bptr[q] = io[order[q]].b;
+    xptr[q] = io[order[q]].x;
   }
   DevMem bdev(sizeof(void *) * npairs), xdev(sizeof(void *) * npairs);
   MDP_HIP(hipMemcpyAsync(bdev.get(), bptr.data(), sizeof(void *) * npairs, hipMemcpyHostToDevice, s));
@@ -1394,12 +1492,13 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
     hipLaunchKernelGGL(gather_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
                        dptr<const int>(gpair), dptr<const int>(gidx), dptr<const double *const>(xdev), xg);
   int rc;
+  std::vector<mdp_stats> sti(st ? static_cast<size_t>(npairs) : 0);  // internal order
   if (opt.precision == MDP_MIXED) {
     Problem<float> pb{&A, pc32.get(), &layout, &W, &opt};
-    rc = fgmres<float>(pb, bg, xg, use_x0, s, st);
+    rc = fgmres<float>(pb, bg, xg, use_x0, s, st ? sti.data() : nullptr);
   } else {
     Problem<double> pb{&A, pc64.get(), &layout, &W, &opt};
-    rc = fgmres<double>(pb, bg, xg, use_x0, s, st);
+    rc = fgmres<double>(pb, bg, xg, use_x0, s, st ? sti.data() : nullptr);
   }
   hipLaunchKernelGGL(scatter_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),
                      dptr<const int>(gpair), dptr<const int>(gidx), static_cast<const double *>(xg),
@@ -1408,7 +1507,9 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   MDP_HIP(hipStreamSynchronize(s));  // bdev / xdev die here
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (st)
-    for (int p = 0; p < npairs; ++p) {
+    for (int q = 0; q < npairs; ++q) {
+      const int p = order[q];
+      st[p] = sti[q];
       st[p].solve_ms = ms;
       st[p].setup_ms = sys[p]->setup_ms;
     }

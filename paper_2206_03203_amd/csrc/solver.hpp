@@ -35,7 +35,12 @@ struct DCsr {
   bool scalar = false;
   int32_t nslices = 0;
   DevMem ptr, col, val;
-  const int *rowpair = nullptr;  // batched: pair of each row (not owned), else NULL
+  const int *rowpair = nullptr;  // batched: system (kb > 1) or pair (kb = 1) of each row, not owned; else NULL
+  // Vector blocks: kb right-hand-side blocks share each matrix read; block r
+  // of x starts r * bxs further on, block r of b, dinv, y, y2 r * bys further.
+  int kb = 1;
+  int64_t bxs = 0, bys = 0;
+  int nsys = 1;  // systems per block (pair of row i in block r: r * nsys + rowpair[i])
   const int *p() const { return dptr<const int>(ptr); }
   const int *rp() const { return rowpair; }
   const int *c() const { return dptr<const int>(col); }
@@ -60,14 +65,20 @@ struct DLevel {
   DevMem pp;          // ping-pong for the swept coarsest systems
 };
 
+// With kb > 1 (several right-hand sides per system in a batch) every level
+// vector holds kb blocks of the one-copy layout: block r is right-hand side r
+// of every system, and n, ncont and sw_off count one block.  The matrices are
+// stored once and applied to all blocks in one pass.
 template <typename T>
 struct DHier {
   std::vector<DLevel<T>> lv;
+  int kb = 1;
   std::vector<DevMem> rowpair;  // batched: per level, the pair of each row
   DevMem cinv;            // dense FP64 inverses of the coarsest levels
   DevMem tmp_res, tmp_dz; // extra cycles: residual and correction at level 0
   bool is_omega = false;  // hierarchy on S~ (its finest level is timed separately)
-  int32_t n() const { return lv.empty() ? 0 : lv[0].n; }
+  int32_t n() const { return lv.empty() ? 0 : lv[0].n; }  // one block
+  int64_t nfull() const { return static_cast<int64_t>(kb) * n(); }
   // true when nothing at level 0 smooths (only dense-solved systems there)
   bool dense_only() const { return lv.size() == 1 && lv[0].ncont == 0 && lv[0].sw_off == lv[0].n; }
 };
@@ -79,7 +90,7 @@ struct Precond {
   DCsr<T> Ago;  // A_GO (lower form)
   DCsr<T> Aog;  // A_OG (upper form)
   DevMem rg;    // r_Gamma - A_GO z_Omega (lower); r_Omega - A_OG z_Gamma (upper)
-  int32_t n_o = 0, n_g = 0;
+  int32_t n_o = 0, n_g = 0;  // all blocks
   int vcycles = 1;
   int form = MDP_BLOCK_LOWER;
 };
@@ -154,14 +165,20 @@ struct Solver {
 };
 
 // A block-diagonal batch of pairs (a system appears once per right-hand side).
+// When every system of the batch has kMultiRhs right-hand sides, the pairs
+// run in right-hand-side-major order (pair r * nsys + s is right-hand side r
+// of system s) and the preconditioner's matrices are stored once for all
+// right-hand sides (kb = kMultiRhs); otherwise each pair is its own block.
 struct Batch {
-  std::vector<const Solver *> sys;  // per pair
+  std::vector<const Solver *> sys;  // per pair, caller's order
   int npairs = 0;
+  int kb = 1, nsys = 0;    // blocks, and systems per block
+  std::vector<int> order;  // internal pair -> caller's pair
   int32_t n = 0, n_o = 0, n_g = 0;
   mdp_options opt{};
   DCsr<double> A;
   DevMem gidx;  // per global row: caller index within its pair's system
-  DevMem gpair; // per global row: pair (also the row-to-pair map of A)
+  DevMem gpair; // per global row: internal pair (also the row-to-pair map of A)
   std::unique_ptr<Precond<double>> pc64;
   std::unique_ptr<Precond<float>> pc32;
   Layout layout;

@@ -9,6 +9,7 @@ constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 constexpr int kRedBlocks = 1024;  // fixed number of partial sums per reduction
 constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi pass
+constexpr int kMultiRhs = 4;       // right-hand sides that share one matrix read in a batch
 constexpr int kDotU = 4;          // elements per thread in the Arnoldi passes
 constexpr int kTileElems = 256 * kDotU;
 

@@ -83,7 +83,7 @@ def test_batch_rejects_mixed_precisions():
         s2.close()
 
 
-def test_batch_split_into_chunks(monkeypatch):
+def test_batch_split_into_chunks(monkeypatch, capfd):
     """A batch larger than the chunk bound is solved as several block-diagonal
     chunks, one after another, on one shared workspace sized for the largest;
     every pair still converges and agrees with the one-chunk batch."""
@@ -100,11 +100,17 @@ def test_batch_split_into_chunks(monkeypatch):
         rc, st1 = L.mdp_solve_batch(hs, bs, one)
         assert rc == L.MDP_OK
         nmax = max(s.n for s in solvers)
-        for cap in (nmax, 3 * nmax):  # one pair per chunk at most / a few pairs per chunk
+        monkeypatch.setenv("MDP_SETUP_VERBOSE", "1")
+        # cap = the largest system: its two right-hand sides go to separate
+        # chunks; 3x: a few systems per chunk
+        for cap in (nmax, 3 * nmax):
             monkeypatch.setenv("MDP_BATCH_MAX_UNKNOWNS", str(cap))
+            capfd.readouterr()
             xs = [torch.zeros_like(b) for b in bs]
             rc, st = L.mdp_solve_batch(hs, bs, xs)
-            say(f"[batch-chunks] cap={cap} iters={[s['iters'] for s in st]}")
+            chunks = [ln for ln in capfd.readouterr().err.splitlines() if "[mdp] batch:" in ln]
+            say(f"[batch-chunks] cap={cap} chunks={len(chunks)} iters={[s['iters'] for s in st]}")
+            assert len(chunks) >= 2
             assert rc == L.MDP_OK
             for a, b in zip(st, st1):
                 assert a["converged"] == 1 and a["rel_res_true"] <= 1e-8
