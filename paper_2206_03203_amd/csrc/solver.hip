@@ -1116,18 +1116,65 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
 
 // ---------------------------------------------------------------------------
 
+// Tiles.  Each Arnoldi pass gives one workgroup per tile and every tile the
+// same work, so the tile count is a multiple of the 256 compute units when
+// the vectors are long enough (a partly filled last round of workgroups costs
+// as much as a full one), with at most kTileElems entries per tile and, for
+// short vectors, at least kMinTile.  The tiles are shared among the ranges in
+// proportion to their lengths (largest remainders first); each range is cut
+// into tiles whose lengths differ by at most one.
+constexpr int64_t kCus = 256;
+constexpr int64_t kMinTile = 64;
+
+int64_t tile_target(int64_t n) {
+  const int64_t fewest = (n + kTileElems - 1) / kTileElems;
+  const int64_t most = std::max<int64_t>(1, (n + kMinTile - 1) / kMinTile);
+  const int64_t balanced = (fewest + kCus - 1) / kCus * kCus;
+  return std::min(balanced, std::max(fewest, most));
+}
+
 void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges, int64_t n_total,
                    hipStream_t s) {
   npairs = static_cast<int>(ranges.size());
   n = n_total;
+  rows.assign(static_cast<size_t>(npairs), 0);
+  struct Share {
+    int p;
+    int64_t start, len, k;
+    double rem;
+  };
+  std::vector<Share> sh;
+  int64_t total = 0;
+  for (int p = 0; p < npairs; ++p)
+    for (const auto &r : ranges[p]) {
+      rows[p] += r.second;
+      total += r.second;
+      if (r.second > 0) sh.push_back(Share{p, r.first, r.second, 0, 0.0});
+    }
+  const int64_t target = tile_target(total);
+  int64_t given = 0;
+  for (Share &x : sh) {
+    const double exact = static_cast<double>(x.len) * target / std::max<int64_t>(total, 1);
+    x.k = static_cast<int64_t>(exact);
+    x.rem = exact - x.k;
+    given += x.k;
+  }
+  std::vector<size_t> by_rem(sh.size());
+  for (size_t i = 0; i < sh.size(); ++i) by_rem[i] = i;
+  std::stable_sort(by_rem.begin(), by_rem.end(), [&](size_t a, size_t b) { return sh[a].rem > sh[b].rem; });
+  for (size_t i = 0; i < by_rem.size() && given < target; ++i, ++given) ++sh[by_rem[i]].k;
   std::vector<Tile> tl;
   std::vector<int32_t> off(static_cast<size_t>(npairs) + 1, 0);
-  rows.assign(static_cast<size_t>(npairs), 0);
+  size_t q = 0;
   for (int p = 0; p < npairs; ++p) {
-    for (const auto &r : ranges[p]) rows[p] += r.second;
-    for (const auto &r : ranges[p])
-      for (int64_t o = 0; o < r.second; o += kTileElems)
-        tl.push_back(Tile{r.first + o, static_cast<int32_t>(std::min<int64_t>(kTileElems, r.second - o)), p});
+    for (; q < sh.size() && sh[q].p == p; ++q) {
+      Share &x = sh[q];
+      x.k = std::min(x.len, std::max({x.k, int64_t{1}, (x.len + kTileElems - 1) / kTileElems}));
+      for (int64_t i = 0; i < x.k; ++i) {
+        const int64_t lo = i * x.len / x.k, hi = (i + 1) * x.len / x.k;
+        tl.push_back(Tile{x.start + lo, static_cast<int32_t>(hi - lo), p});
+      }
+    }
     off[p + 1] = static_cast<int32_t>(tl.size());
   }
   ntiles = static_cast<int>(tl.size());

@@ -10,7 +10,7 @@ constexpr int kXcds = 8;
 constexpr int kRedBlocks = 1024;  // fixed number of partial sums per reduction
 constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi pass
 constexpr int kMultiRhs = 4;       // right-hand sides that share one matrix read in a batch
-constexpr int kDotU = 4;          // elements per thread in the Arnoldi passes
+constexpr int kDotU = 9;          // elements per thread in the Arnoldi passes (tiles of up to 2304)
 constexpr int kTileElems = 256 * kDotU;
 
 // Per-cycle FGMRES state in device memory.

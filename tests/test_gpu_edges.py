@@ -1,6 +1,7 @@
 """Edge cases of the GPU path against the oracle (dense LAPACK solutions of
 the oracle's own assembly): the smallest systems (one host cell; one
-fracture cell), sizes on and just past a reduction-tile boundary, an empty
+fracture cell), sizes on and just past 1024 unknowns, systems whose Arnoldi
+tiles have the largest length (true residual of the oracle's matrix), an empty
 batch and systems with no right-hand side in a batch, a batch mixing a zero
 right-hand side with others, and an exhausted iteration budget."""
 
@@ -47,6 +48,34 @@ def test_smallest_and_tile_boundary_systems(name, prec):
         assert st[0]["converged"] == 1
         assert np.linalg.norm(bo - Ao @ host(x)) <= 1e-8 * np.linalg.norm(bo)
         assert relerr(host(x), x_ref) <= 1e-6
+    finally:
+        s.close()
+
+
+def _tile_limit_cases():
+    """768^2 = 256 x 2304 unknowns: 256 tiles of exactly the largest tile
+    length; with a fracture, 512 tiles shared between the Omega and Gamma
+    ranges in proportion to their lengths."""
+    k = synth.scenarios._lognormal(768 * 768, seed=3, sigma=1.0)
+    return {
+        "tile-2304x256": Scenario(2, 768, k, [], DIR),
+        "tile-2304x256-plus-fracture": Scenario(2, 768, k, [Fracture(1, 300, (100,), (400,), 1e3, 1e-2, 1e-3)], DIR),
+    }
+
+
+@pytest.mark.parametrize("name", list(_tile_limit_cases()))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_largest_tile_systems(name, prec):
+    sc = _tile_limit_cases()[name]
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    say(f"[edges] {name} n={A.shape[0]} prec={prec}")
+    s = Solver(A, part, precision=prec)
+    try:
+        x, st = s.solve(dev(b))
+        res = np.linalg.norm(bo - Ao @ host(x)) / np.linalg.norm(bo)
+        say(f"    iters={st[0]['iters']} res={res:.2e}")
+        assert st[0]["converged"] == 1 and res <= 1e-8
     finally:
         s.close()
 
