@@ -10,9 +10,10 @@ hierarchies are resident in HBM before the clock starts.
 
 The JSON line reports the plain-FP64 method as ``value`` and, beside it, the
 mixed mode (FP32 preconditioner, FP64 outer loop and coarse solve) on the
-same systems, per-solve latency percentiles, the roofline position of the
-dominant kernel (timed with HIP events inside the library on the launch
-stream) and the CPU oracle timed on a bounded sample on this host.
+same systems, per-solve latency percentiles, the same four systems solved
+together as one batch (``batched``, both precisions), the roofline position
+of the dominant kernel (timed with HIP events inside the library on the
+launch stream) and the CPU oracle timed on a bounded sample on this host.
 
 Two more workloads, each printing its own JSON line:
 
@@ -169,6 +170,31 @@ def main():
     value = args.steps / fp["seconds"]
     mixed_value = args.steps / mx["seconds"]
 
+    # Beside the one-at-a-time solves: the same systems solved together as
+    # one block-diagonal batch (mdp_solve_batch), one launch per operation.
+    batched = {}
+    if args.block == "lower":
+        nb = max(1, args.steps // len(systems))
+        for prec in ("fp64", "mixed"):
+            hs = [s["h"][prec] for s in systems]
+            bs = [s["b"] for s in systems]
+            xs = [torch.zeros_like(s["b"]) for s in systems]
+            L.mdp_solve_batch(hs, bs, xs, stream)  # builds the batch plan (untimed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nb):
+                rc, st = L.mdp_solve_batch(hs, bs, xs, stream)
+                if rc != L.MDP_OK:
+                    raise RuntimeError(f"batched {prec} solve did not converge: rc={rc}")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            batched[prec] = {"value": round(len(systems) * nb / dt, 3), "unit": "solves/s",
+                             "ms_per_batch": round(1e3 * dt / nb, 3), "batches": nb,
+                             "iters": [x["iters"] for x in st],
+                             "max_rel_res": max(x["rel_res_true"] for x in st)}
+            log(f"[bench] batched {prec}: {nb} batches of {len(systems)} in {dt:.3f}s")
+        batched["what"] = "the same systems solved together as one block-diagonal batch"
+
     # Roofline: the same FP64 steps again, with HIP events recorded by the
     # library around every launch of each kernel class on its launch stream
     # (kept out of the timed passes above: the events lengthen the gaps
@@ -218,6 +244,7 @@ def main():
                   "ms_per_step": round(1e3 * mx["seconds"] / args.steps, 3), "p50_ms": pct(mx["lat"], 50),
                   "p99_ms": pct(mx["lat"], 99), "iters": sorted(set(mx["iters"])),
                   "max_rel_res": max(mx["res"]), "speedup_vs_fp64": round(mixed_value / value, 3)},
+        "batched": batched or None,
         "roofline": roofline,
         "kernel_classes": classes,
         "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_setup, 2)},

@@ -321,6 +321,76 @@ __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
                             blk(y2, r * bk.ys));
 }
 
+// Diagonals plus a CSR remainder, one thread per row: for stencil matrices
+// with a few irregular couplings (the system matrix: the host's stencil on
+// the diagonals; host-fracture and fracture-fracture couplings in the
+// remainder).  Entry (i, i + doff[d]) of the diagonals is at dval[d * nr + i]
+// (zero where absent, or past the columns); the remainder's row i holds the
+// other entries of row i.  Diagonal terms are summed first, in offset order.
+template <int KB, int MODE, typename TA, typename TX, typename TY>
+__global__ __launch_bounds__(kThreads) void hyb_kernel(
+    int nr, int nc, int ndiag, const int *__restrict__ doff, const TA *__restrict__ dval,
+    const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
+    const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst, Blocks bk) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TX>::type;
+  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
+  const int row = blk_id * kThreads + static_cast<int>(threadIdx.x);
+  if (row >= nr) return;
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
+  for (int d0 = 0; d0 < ndiag; d0 += kDiaBatch) {
+    int c[kDiaBatch];
+    bool in[kDiaBatch];
+    Acc v[kDiaBatch];
+#pragma unroll
+    for (int k = 0; k < kDiaBatch; ++k) {
+      const int d = d0 + k;
+      c[k] = d < ndiag ? row + doff[d] : row;
+      in[k] = d < ndiag && c[k] >= 0 && c[k] < nc;
+      v[k] = in[k] ? static_cast<Acc>(dval[static_cast<int64_t>(d) * nr + row]) : Acc(0);
+    }
+#pragma unroll
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < kDiaBatch; ++k) {
+          const Acc xv =
+              in[k] ? spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys)) : Acc(0);
+          sum[r] += v[k] * xv;
+        }
+  }
+  const int s = ptr[row], e = ptr[row + 1];
+  for (int p0 = s; p0 < e; p0 += kScalarBatch) {
+    int c[kScalarBatch];
+    Acc v[kScalarBatch];
+#pragma unroll
+    for (int k = 0; k < kScalarBatch; ++k) {
+      const int p = p0 + k;
+      c[k] = p < e ? col[p] : col[s];
+      v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
+    }
+#pragma unroll
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < kScalarBatch; ++k)
+          sum[r] += v[k] * spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
+  }
+#pragma unroll
+  for (int r = 0; r < KB; ++r)
+    if (live[r])
+      spmv_store<MODE, Acc>(row, sum[r], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                            blk(y2, r * bk.ys));
+}
+
 // Coarsest level: x = Ainv b with a dense FP64 inverse (row-major n x n); one
 // wavefront per row, FP64 accumulation whatever the vector type.
 template <typename T>

@@ -27,6 +27,7 @@
 #include <mutex>
 #include <tuple>
 #include <type_traits>
+#include <unordered_map>
 
 #include "kernels.hpp"
 #include "ktimer.hpp"
@@ -87,6 +88,7 @@ struct FormatChoice {
   int lpr = 8;
   int batch = kCsrBatch;  // CSR-vector entries in flight per lane (4 or 8)
   bool dia = false;
+  bool hyb = false;
 };
 
 struct SliceStats {
@@ -128,14 +130,49 @@ std::vector<int32_t> dia_offsets(const HCsr &h) {
   return offs;
 }
 
+// Diagonals for the diagonals-plus-remainder layout: the offsets that hold
+// an entry in at least half of the rows (at most kMaxDiag, the fullest), when
+// together they hold at least 80% of the entries with at most 25% padding;
+// empty otherwise.  Rows of more than kMaxDiag + 4 entries on average are
+// not looked at.
+std::vector<int32_t> hyb_offsets(const HCsr &h) {
+  if (h.nr == 0 || h.nnz() > static_cast<int64_t>(kMaxDiag + 4) * h.nr) return {};
+  std::unordered_map<int32_t, int64_t> count;
+  count.reserve(64);
+  for (int32_t i = 0; i < h.nr; ++i)
+    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) ++count[h.col[k] - i];
+  std::vector<std::pair<int64_t, int32_t>> full;
+  for (const auto &c : count)
+    if (2 * c.second >= h.nr) full.emplace_back(c.second, c.first);
+  std::sort(full.begin(), full.end(), [](const auto &a, const auto &b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  if (full.size() > static_cast<size_t>(kMaxDiag)) full.resize(kMaxDiag);
+  int64_t covered = 0;
+  std::vector<int32_t> offs;
+  for (const auto &f : full) {
+    covered += f.first;
+    offs.push_back(f.second);
+  }
+  std::sort(offs.begin(), offs.end());
+  const double stored = static_cast<double>(offs.size()) * h.nr;
+  if (offs.empty() || covered < 0.8 * h.nnz() || stored > 1.25 * covered) return {};
+  return offs;
+}
+
 // Fixed rule (also the autotuner's fallback): diagonal storage for stencil
-// matrices, sliced ELL when the slices carry at most 15% padding, one thread
-// per row for other short rows, else enough lanes per row for kCsrBatch
-// entries each.
-FormatChoice heuristic_format(const HCsr &h, const SliceStats &st, bool dia_ok) {
+// matrices, diagonals plus a remainder for stencils with a few irregular
+// couplings, sliced ELL when the slices carry at most 15% padding, one
+// thread per row for other short rows, else enough lanes per row for
+// kCsrBatch entries each.
+FormatChoice heuristic_format(const HCsr &h, const SliceStats &st, bool dia_ok, bool hyb_ok) {
   FormatChoice f;
   if (dia_ok) {
     f.dia = true;
+    return f;
+  }
+  if (hyb_ok) {
+    f.hyb = true;
     return f;
   }
   const int64_t nnz = h.nnz();
@@ -161,22 +198,23 @@ void upload_sell_arrays(const HCsr &h, DCsr<T> &d, const SliceStats &st, hipStre
   int64_t o = 0;
   for (int32_t sl = 0; sl < ns; ++sl) {
     const int32_t r0 = sl * 64, r1 = std::min(h.nr, r0 + 64);
-    int32_t w = 0;
-    for (int32_t r = r0; r < r1; ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+    int32_t w = 0, first = 0;
+    for (int32_t r = r1 - 1; r >= r0; --r) {
+      w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+      if (h.ptr[r + 1] > h.ptr[r]) first = h.col[h.ptr[r]];
+    }
     soff[sl] = static_cast<int32_t>(o);
     for (int32_t lane = 0; lane < 64; ++lane) {
       const int32_t r = r0 + lane;
       const int32_t len = r < r1 ? h.ptr[r + 1] - h.ptr[r] : 0;
-      int32_t lastc = 0;
+      int32_t lastc = first;  // padding: a valid, nearby column with value 0
       for (int32_t k = 0; k < w; ++k) {
         const int64_t dst = o + static_cast<int64_t>(k) * 64 + lane;
         if (k < len) {
           lastc = h.col[h.ptr[r] + k];
-          col[dst] = lastc;
           val[dst] = static_cast<T>(h.val[h.ptr[r] + k]);
-        } else {
-          col[dst] = lastc;  // padding: a valid, nearby column with value 0
         }
+        col[dst] = lastc;
       }
     }
     o += static_cast<int64_t>(w) * 64;
@@ -197,6 +235,33 @@ void upload_dia_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &of
       val[di * h.nr + i] = static_cast<T>(h.val[k]);
     }
   upload_vec(d.ptr, keep.put(std::vector<int32_t>(offs)), s);
+  upload_vec(d.val, keep.put(std::move(val)), s);
+}
+
+template <typename T>
+void upload_hyb_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &offs, hipStream_t s, Keep &keep) {
+  d.ndiag = static_cast<int32_t>(offs.size());
+  std::vector<T> dval(offs.size() * static_cast<size_t>(h.nr), T(0));
+  std::vector<int32_t> ptr(static_cast<size_t>(h.nr) + 1, 0), col;
+  std::vector<T> val;
+  for (int32_t i = 0; i < h.nr; ++i) {
+    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+      const int32_t off = h.col[k] - i;
+      const auto it = std::lower_bound(offs.begin(), offs.end(), off);
+      if (it != offs.end() && *it == off) {
+        dval[static_cast<size_t>(it - offs.begin()) * h.nr + i] = static_cast<T>(h.val[k]);
+      } else {
+        col.push_back(h.col[k]);
+        val.push_back(static_cast<T>(h.val[k]));
+      }
+    }
+    ptr[i + 1] = static_cast<int32_t>(col.size());
+  }
+  d.rem_nnz = static_cast<int64_t>(col.size());
+  upload_vec(d.doff, keep.put(std::vector<int32_t>(offs)), s);
+  upload_vec(d.dval, keep.put(std::move(dval)), s);
+  upload_vec(d.ptr, keep.put(std::move(ptr)), s);
+  upload_vec(d.col, keep.put(std::move(col)), s);
   upload_vec(d.val, keep.put(std::move(val)), s);
 }
 
@@ -224,8 +289,8 @@ std::mutex g_tune_mu;
 std::map<TuneKey, FormatChoice> g_tune;
 
 template <typename T>
-FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs, hipStream_t s,
-                             Keep &keep);
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
+                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep);
 
 // Upload a host CSR in the device format that suits it.  With autotuning
 // on, matrices of at least kTuneMinNnz entries are timed on the device in
@@ -239,15 +304,19 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   d.nnz = h.nnz();
   const SliceStats st = slice_stats(h);
   const std::vector<int32_t> offs = h.nr > 0 ? dia_offsets(h) : std::vector<int32_t>{};
-  FormatChoice f = heuristic_format(h, st, !offs.empty());
-  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, offs, s, keep);
+  const std::vector<int32_t> hoffs = offs.empty() ? hyb_offsets(h) : std::vector<int32_t>{};
+  FormatChoice f = heuristic_format(h, st, !offs.empty(), !hoffs.empty());
+  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, offs, hoffs, s, keep);
   d.dia = f.dia;
+  d.hyb = f.hyb;
   d.sell = f.sell;
   d.scalar = f.scalar;
   d.lpr = f.lpr;
   d.batch = f.batch;
   if (f.dia)
     upload_dia_arrays(h, d, offs, s, keep);
+  else if (f.hyb)
+    upload_hyb_arrays(h, d, hoffs, s, keep);
   else if (f.sell)
     upload_sell_arrays(h, d, st, s, keep);
   else
@@ -464,6 +533,9 @@ double spmv_bytes(const DCsr<TA> &A) {
   // per row (zeros included) and no indices
   double b = A.dia ? static_cast<double>(sizeof(TA)) * A.ndiag * A.nr + 4.0 * A.ndiag
                    : (sizeof(TA) + 4.0) * A.nnz + 4.0 * (A.nr + 1.0);
+  if (A.hyb)  // diagonals (zeros included), then the remainder's entries and row pointers
+    b = static_cast<double>(sizeof(TA)) * A.ndiag * A.nr + 4.0 * A.ndiag + (sizeof(TA) + 4.0) * A.rem_nnz +
+        4.0 * (A.nr + 1.0);
   const double sx = sizeof(TX) * A.kb, sy = sizeof(TY) * A.kb;  // vectors once per block
   if (MODE == kPlain) b += sx * A.nc + sy * A.nr;
   if (MODE == kResid) b += sx * A.nc + 2 * sy * A.nr;
@@ -496,6 +568,15 @@ void spmv_kb(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y,
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
       hipLaunchKernelGGL((dia_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc,
                          A.ndiag, A.p(), A.v(), x, b, dinv, y, y2, gate.all, rp, gate.st, bk);
+    });
+    return;
+  }
+  if (A.hyb) {
+    const int blocks = (A.nr + kThreads - 1) / kThreads;
+    timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+      hipLaunchKernelGGL((hyb_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc,
+                         A.ndiag, dptr<const int>(A.doff), dptr<const TA>(A.dval), A.p(), A.c(), A.v(), x, b, dinv,
+                         y, y2, gate.all, rp, gate.st, bk);
     });
     return;
   }
@@ -558,14 +639,15 @@ T *mnull() {
 }
 
 // Time every candidate format of one matrix (kTuneReps residual products
-// each, after two untimed ones) and return the fastest.  Candidates: CSR with 2..64 lanes per row and 4 or 8
-// entries in flight per lane, CSR with one thread per row, and sliced ELL
-// when its padding stays within 2x.
+// each, after two untimed ones) and return the fastest.  Candidates: CSR with
+// 2..64 lanes per row and 4 or 8 entries in flight per lane, CSR with one
+// thread per row, sliced ELL when its padding stays within 2x, and the
+// diagonal layouts when the matrix has them.
 constexpr int kTuneReps = 10;
 
 template <typename T>
-FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs, hipStream_t s,
-                             Keep &keep) {
+FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
+                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep) {
   const TuneKey key{static_cast<int>(sizeof(T)), h.nr, h.nc, st.maxlen, h.nnz(), st.padded};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -594,6 +676,14 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
     dia.dia = true;
     upload_dia_arrays(h, dia, offs, s, keep);
   }
+  DCsr<T> hyb;
+  if (!hoffs.empty()) {
+    hyb.nr = h.nr;
+    hyb.nc = h.nc;
+    hyb.nnz = h.nnz();
+    hyb.hyb = true;
+    upload_hyb_arrays(h, hyb, hoffs, s, keep);
+  }
   DevMem xv(sizeof(T) * std::max<int32_t>(h.nc, 1)), bv(sizeof(T) * h.nr), yv(sizeof(T) * h.nr);
   MDP_HIP(hipMemsetAsync(xv.get(), 0, xv.bytes(), s));
   MDP_HIP(hipMemsetAsync(bv.get(), 0, bv.bytes(), s));
@@ -612,7 +702,7 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
     MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
     return ms;
   };
-  FormatChoice best = heuristic_format(h, st, !offs.empty());
+  FormatChoice best = heuristic_format(h, st, !offs.empty(), !hoffs.empty());
   float tbest = std::numeric_limits<float>::max();
   // CSR-vector shapes whose lanes are neither mostly idle (more lanes than
   // twice the average row) nor too few (a row needing more than four steps)
@@ -637,13 +727,18 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
     const float t = time_one(dia);
     if (t < tbest) tbest = t, best = FormatChoice{false, false, 8, kCsrBatch, true};
   }
+  if (!hoffs.empty()) {
+    const float t = time_one(hyb);
+    if (t < tbest) tbest = t, best = FormatChoice{false, false, 8, kCsrBatch, false, true};
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   MDP_HIP(hipStreamSynchronize(s));
   if (std::getenv("MDP_SETUP_VERBOSE"))
     std::fprintf(stderr, "[mdp] autotune %s n=%d nnz=%lld: %s lpr=%d batch=%d (%.2f us)\n",
                  sizeof(T) == 8 ? "f64" : "f32", h.nr, static_cast<long long>(h.nnz()),
-                 best.dia ? "dia" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector", best.lpr, best.batch,
+                 best.dia ? "dia" : best.hyb ? "dia+csr" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
+                 best.lpr, best.batch,
                  1e3 * tbest / kTuneReps);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.emplace(key, best);

@@ -20,9 +20,11 @@
 namespace mdp {
 
 // A device sparse matrix: diagonal storage (`dia`, `ptr` = the ndiag
-// offsets, `val` = ndiag x nr), sliced ELL (`sell`, 64-row slices, `ptr` =
-// slice offsets), CSR with one thread per row (`scalar`), or CSR with `lpr`
-// lanes per row and `batch` entries in flight per lane.
+// offsets, `val` = ndiag x nr), diagonals plus a CSR remainder (`hyb`: the
+// ndiag offsets in `doff`, their values ndiag x nr in `dval`, the remaining
+// rem_nnz entries in ptr / col / val), sliced ELL (`sell`, 64-row slices,
+// `ptr` = slice offsets), CSR with one thread per row (`scalar`), or CSR with
+// `lpr` lanes per row and `batch` entries in flight per lane.
 template <typename T>
 struct DCsr {
   int32_t nr = 0, nc = 0;
@@ -30,7 +32,10 @@ struct DCsr {
   int lpr = 8;
   int batch = 4;  // CSR-vector: entries in flight per lane
   bool dia = false;
+  bool hyb = false;
   int32_t ndiag = 0;
+  int64_t rem_nnz = 0;
+  DevMem doff, dval;
   bool sell = false;
   bool scalar = false;
   int32_t nslices = 0;

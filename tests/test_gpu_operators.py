@@ -33,12 +33,18 @@ TOL = {"fp64": 1e-11, "mixed": 3e-5}
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_operators_match_oracle(name, prec):
+@pytest.mark.parametrize("tune", ["autotune", "fixed-rule"])
+def test_operators_match_oracle(name, prec, tune):
+    """With the fixed rule every matrix takes its heuristic format (the
+    system matrix of these grids: diagonals plus a remainder); with the
+    autotuner, whichever format timed fastest."""
     sc = CASES[name]()
     A, b, part = tpfa.assemble(sc)
     Ao, bo, po = oa.assemble(sc)
     kw = dict(max_coarse=50)  # several levels even on small grids
-    say(f"[operators] case={name} prec={prec} n={A.shape[0]}")
+    if tune == "fixed-rule":
+        kw["flags"] = L.MDP_NO_AUTOTUNE
+    say(f"[operators] case={name} prec={prec} {tune} n={A.shape[0]}")
     s = Solver(A, part, precision=prec, **kw)
     M = precond.ML(Ao, po, cycles=1, amg_opts=amg.AMGOptions(max_coarse=50))
     try:
