@@ -881,17 +881,19 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__res
     uu[k] = in ? u[base + k * kThreads] : 0.0;
     ww[k] = in ? w[base + k * kThreads] : 0.0;
   }
-  int i = 0;
-  for (; i + 4 <= nq; i += 4) {
+  // newest columns first: the reduction pass has just read them, so they are
+  // the ones still in the Infinity Cache
+  int i = nq;
+  for (; i >= 4; i -= 4) {
     double ca[4], cb[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      ca[c] = cf->a[i + c];
-      cb[c] = cf->b[i + c];
+      ca[c] = cf->a[i - 1 - c];
+      cb[c] = cf->b[i - 1 - c];
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double *q = V + static_cast<int64_t>(i + c) * ld;
+      const double *q = V + static_cast<int64_t>(i - 1 - c) * ld;
 #pragma unroll
       for (int k = 0; k < kDotU; ++k) {
         const double qe = k * kThreads < lim ? q[base + k * kThreads] : 0.0;
@@ -900,9 +902,9 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__res
       }
     }
   }
-  for (; i < nq; ++i) {
-    const double ca = cf->a[i], cb = cf->b[i];
-    const double *q = V + static_cast<int64_t>(i) * ld;
+  for (; i > 0; --i) {
+    const double ca = cf->a[i - 1], cb = cf->b[i - 1];
+    const double *q = V + static_cast<int64_t>(i - 1) * ld;
 #pragma unroll
     for (int k = 0; k < kDotU; ++k) {
       const double qe = k * kThreads < lim ? q[base + k * kThreads] : 0.0;
