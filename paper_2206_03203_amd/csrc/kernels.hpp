@@ -723,7 +723,7 @@ __device__ __forceinline__ void pair_finish(GmresState *s, BatchCtl *ctl, int np
   if (atomicAdd(&ctl->ndone, 1) == npairs - 1) ctl->all_done = 1;
 }
 
-// Step j of the cycle for pair blockIdx.x (one thread does the O(j) scalar work):
+// Step j of the cycle for pair blockIdx.x (one wavefront):
 //  * j > 0: re-orthogonalise u_j against q_0..q_{j-1} (coefficients a) and
 //    finalise Hessenberg column j-1 = hprev + nu a, with subdiagonal nu r;
 //    apply the stored rotations, form rotation j-1, update g; the estimate
@@ -744,6 +744,9 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
                                                            double *__restrict__ cs_all, double *__restrict__ sn_all,
                                                            double *__restrict__ g_all, double *__restrict__ hist_all,
                                                            int ldv) {
+  // One wavefront per pair: the O(j) vector work (loads, dot products,
+  // column updates, stores) is spread over the 64 lanes; lane 0 runs the two
+  // rotation chains and the scalar decisions.
   const int p = blockIdx.x;
   GmresState *st = st_all + p;
   if (st->done) return;
@@ -758,77 +761,86 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
   const int kmax = kmaxp[p];
   const double tol_abs = tolp[p];
   __shared__ double a[kMaxCols + 1], b[kMaxCols + 1], col[kMaxCols + 2], sc[kMaxCols + 1], ss[kMaxCols + 1];
+  __shared__ int stop;
   const int t = threadIdx.x;
+  double paa = 0.0, pab = 0.0, pbb = 0.0;
   for (int i = t; i < j; i += 64) {
-    a[i] = sums[i];
-    b[i] = sums[j + i];
+    const double ai = sums[i], bi = sums[j + i];
+    a[i] = ai;
+    b[i] = bi;
     sc[i] = cs[i];
     ss[i] = sn[i];
     col[i] = hprev[i];
+    paa += ai * ai;
+    pab += ai * bi;
+    pbb += bi * bi;
   }
-  __syncthreads();
-  if (t != 0) return;
   const double alpha = sums[2 * j], beta = sums[2 * j + 1], gamma = sums[2 * j + 2];
+  const double saa = group_sum<64>(paa), sab = group_sum<64>(pab), sbb = group_sum<64>(pbb);
   bool bad = !isfinite(alpha) || !isfinite(beta) || !isfinite(gamma);
-  double saa = 0.0, sab = 0.0;
-  for (int i = 0; i < j; ++i) {
-    saa += a[i] * a[i];
-    sab += a[i] * b[i];
-  }
   const double r2 = alpha - saa;
   const double r = sqrt(r2 > 1e-30 * alpha ? r2 : 1e-30 * alpha);
+  if (t == 0) stop = 0;
   if (j == 0) {
-    g[0] = r;  // the cycle's first vector is the unnormalised residual
+    if (t == 0) g[0] = r;  // the cycle's first vector is the unnormalised residual
   } else {
     const double nu = st->nu;
-    for (int i = 0; i < j; ++i) col[i] += nu * a[i];
-    col[j] = nu * r;
-    // apply the stored rotations; the rotated entry carried to the next
-    // rotation stays in a register
-    double cur = col[0];
-    for (int i = 0; i + 1 < j; ++i) {
-      const double nxt = col[i + 1];
-      const double tt = sc[i] * cur + ss[i] * nxt;
-      cur = -ss[i] * cur + sc[i] * nxt;
-      col[i] = tt;
+    for (int i = t; i < j; i += 64) col[i] += nu * a[i];
+    if (t == 0) col[j] = nu * r;
+    __syncthreads();
+    if (t == 0) {
+      // apply the stored rotations; the rotated entry carried to the next
+      // rotation stays in a register
+      double cur = col[0];
+      for (int i = 0; i + 1 < j; ++i) {
+        const double nxt = col[i + 1];
+        const double tt = sc[i] * cur + ss[i] * nxt;
+        cur = -ss[i] * cur + sc[i] * nxt;
+        col[i] = tt;
+      }
+      col[j - 1] = cur;
+      double c, s, rr;
+      givens(col[j - 1], col[j], c, s, rr);
+      cs[j - 1] = c;
+      sn[j - 1] = s;
+      col[j - 1] = rr;
+      col[j] = 0.0;
+      const double gj = g[j - 1];
+      g[j] = -s * gj;
+      g[j - 1] = c * gj;
+      const double est = fabs(g[j]);
+      hist[j - 1] = est;
+      st->k = j;
+      st->est = est;
+      const bool bad1 = bad || !isfinite(est);
+      if (bad1 || st->finishing || est <= tol_abs) {
+        st->nan = bad1;
+        pair_finish(st, ctl, npairs);
+        stop = 1;
+      }
+      sc[j - 1] = c;  // the rotations now include the one just formed
+      ss[j - 1] = s;
     }
-    col[j - 1] = cur;
-    double c, s, rr;
-    givens(col[j - 1], col[j], c, s, rr);
-    cs[j - 1] = c;
-    sn[j - 1] = s;
-    col[j - 1] = rr;
-    col[j] = 0.0;
-    for (int i = 0; i <= j; ++i) Hr[static_cast<int64_t>(j - 1) * ldh + i] = col[i];
-    const double gj = g[j - 1];
-    g[j] = -s * gj;
-    g[j - 1] = c * gj;
-    const double est = fabs(g[j]);
-    hist[j - 1] = est;
-    st->k = j;
-    st->est = est;
-    bad = bad || !isfinite(est);
-    if (bad || st->finishing || est <= tol_abs) {
-      st->nan = bad;
-      pair_finish(st, ctl, npairs);
-      return;
-    }
-    sc[j - 1] = c;  // the rotations now include the one just formed
-    ss[j - 1] = s;
+    __syncthreads();
+    for (int i = t; i <= j; i += 64) Hr[static_cast<int64_t>(j - 1) * ldh + i] = col[i];
+    if (stop) return;
+    __syncthreads();  // col is rewritten below
   }
   // provisional column j
-  double sh = 0.0;
-  for (int i = 0; i < j; ++i) {
-    col[i] = b[i];
-    sh += b[i] * b[i];
-  }
   const double hj = (beta - sab) / r;
-  col[j] = hj;
-  sh += hj * hj;
+  const double sh = sbb + hj * hj;
+  for (int i = t; i < j; i += 64) col[i] = b[i];
+  if (t == 0) col[j] = hj;
   const double nu2 = gamma - sh;
   const bool brk = !(nu2 > 1e-24 * gamma);
   const double nu = sqrt(brk ? fmax(1e-24 * gamma, 1e-300) : nu2);
-  for (int i = 0; i <= j; ++i) hprev[i] = col[i];
+  __syncthreads();
+  for (int i = t; i <= j; i += 64) hprev[i] = col[i];
+  for (int i = t; i < j; i += 64) {
+    cf->a[i] = a[i];
+    cf->b[i] = b[i];
+  }
+  if (t != 0) return;
   // only the last entry of the rotated provisional column is needed: carry it
   double cur = col[0];
   for (int i = 0; i < j; ++i) cur = -ss[i] * cur + sc[i] * col[i + 1];
@@ -839,10 +851,6 @@ __global__ __launch_bounds__(64) void dcgs_finalize_kernel(GmresState *__restric
   cf->inv_r = 1.0 / r;
   cf->hj = hj;
   cf->inv_nu = 1.0 / nu;
-  for (int i = 0; i < j; ++i) {
-    cf->a[i] = a[i];
-    cf->b[i] = b[i];
-  }
   st->nu = nu;
   st->nan = bad;
   if (bad) {
