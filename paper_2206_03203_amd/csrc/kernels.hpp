@@ -116,7 +116,6 @@ __device__ __forceinline__ Acc spmv_gather(int c, const TX *__restrict__ x, cons
 
 // CSR-vector kernel for long rows: LPR lanes per row, each lane keeps BATCH
 // entries in flight (indices and values loaded before the gathers).
-constexpr int kCsrBatch = 4;  // the fixed rule's batch
 
 template <int LPR, int BATCH, int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void spmv_kernel(
@@ -225,7 +224,6 @@ __global__ __launch_bounds__(kThreads) void sell_kernel(
 // ascending, so each row is summed in column order as in the other formats.
 // One thread per row; no column indices are read and the gathers of a
 // wavefront are contiguous.
-constexpr int kMaxDiag = 16;
 constexpr int kDiaBatch = 8;
 
 template <int KB, int MODE, typename TA, typename TX, typename TY>

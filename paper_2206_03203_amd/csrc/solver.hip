@@ -29,6 +29,7 @@
 #include <type_traits>
 #include <unordered_map>
 
+#include "formats.hpp"
 #include "kernels.hpp"
 #include "ktimer.hpp"
 #include "solver.hpp"
@@ -39,15 +40,6 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Upload helpers
-
-// Lanes per row for the CSR-vector kernel: enough that one batch of
-// kCsrBatch entries per lane covers an average row.
-int choose_lpr(int64_t nnz, int32_t nr) {
-  const double avg = nr > 0 ? static_cast<double>(nnz) / nr : 0.0;
-  int l = 4;
-  while (l * kCsrBatch < avg && l < 64) l *= 2;
-  return l;
-}
 
 template <typename T>
 void upload_vec(DevMem &d, const std::vector<T> &h, hipStream_t s) {
@@ -82,106 +74,6 @@ struct Keep {
 
 // Device formats of a sparse matrix, and the setup-time autotuner that picks
 // one per matrix by timing the candidates on the device.
-struct FormatChoice {
-  bool sell = false;
-  bool scalar = false;
-  int lpr = 8;
-  int batch = kCsrBatch;  // CSR-vector entries in flight per lane (4 or 8)
-  bool dia = false;
-  bool hyb = false;
-};
-
-struct SliceStats {
-  int64_t padded = 0;  // entries of the sliced-ELL layout (64-row slices)
-  int32_t maxlen = 0;
-};
-
-SliceStats slice_stats(const HCsr &h) {
-  SliceStats st;
-  const int32_t ns = (h.nr + 63) / 64;
-  for (int32_t sl = 0; sl < ns; ++sl) {
-    int32_t w = 0;
-    for (int32_t r = sl * 64; r < std::min(h.nr, sl * 64 + 64); ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
-    st.padded += 64 * static_cast<int64_t>(w);
-    st.maxlen = std::max(st.maxlen, w);
-  }
-  return st;
-}
-
-bool sell_possible(const SliceStats &st, int64_t nnz, double max_padding) {
-  return st.maxlen <= 64 && static_cast<double>(st.padded) <= max_padding * static_cast<double>(std::max<int64_t>(nnz, 1)) &&
-         st.padded < std::numeric_limits<int32_t>::max();
-}
-
-// The distinct diagonal offsets (column - row) of a matrix, ascending, when
-// there are at most kMaxDiag of them and the diagonal layout pads the
-// entries by at most 20%; empty otherwise.
-std::vector<int32_t> dia_offsets(const HCsr &h) {
-  std::vector<int32_t> offs;
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const int32_t d = h.col[k] - i;
-      const auto it = std::lower_bound(offs.begin(), offs.end(), d);
-      if (it != offs.end() && *it == d) continue;
-      if (static_cast<int>(offs.size()) == kMaxDiag) return {};
-      offs.insert(it, d);
-    }
-  if (static_cast<double>(offs.size()) * h.nr > 1.2 * static_cast<double>(std::max<int64_t>(h.nnz(), 1))) return {};
-  return offs;
-}
-
-// Diagonals for the diagonals-plus-remainder layout: the offsets that hold
-// an entry in at least half of the rows (at most kMaxDiag, the fullest), when
-// together they hold at least 80% of the entries with at most 25% padding;
-// empty otherwise.  Rows of more than kMaxDiag + 4 entries on average are
-// not looked at.
-std::vector<int32_t> hyb_offsets(const HCsr &h) {
-  if (h.nr == 0 || h.nnz() > static_cast<int64_t>(kMaxDiag + 4) * h.nr) return {};
-  std::unordered_map<int32_t, int64_t> count;
-  count.reserve(64);
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) ++count[h.col[k] - i];
-  std::vector<std::pair<int64_t, int32_t>> full;
-  for (const auto &c : count)
-    if (2 * c.second >= h.nr) full.emplace_back(c.second, c.first);
-  std::sort(full.begin(), full.end(), [](const auto &a, const auto &b) {
-    return a.first != b.first ? a.first > b.first : a.second < b.second;
-  });
-  if (full.size() > static_cast<size_t>(kMaxDiag)) full.resize(kMaxDiag);
-  int64_t covered = 0;
-  std::vector<int32_t> offs;
-  for (const auto &f : full) {
-    covered += f.first;
-    offs.push_back(f.second);
-  }
-  std::sort(offs.begin(), offs.end());
-  const double stored = static_cast<double>(offs.size()) * h.nr;
-  if (offs.empty() || covered < 0.8 * h.nnz() || stored > 1.25 * covered) return {};
-  return offs;
-}
-
-// Fixed rule (also the autotuner's fallback): diagonal storage for stencil
-// matrices, diagonals plus a remainder for stencils with a few irregular
-// couplings, sliced ELL when the slices carry at most 15% padding, one
-// thread per row for other short rows, else enough lanes per row for
-// kCsrBatch entries each.
-FormatChoice heuristic_format(const HCsr &h, const SliceStats &st, bool dia_ok, bool hyb_ok) {
-  FormatChoice f;
-  if (dia_ok) {
-    f.dia = true;
-    return f;
-  }
-  if (hyb_ok) {
-    f.hyb = true;
-    return f;
-  }
-  const int64_t nnz = h.nnz();
-  f.lpr = choose_lpr(nnz, h.nr);
-  f.sell = h.nr > 0 && sell_possible(st, nnz, 1.15);
-  f.scalar = !f.sell && (h.nr > 0 ? static_cast<double>(nnz) / h.nr : 0.0) <= 12.0;
-  return f;
-}
-
 template <typename T>
 void upload_csr_arrays(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   upload_vec(d.ptr, h.ptr, s);
@@ -190,79 +82,37 @@ void upload_csr_arrays(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
 }
 
 template <typename T>
+std::vector<T> as_type(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+template <typename T>
 void upload_sell_arrays(const HCsr &h, DCsr<T> &d, const SliceStats &st, hipStream_t s, Keep &keep) {
-  const int32_t ns = (h.nr + 63) / 64;
-  d.nslices = ns;
-  std::vector<int32_t> soff(static_cast<size_t>(ns) + 1, 0), col(static_cast<size_t>(st.padded));
-  std::vector<T> val(static_cast<size_t>(st.padded), T(0));
-  int64_t o = 0;
-  for (int32_t sl = 0; sl < ns; ++sl) {
-    const int32_t r0 = sl * 64, r1 = std::min(h.nr, r0 + 64);
-    int32_t w = 0, first = 0;
-    for (int32_t r = r1 - 1; r >= r0; --r) {
-      w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
-      if (h.ptr[r + 1] > h.ptr[r]) first = h.col[h.ptr[r]];
-    }
-    soff[sl] = static_cast<int32_t>(o);
-    for (int32_t lane = 0; lane < 64; ++lane) {
-      const int32_t r = r0 + lane;
-      const int32_t len = r < r1 ? h.ptr[r + 1] - h.ptr[r] : 0;
-      int32_t lastc = first;  // padding: a valid, nearby column with value 0
-      for (int32_t k = 0; k < w; ++k) {
-        const int64_t dst = o + static_cast<int64_t>(k) * 64 + lane;
-        if (k < len) {
-          lastc = h.col[h.ptr[r] + k];
-          val[dst] = static_cast<T>(h.val[h.ptr[r] + k]);
-        }
-        col[dst] = lastc;
-      }
-    }
-    o += static_cast<int64_t>(w) * 64;
-  }
-  soff[ns] = static_cast<int32_t>(o);
-  upload_vec(d.ptr, keep.put(std::move(soff)), s);
-  upload_vec(d.col, keep.put(std::move(col)), s);
-  upload_vec(d.val, keep.put(std::move(val)), s);
+  SellLayout L = sell_layout(h, st);
+  d.nslices = L.nslices;
+  upload_vec(d.ptr, keep.put(std::move(L.soff)), s);
+  upload_vec(d.col, keep.put(std::move(L.col)), s);
+  upload_vec(d.val, keep.put(as_type<T>(L.val)), s);
 }
 
 template <typename T>
 void upload_dia_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &offs, hipStream_t s, Keep &keep) {
+  DiaLayout L = dia_layout(h, offs);
   d.ndiag = static_cast<int32_t>(offs.size());
-  std::vector<T> val(offs.size() * static_cast<size_t>(h.nr), T(0));
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const size_t di = std::lower_bound(offs.begin(), offs.end(), h.col[k] - i) - offs.begin();
-      val[di * h.nr + i] = static_cast<T>(h.val[k]);
-    }
-  upload_vec(d.ptr, keep.put(std::vector<int32_t>(offs)), s);
-  upload_vec(d.val, keep.put(std::move(val)), s);
+  upload_vec(d.ptr, keep.put(std::move(L.offs)), s);
+  upload_vec(d.val, keep.put(as_type<T>(L.val)), s);
 }
 
 template <typename T>
 void upload_hyb_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &offs, hipStream_t s, Keep &keep) {
+  HybLayout L = hyb_layout(h, offs);
   d.ndiag = static_cast<int32_t>(offs.size());
-  std::vector<T> dval(offs.size() * static_cast<size_t>(h.nr), T(0));
-  std::vector<int32_t> ptr(static_cast<size_t>(h.nr) + 1, 0), col;
-  std::vector<T> val;
-  for (int32_t i = 0; i < h.nr; ++i) {
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const int32_t off = h.col[k] - i;
-      const auto it = std::lower_bound(offs.begin(), offs.end(), off);
-      if (it != offs.end() && *it == off) {
-        dval[static_cast<size_t>(it - offs.begin()) * h.nr + i] = static_cast<T>(h.val[k]);
-      } else {
-        col.push_back(h.col[k]);
-        val.push_back(static_cast<T>(h.val[k]));
-      }
-    }
-    ptr[i + 1] = static_cast<int32_t>(col.size());
-  }
-  d.rem_nnz = static_cast<int64_t>(col.size());
-  upload_vec(d.doff, keep.put(std::vector<int32_t>(offs)), s);
-  upload_vec(d.dval, keep.put(std::move(dval)), s);
-  upload_vec(d.ptr, keep.put(std::move(ptr)), s);
-  upload_vec(d.col, keep.put(std::move(col)), s);
-  upload_vec(d.val, keep.put(std::move(val)), s);
+  d.rem_nnz = static_cast<int64_t>(L.col.size());
+  upload_vec(d.doff, keep.put(std::move(L.offs)), s);
+  upload_vec(d.dval, keep.put(as_type<T>(L.dval)), s);
+  upload_vec(d.ptr, keep.put(std::move(L.ptr)), s);
+  upload_vec(d.col, keep.put(std::move(L.col)), s);
+  upload_vec(d.val, keep.put(as_type<T>(L.val)), s);
 }
 
 // Autotuning is on while an AutotuneScope with on = true is alive on this
@@ -1211,67 +1061,15 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
 
 // ---------------------------------------------------------------------------
 
-// Tiles.  Each Arnoldi pass gives one workgroup per tile and every tile the
-// same work, so the tile count is a multiple of the 256 compute units when
-// the vectors are long enough (a partly filled last round of workgroups costs
-// as much as a full one), with at most kTileElems entries per tile and, for
-// short vectors, at least kMinTile.  The tiles are shared among the ranges in
-// proportion to their lengths (largest remainders first); each range is cut
-// into tiles whose lengths differ by at most one.
-constexpr int64_t kCus = 256;
-constexpr int64_t kMinTile = 64;
-
-int64_t tile_target(int64_t n) {
-  const int64_t fewest = (n + kTileElems - 1) / kTileElems;
-  const int64_t most = std::max<int64_t>(1, (n + kMinTile - 1) / kMinTile);
-  const int64_t balanced = (fewest + kCus - 1) / kCus * kCus;
-  return std::min(balanced, std::max(fewest, most));
-}
-
 void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &ranges, int64_t n_total,
                    hipStream_t s) {
   npairs = static_cast<int>(ranges.size());
   n = n_total;
   rows.assign(static_cast<size_t>(npairs), 0);
-  struct Share {
-    int p;
-    int64_t start, len, k;
-    double rem;
-  };
-  std::vector<Share> sh;
-  int64_t total = 0;
   for (int p = 0; p < npairs; ++p)
-    for (const auto &r : ranges[p]) {
-      rows[p] += r.second;
-      total += r.second;
-      if (r.second > 0) sh.push_back(Share{p, r.first, r.second, 0, 0.0});
-    }
-  const int64_t target = tile_target(total);
-  int64_t given = 0;
-  for (Share &x : sh) {
-    const double exact = static_cast<double>(x.len) * target / std::max<int64_t>(total, 1);
-    x.k = static_cast<int64_t>(exact);
-    x.rem = exact - x.k;
-    given += x.k;
-  }
-  std::vector<size_t> by_rem(sh.size());
-  for (size_t i = 0; i < sh.size(); ++i) by_rem[i] = i;
-  std::stable_sort(by_rem.begin(), by_rem.end(), [&](size_t a, size_t b) { return sh[a].rem > sh[b].rem; });
-  for (size_t i = 0; i < by_rem.size() && given < target; ++i, ++given) ++sh[by_rem[i]].k;
-  std::vector<Tile> tl;
-  std::vector<int32_t> off(static_cast<size_t>(npairs) + 1, 0);
-  size_t q = 0;
-  for (int p = 0; p < npairs; ++p) {
-    for (; q < sh.size() && sh[q].p == p; ++q) {
-      Share &x = sh[q];
-      x.k = std::min(x.len, std::max({x.k, int64_t{1}, (x.len + kTileElems - 1) / kTileElems}));
-      for (int64_t i = 0; i < x.k; ++i) {
-        const int64_t lo = i * x.len / x.k, hi = (i + 1) * x.len / x.k;
-        tl.push_back(Tile{x.start + lo, static_cast<int32_t>(hi - lo), p});
-      }
-    }
-    off[p + 1] = static_cast<int32_t>(tl.size());
-  }
+    for (const auto &r : ranges[p]) rows[p] += r.second;
+  std::vector<int32_t> off;
+  const std::vector<Tile> tl = plan_tiles(ranges, off);
   ntiles = static_cast<int>(tl.size());
   upload_vec(tiles, tl, s);
   upload_vec(tile_off, off, s);

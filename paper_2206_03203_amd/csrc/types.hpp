@@ -9,6 +9,8 @@ constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 constexpr int kRedBlocks = 1024;  // fixed number of partial sums per reduction
 constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi pass
+constexpr int kCsrBatch = 4;       // CSR-vector entries in flight per lane under the fixed rule
+constexpr int kMaxDiag = 16;       // most offsets of the diagonal layouts
 constexpr int kMultiRhs = 4;       // right-hand sides that share one matrix read in a batch
 constexpr int kDotU = 9;          // elements per thread in the Arnoldi passes (tiles of up to 2304)
 constexpr int kTileElems = 256 * kDotU;
