@@ -27,7 +27,6 @@
 #include <mutex>
 #include <tuple>
 #include <type_traits>
-#include <unordered_map>
 
 #include "formats.hpp"
 #include "kernels.hpp"
