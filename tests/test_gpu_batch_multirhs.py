@@ -160,3 +160,43 @@ def test_four_rhs_chunks(monkeypatch, capfd):
     finally:
         for s in solvers:
             s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_four_rhs_initial_guesses_and_budget(prec):
+    """Shared matrices with MDP_USE_X0 (each pair starts from its own guess,
+    gathered in the internal right-hand-side-major order) and with an
+    iteration budget that stops some pairs unconverged: every pair matches
+    its solve alone, stats land in the caller's order."""
+    cases = [(synth.random_2d(21, n_range=(40, 70), max_segments=6), dict(max_coarse=50)),
+             (synth.regular_3d(n=10, k_par=1e4, kappa=1e-4, seed=6), dict(max_coarse=50))]
+    for flags, max_iter in ((L.MDP_USE_X0, 1000), (0, 6)):
+        solvers, bs, x0s = [], [], []
+        for i, (sc, kw) in enumerate(cases):
+            fs = [synth.host_sources(sc, 300 + 10 * i + k) for k in range(NRHS)]
+            A, B, part = tpfa.assemble(sc, sources=fs)
+            solvers.append(Solver(A, part, precision=prec, flags=flags, max_iter=max_iter, **kw))
+            bs.append(dev(B.T.copy()))
+            x0s.append(dev(np.stack([synth.random_vector(A.shape[0], 700 + 10 * i + k) * 0.1 for k in range(NRHS)])))
+        say(f"[batch-rhs] prec={prec} flags={flags} max_iter={max_iter}")
+        try:
+            xs = [x0.clone() for x0 in x0s]
+            rc, st = L.mdp_solve_batch([s.handle for s in solvers], bs, xs)
+            k = 0
+            for i, s in enumerate(solvers):
+                for r in range(NRHS):
+                    x1 = x0s[i][r].clone()
+                    _, st1 = s.solve(bs[i][r].clone(), x1)
+                    assert st[k]["converged"] == st1[0]["converged"]
+                    assert abs(st[k]["iters"] - st1[0]["iters"]) <= 1
+                    if max_iter < 1000:
+                        assert st[k]["iters"] <= max_iter
+                    d = relerr(host(xs[i][r]), host(x1))
+                    say(f"    sys={i} rhs={r} iters={st[k]['iters']}/{st1[0]['iters']} conv={st[k]['converged']} diff={d:.1e}")
+                    assert d <= (1e-6 if st1[0]["converged"] else 1e-3)
+                    k += 1
+            if max_iter < 1000:
+                assert rc == L.MDP_NOT_CONVERGED
+        finally:
+            for s in solvers:
+                s.close()
