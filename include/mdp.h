@@ -71,12 +71,15 @@ extern "C" {
                               at every size).  Not with MDP_GRAPHS. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
-                              (diagonal storage for stencil matrices, sliced
-                              ELL, CSR with one thread per row, CSR with 2..64
-                              lanes per row and 4 or 8 entries in flight per
-                              lane) on the device and keeping the fastest.  The format changes only the order of
-                              the additions in each row; equal matrices get
-                              equal formats within a process. */
+                              (diagonal storage for stencil matrices,
+                              diagonals plus a CSR remainder for stencils
+                              with irregular couplings, sliced ELL, CSR with
+                              one thread per row, CSR with 2..64 lanes per
+                              row and 4 or 8 entries in flight per lane) on
+                              the device and keeping the fastest.  The format
+                              changes only the order of the additions in each
+                              row; equal matrices get equal formats within a
+                              process. */
 
 /* ---- block preconditioner (Section 3.2: the factorisation eq. (5) gives
  *      B_L = (D L)^-1, B_D = D^-1 and B_U = (U D)^-1; each is made inexact
