@@ -389,26 +389,9 @@ __global__ __launch_bounds__(kThreads) void hyb_kernel(
                             blk(y2, r * bk.ys));
 }
 
-// Coarsest level: x = Ainv b with a dense FP64 inverse (row-major n x n); one
-// wavefront per row, FP64 accumulation whatever the vector type.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void dense_gemv_kernel(int n, const double *__restrict__ ainv,
-                                                              const T *__restrict__ b,
-                                                              T *__restrict__ x,
-                                                              const int *__restrict__ gate) {
-  if (gate && *gate) return;
-  const int row = blockIdx.x * (kThreads / 64) + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (row >= n) return;
-  const double *a = ainv + static_cast<size_t>(row) * n;
-  double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += a[j] * static_cast<double>(b[j]);
-  s = group_sum<64>(s);
-  if (lane == 0) x[row] = static_cast<T>(s);
-}
-
-// Coarsest levels of several systems at once: x = Ainv_d b on each
-// descriptor's rows; grid (ceil(max n / 4), ndesc), one wavefront per row.
+// Coarsest levels (dense FP64 inverses, row-major): x = Ainv_d b on each
+// descriptor's rows; grid (ceil(max n / 4), ndesc), one wavefront per row,
+// FP64 accumulation whatever the vector type.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void dense_gemv_batched_kernel(const DenseDesc *__restrict__ desc,
                                                                       const double *__restrict__ ainv,
@@ -533,13 +516,6 @@ __device__ __forceinline__ T block_sum(T v, T *lds /* kThreads/64 entries */) {
     for (int k = 0; k < kThreads / 64; ++k) r += lds[k];
   }
   return r;  // valid in thread 0
-}
-
-// Contiguous element range of reduction block `blk` out of kRedBlocks.
-__device__ __forceinline__ void red_range(int64_t n, int blk, int64_t &lo, int64_t &hi) {
-  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
-  lo = blk * chunk;
-  hi = lo + chunk < n ? lo + chunk : n;
 }
 
 // ---------------------------------------------------------------------------

@@ -7,7 +7,6 @@ namespace mdp {
 
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;
-constexpr int kRedBlocks = 1024;  // fixed number of partial sums per reduction
 constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi pass
 constexpr int kCsrBatch = 4;       // CSR-vector entries in flight per lane under the fixed rule
 constexpr int kMaxDiag = 16;       // most offsets of the diagonal layouts
