@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--n", type=int, default=100, help="host cells per side")
     p.add_argument("--seeds", type=int, default=1, help="log-normal seeds per (K_par, kappa) pair")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
+    p.add_argument("--max-coarse", type=int, default=400,
+                   help="AMG: stop coarsening at this many unknowns (the coarsest is dense up to 2000)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="only run a device-to-device copy of this many MiB (5 times) and exit; used to "
@@ -126,8 +128,10 @@ def main():
             t1 = time.perf_counter()
             fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | _graph_flags(args)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
-            o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf)
-            o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf)
+            o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf,
+                                        max_coarse=args.max_coarse)
+            o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf,
+                                        max_coarse=args.max_coarse)
             hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
@@ -203,7 +207,8 @@ def main():
     # between kernels, not the kernels).
     roofline, classes = roofline_pass(lambda: run("fp64", args.steps), args.kernel_class,
                                       f"the {args.steps} FP64 steps repeated", fp["seconds"])
-    if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower":
+    if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
+            args.max_coarse == 400 and args.n == 100:
         roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{args.n}")
 
     cpu = None
@@ -235,6 +240,7 @@ def main():
         "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
+                   "amg_max_coarse": args.max_coarse,
                    "autotune": not args.no_autotune,
                    "graphs": _graph_policy(args),
                    "block_preconditioner": args.block},
