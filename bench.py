@@ -71,9 +71,7 @@ def parse():
     p.add_argument("--block", choices=["lower", "diag", "upper"], default="lower",
                    help="block preconditioner: M_L (eq. 8, the paper's), or the inexact B_D / B_U of Section 3.2")
     p.add_argument("--graphs", action="store_true",
-                   help="replay each Arnoldi step from a captured HIP graph at every size (MDP_GRAPHS)")
-    p.add_argument("--no-graphs", action="store_true",
-                   help="never replay graphs (MDP_NO_GRAPHS); by default systems of at most 131072 unknowns do")
+                   help="replay each Arnoldi step from a captured HIP graph instead of launching its kernels")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the fixed rule for sparse formats instead of timing candidates at setup")
     p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
@@ -126,7 +124,7 @@ def main():
             t0 = time.perf_counter()
             A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
-            fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | _graph_flags(args)
+            fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
             o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf,
                                         max_coarse=args.max_coarse)
@@ -241,8 +239,7 @@ def main():
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
                    "amg_max_coarse": args.max_coarse,
-                   "autotune": not args.no_autotune,
-                   "graphs": _graph_policy(args),
+                   "autotune": not args.no_autotune, "graphs": args.graphs,
                    "block_preconditioner": args.block},
         "p50_ms": pct(fp["lat"], 50),
         "p99_ms": pct(fp["lat"], 99),
@@ -332,15 +329,6 @@ def _pct(a, q):
     return round(1e3 * float(np.percentile(a, q)), 3) if len(a) else None
 
 
-def _graph_flags(args):
-    from paper_2206_03203_amd import _lib as L
-    return (L.MDP_GRAPHS if args.graphs else 0) | (L.MDP_NO_GRAPHS if args.no_graphs else 0)
-
-
-def _graph_policy(args):
-    return "all sizes" if args.graphs else "never" if args.no_graphs else "at most 131072 unknowns"
-
-
 def _setup_pool(scs, sources_per_sys, precisions, stream, tag, flags=0):
     """Assemble and set up every scenario; returns a list of dicts holding the
     handles (one per precision, sharing the host setup), the right-hand sides
@@ -391,7 +379,7 @@ def mode_batch(args):
     scs = [synth.random_2d(s) for s in range(args.systems)]
     srcs = [[synth.host_sources(sc, 4 * s + k) for k in range(args.rhs)] for s, sc in enumerate(scs)]
     pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch",
-                                     (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | _graph_flags(args))
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
     pairs = sum(p["b"].shape[0] for p in pool)
     unknowns = sum(p["n"] * p["b"].shape[0] for p in pool)
     xs = [torch.zeros_like(p["b"]) for p in pool]
@@ -450,8 +438,7 @@ def mode_batch(args):
         "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
         "config": {"workload": f"2d-uneven-batch-{args.systems}x{args.rhs}", "systems": len(pool),
                    "pairs": pairs, "unknowns_total": unknowns,
-                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8,
-                   "graphs_in_sequential_solves": _graph_policy(args)},
+                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8},
         "iters_mean": round(float(np.mean(its_b)), 2), "iters_max": int(max(its_b)),
         "max_rel_res": max(s["rel_res_true"] for s in st_b),
         "sequential_mixed": {"value": round(pairs / t_seq, 2), "unit": "solves/s",
@@ -480,7 +467,7 @@ def mode_serve(args):
     nb = 4  # right-hand sides per system to draw requests from
     srcs = [[synth.host_sources(sc, 4 * (3000 + s) + k) for k in range(nb)] for s, sc in enumerate(scs)]
     pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed",), stream, "serve",
-                                     (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | _graph_flags(args))
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
     budget = int(args.budget_gb * (1 << 30))
     srv = L.mdp_server_create(budget, args.slots)
     for p in pool:
@@ -567,7 +554,7 @@ def mode_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
         "config": {"workload": f"serving-pool-{len(pool)}-2d64-512-3d40-160", "slots": args.slots,
-                   "budget_gb": args.budget_gb, "requests_per_rate": args.requests, "graphs": _graph_policy(args),
+                   "budget_gb": args.budget_gb, "requests_per_rate": args.requests,
                    "unknowns_range": [min(p["n"] for p in pool), max(p["n"] for p in pool)]},
         "saturated": {"solves_per_s": round(sat, 2), "p50_ms": _pct(lat_sat, 50), "p99_ms": _pct(lat_sat, 99),
                       "iters_mean": round(float(np.mean(it_sat)), 2)},

@@ -59,16 +59,11 @@ extern "C" {
                               without a GPU.  Solve calls then return EINVAL. */
 #define MDP_GRAPHS 8u      /* mdp_solve: replay each Arnoldi step from a HIP graph
                               captured on first use instead of launching its
-                              kernels one by one, at every system size
-                              (single-system solves; never while kernel timers
-                              run).  Same kernels and results.  Without this
-                              flag, systems of at most 131072 unknowns replay
-                              graphs anyway (where launches dominate: 5-20%
-                              less time per iteration measured on 4k-70k
-                              unknowns) and larger ones launch directly (about
-                              2% faster at 1.09M unknowns). */
-#define MDP_NO_GRAPHS 16u  /* mdp_solve: never replay graphs (direct launches
-                              at every size).  Not with MDP_GRAPHS. */
+                              kernels one by one (single-system solves; never
+                              while kernel timers run).  Same kernels and
+                              results.  Measured on small, launch-bound systems
+                              (4k-70k unknowns): 5-20% less time per iteration;
+                              on 100^3 systems: about 2% more. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,
@@ -127,7 +122,7 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length m (64, at most 64)                  */
   int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
-  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS | MDP_NO_GRAPHS */
+  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS */
   int32_t block_form;     /* MDP_BLOCK_LOWER (default), MDP_BLOCK_DIAG, MDP_BLOCK_UPPER */
 } mdp_options;
 

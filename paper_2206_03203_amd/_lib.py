@@ -44,7 +44,7 @@ if len(_hip_runtimes()) > 1:
 MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING = 0, 1, 2
 MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP_EBUSY = -1, -2, -3, -4, -5, -6, -7
 MDP_FP64, MDP_MIXED = 0, 1
-MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS, MDP_NO_GRAPHS = 1, 2, 4, 8, 16
+MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS = 1, 2, 4, 8
 MDP_BLOCK_LOWER, MDP_BLOCK_DIAG, MDP_BLOCK_UPPER = 0, 1, 2
 MDP_OP_A, MDP_OP_ML, MDP_OP_QOO, MDP_OP_QGG = 0, 1, 2, 3
 MDP_BLOCK_OMEGA, MDP_BLOCK_GAMMA = 0, 1

@@ -82,9 +82,7 @@ int check_options(const mdp_options &o) {
   if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
   if (o.max_iter < 0) return bad("max_iter must be >= 0");
   if (!(o.rtol > 0.0)) return bad("rtol must be > 0");
-  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS | MDP_NO_GRAPHS))
-    return bad("unknown bits in flags");
-  if ((o.flags & MDP_GRAPHS) && (o.flags & MDP_NO_GRAPHS)) return bad("MDP_GRAPHS and MDP_NO_GRAPHS together");
+  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS)) return bad("unknown bits in flags");
   if (o.block_form != MDP_BLOCK_LOWER && o.block_form != MDP_BLOCK_DIAG && o.block_form != MDP_BLOCK_UPPER)
     return bad("block_form must be MDP_BLOCK_LOWER, MDP_BLOCK_DIAG or MDP_BLOCK_UPPER");
   return MDP_OK;

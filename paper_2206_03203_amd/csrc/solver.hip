@@ -782,16 +782,6 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
 // ---------------------------------------------------------------------------
 // FGMRES over a batch of pairs
 
-// Single-system solves replay their Arnoldi steps from captured graphs when
-// MDP_GRAPHS asks for it, or by default for systems of at most
-// kGraphAutoUnknowns unknowns, where launches rather than bytes bound a step.
-constexpr int64_t kGraphAutoUnknowns = 131072;
-
-bool graphs_wanted(const mdp_options &o, int64_t n) {
-  if (o.flags & MDP_GRAPHS) return true;
-  return !(o.flags & MDP_NO_GRAPHS) && n <= kGraphAutoUnknowns;
-}
-
 // Capture the launches that `enqueue` makes on stream s into an executable
 // graph; false (and no graph) if capture or instantiation fails.
 template <typename F>
@@ -876,10 +866,10 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     beta = bnorm;
   }
 
-  // Single-system solves may replay each step from a captured graph (see
-  // graphs_wanted; not on the legacy stream, which cannot be captured, and
-  // not while timers run).
-  bool use_graphs = np == 1 && graphs_wanted(opt, n) && !ktimer_any_on() && !ws.graphs_failed && s != nullptr;
+  // With MDP_GRAPHS, single-system solves replay each step from a captured
+  // graph (not on the legacy stream, which cannot be captured, and not while
+  // timers run).
+  bool use_graphs = np == 1 && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed && s != nullptr;
   if (use_graphs && ws.gexec.size() != static_cast<size_t>(2 * (m + 1))) ws.gexec.assign(2 * (m + 1), nullptr);
   while (true) {
     int nactive = 0, kmax_all = 0;
@@ -1216,7 +1206,7 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   // The legacy stream cannot be captured: a solve handed it runs on the
   // workspace's own stream, after the caller's earlier work on s.
   const hipStream_t caller = s;
-  if (s == nullptr && graphs_wanted(opt, n) && !ktimer_any_on() && !ws.graphs_failed) {
+  if (s == nullptr && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed) {
     s = ws.own_stream();
     MDP_HIP(hipEventRecord(ws.handoff, caller));
     MDP_HIP(hipStreamWaitEvent(s, ws.handoff, 0));

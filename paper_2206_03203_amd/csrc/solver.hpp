@@ -129,7 +129,7 @@ struct Workspace {
   GmresState *host_state = nullptr;  // pinned, npairs
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
-  // Single-system solves that replay graphs (MDP_GRAPHS, or small systems by default) capture each Arnoldi step:
+  // With MDP_GRAPHS, single-system solves replay each Arnoldi step from a captured graph:
   // gexec[j] for step j, gexec[m + 1 + j] for a cycle's last step j (which
   // reuses preconditioned column j - 1).  Valid while the workspace lives.
   std::vector<hipGraphExec_t> gexec;

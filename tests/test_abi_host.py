@@ -225,19 +225,6 @@ def test_unknown_flag_bits_rejected():
     assert e.value.code == L.MDP_EINVAL
 
 
-def test_graph_flags_exclusive():
-    """MDP_GRAPHS forces graph replay, MDP_NO_GRAPHS forbids it: not both."""
-    sc = synth.tiny_2d(6)
-    A, b, part = tpfa.assemble(sc)
-    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | L.MDP_GRAPHS | L.MDP_NO_GRAPHS)
-    with pytest.raises(L.MdpError) as e:
-        L.mdp_setup(A, part, o)
-    assert e.value.code == L.MDP_EINVAL
-    for f in (L.MDP_GRAPHS, L.MDP_NO_GRAPHS):
-        h = L.mdp_setup(A, part, L.mdp_options_default(flags=L.MDP_HOST_ONLY | f))
-        L.mdp_destroy(h)
-
-
 def _all_levels(h):
     info = L.mdp_info(h)
     out = []

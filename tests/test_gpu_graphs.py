@@ -1,10 +1,9 @@
-"""Arnoldi steps replayed from captured HIP graphs give exactly the results
-of direct launches (MDP_NO_GRAPHS): forced (MDP_GRAPHS) and by default on
-small systems; several solves in a row on the same handle, with other device
-work in between, on torch's default (legacy) stream and on a side stream;
-restarts whose last cycle is shorter than the restart length (the last-step
-graph variant); two V-cycles on a system whose finest level is solved densely
-(the zero-fill inside a captured step)."""
+"""Arnoldi steps replayed from captured HIP graphs (MDP_GRAPHS) give exactly
+the results of direct launches: several solves in a row on the same
+handle, with other device work in between, on torch's default (legacy)
+stream and on a side stream; restarts whose last cycle is shorter than the
+restart length (the last-step graph variant); two V-cycles on a system whose
+finest level is solved densely (the zero-fill inside a captured step)."""
 
 import numpy as np
 import pytest
@@ -19,12 +18,11 @@ from gpu_common import dev, say
 pytestmark = pytest.mark.gpu
 
 
-def _pair(A, part, graph_flag=L.MDP_GRAPHS, **kw):
+def _pair(A, part, **kw):
     o1 = L.mdp_options_default(**kw)
-    o1.flags |= graph_flag  # 0: the default policy (graphs at these sizes)
+    o1.flags |= L.MDP_GRAPHS
     h1 = L.mdp_setup(A, part, o1)
     o2 = L.mdp_options_default(**kw)
-    o2.flags |= L.MDP_NO_GRAPHS
     h2 = L.mdp_setup_like(h1, o2)
     return h1, h2
 
@@ -39,14 +37,12 @@ CASES = [
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("prec", [L.MDP_FP64, L.MDP_MIXED])
-@pytest.mark.parametrize("mode", ["forced", "default"])
-def test_graph_replay_equals_direct_launches(name, make, kw, prec, mode):
+def test_graph_replay_equals_direct_launches(name, make, kw, prec):
     sc = make()
     srcs = [None] + [synth.host_sources(sc, 40 + k) for k in range(3)]
     A, B, part = tpfa.assemble(sc, sources=srcs)
-    assert A.shape[0] <= 131072  # the default policy replays graphs at this size
-    h1, h2 = _pair(A, part, graph_flag=L.MDP_GRAPHS if mode == "forced" else 0, precision=prec, **kw)
-    say(f"[graphs] case={name} prec={prec} mode={mode}")
+    h1, h2 = _pair(A, part, precision=prec, **kw)
+    say(f"[graphs] case={name} prec={prec}")
     side = torch.cuda.Stream()
     try:
         for rep in range(2):
