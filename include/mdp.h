@@ -190,7 +190,14 @@ int mdp_destroy(mdp_handle *h);
  * receives the per-column result.  Returns MDP_OK when every column
  * converged, MDP_NOT_CONVERGED when any did not (x holds the last iterate),
  * or a negative error (ENAN for NaN/Inf in b or a breakdown producing one).
- * Synchronises hip_stream before returning. */
+ * With nrhs >= 4, columns are solved four at a time as one batch of this
+ * system whose sparse products read each matrix once for all four (each
+ * column keeps its own Krylov process; results equal one-column solves up to
+ * rounding).  That batch (a four-column Krylov workspace and a four-fold copy
+ * of the system matrix) is built on first use and kept with the handle until
+ * mdp_destroy; if its memory cannot be had, the columns are solved one by
+ * one.  Remaining columns are solved one by one.  Synchronises hip_stream
+ * before returning. */
 int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
               int64_t ld, void *hip_stream, mdp_stats *stats);
 

@@ -261,10 +261,38 @@ int mdp_solve(mdp_handle *h, const double *b, double *x, int32_t nrhs, int64_t l
     set_last_error("handle was set up host-only");
     return MDP_EINVAL;
   }
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
   int worst = MDP_OK;
-  for (int32_t k = 0; k < nrhs; ++k) {
+  int32_t k = 0;
+  // Four columns at a time run as one batch of the same system, whose
+  // sparse products read each matrix once for all four (the plan is built on
+  // first use and kept with the handle); if its memory cannot be had, the
+  // columns are solved one by one.
+  if (nrhs >= kMultiRhs && !h->rhs4) {
+    try {
+      auto bt = std::make_unique<Batch>();
+      bt->build(std::vector<const Solver *>(kMultiRhs, &h->s), s, true);
+      h->rhs4 = std::move(bt);
+    } catch (const Error &e) {
+      if (e.code != MDP_ENOMEM) throw;
+      (void)hipGetLastError();  // clear the failed allocation's error state
+    }
+  }
+  if (h->rhs4) {
+    for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
+      std::vector<PairIO> io;
+      for (int r = 0; r < kMultiRhs; ++r) io.push_back(PairIO{b + (k + r) * ld, x + (k + r) * ld});
+      mdp_stats st[kMultiRhs] = {};
+      const int rc = h->rhs4->solve(io, s, st);
+      if (stats)
+        for (int r = 0; r < kMultiRhs; ++r) stats[k + r] = st[r];
+      if (rc < 0) return rc;
+      if (rc > worst) worst = rc;
+    }
+  }
+  for (; k < nrhs; ++k) {
     mdp_stats st{};
-    const int rc = h->s.solve(b + k * ld, x + k * ld, static_cast<hipStream_t>(hip_stream), &st);
+    const int rc = h->s.solve(b + k * ld, x + k * ld, s, &st);
     if (stats) stats[k] = st;
     if (rc < 0) return rc;
     if (rc > worst) worst = rc;

@@ -198,4 +198,8 @@ struct Batch {
 
 struct mdp_handle {
   mdp::Solver s;
+  // mdp_solve with four or more columns: the same system as a batch of
+  // kMultiRhs pairs sharing the preconditioner's matrix reads (built on first
+  // use, kept until mdp_destroy)
+  std::unique_ptr<mdp::Batch> rhs4;
 };

@@ -85,6 +85,53 @@ def test_multiple_rhs_and_sources():
         s.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_column_groups_of_four_share_matrices(prec):
+    """mdp_solve with 4 and 6 columns: each group of four runs as one batch of
+    the system whose sparse products read each matrix once for all four, the
+    rest one by one.  Every column matches its one-column solve (iterations
+    within one, solution within 1e-6) and the oracle's residual check, with
+    zero and given initial guesses; a leading dimension above n leaves the
+    padding alone and gives the same bits as the contiguous call."""
+    sc = synth.regular_3d(n=12, k_par=1e4, kappa=1e-4, seed=8)
+    fs = [None] + [synth.host_sources(sc, 60 + k) for k in range(5)]
+    A, B, part = tpfa.assemble(sc, sources=fs)
+    n = A.shape[0]
+    for flags in (0, L.MDP_USE_X0):
+        s = Solver(A, part, precision=prec, flags=flags, max_coarse=50)
+        say(f"[solve] column groups prec={prec} flags={flags}")
+        try:
+            for nrhs in (4, 6):
+                bt = dev(B[:, :nrhs].T.copy())
+                if flags:
+                    x0 = dev(np.stack([0.1 * synth.random_vector(n, 90 + k) for k in range(nrhs)]))
+                else:
+                    x0 = torch.zeros_like(bt)
+                x = x0.clone()
+                rc, st = L.mdp_solve(s.handle, bt, x)
+                assert rc == L.MDP_OK
+                for k in range(nrhs):
+                    x1 = x0[k].clone()
+                    _, st1 = s.solve(bt[k].clone(), x1)
+                    d = relerr(host(x[k]), host(x1))
+                    assert abs(st[k]["iters"] - st1[0]["iters"]) <= 1 and d <= 1e-6, (nrhs, k, st[k], st1[0], d)
+                    Ao, bo, _ = oa.assemble(sc if fs[k] is None else sc.with_source(fs[k]))
+                    assert np.linalg.norm(bo - Ao @ host(x[k])) <= 1e-8 * np.linalg.norm(bo)
+                if nrhs == 4:
+                    ld = n + 16
+                    bpad = torch.zeros((4, ld), dtype=torch.float64, device="cuda:0")
+                    bpad[:, :n] = bt
+                    xpad = torch.full((4, ld), 7.0, dtype=torch.float64, device="cuda:0")
+                    xpad[:, :n] = x0
+                    stats = (L.mdp_stats * 4)()
+                    rc = L.lib.mdp_solve(s.handle, L._dptr(bpad), L._dptr(xpad), 4, ld, None, stats)
+                    torch.cuda.synchronize()
+                    assert rc == L.MDP_OK
+                    assert torch.equal(xpad[:, :n], x) and bool((xpad[:, n:] == 7.0).all())
+        finally:
+            s.close()
+
+
 def test_interleaved_unknown_order():
     sc = synth.regular_3d(n=12, seed=7)
     A, b, part = tpfa.assemble(sc)
