@@ -11,7 +11,8 @@ hierarchies are resident in HBM before the clock starts.
 The JSON line reports the plain-FP64 method as ``value`` and, beside it, the
 mixed mode (FP32 preconditioner, FP64 outer loop and coarse solve) on the
 same systems, per-solve latency percentiles, the same four systems solved
-together as one batch (``batched``, both precisions), the roofline position
+together as one batch (``batched``, both precisions), each system with four
+right-hand sides in one call (``multi_rhs``), the roofline position
 of the dominant kernel (timed with HIP events inside the library on the
 launch stream) and the CPU oracle timed on a bounded sample on this host.
 
@@ -74,6 +75,8 @@ def parse():
                    help="replay each Arnoldi step from a captured HIP graph instead of launching its kernels")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the fixed rule for sparse formats instead of timing candidates at setup")
+    p.add_argument("--multi-rhs", type=int, default=2,
+                   help="rounds over the systems with four right-hand sides each (0 = skip)")
     p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
     p.add_argument("--rhs", type=int, default=4, help="batch mode: right-hand sides per system")
     p.add_argument("--pool", type=int, default=64, help="serve mode: resident systems (half 2D, half 3D)")
@@ -137,7 +140,7 @@ def main():
             t_setup += t2 - t1
             bt = torch.tensor(b, dtype=torch.float64, device=dev)
             xt = torch.zeros_like(bt)
-            systems.append({"name": sc.name, "h": hs, "b": bt, "x": xt, "n": A.shape[0], "nnz": A.nnz})
+            systems.append({"name": sc.name, "sc": sc, "h": hs, "b": bt, "x": xt, "n": A.shape[0], "nnz": A.nnz})
             log(f"[bench] set up {sc.name}: n={A.shape[0]} nnz={A.nnz}")
     torch.cuda.synchronize()
 
@@ -199,6 +202,51 @@ def main():
             log(f"[bench] batched {prec}: {nb} batches of {len(systems)} in {dt:.3f}s")
         batched["what"] = "the same systems solved together as one block-diagonal batch"
 
+    # Beside them: four right-hand sides per system (the Dirichlet data alone
+    # and with three host source fields) in one mdp_solve call, which takes
+    # the columns four at a time with each matrix read once for all four,
+    # against the same columns solved one at a time.
+    multi_rhs = {}
+    if args.block == "lower" and args.multi_rhs:
+        for s in systems:
+            fs = [None] + [synth.host_sources(s["sc"], 100 + k) for k in range(3)]
+            _, B, _ = tpfa.assemble(s["sc"], sources=fs)
+            s["B4"] = torch.tensor(np.ascontiguousarray(B.T), dtype=torch.float64, device=dev)
+        nr = args.multi_rhs
+        for prec in ("fp64", "mixed"):
+            xs = [torch.zeros_like(s["B4"]) for s in systems]
+            for s, x in zip(systems, xs):
+                L.mdp_solve(s["h"][prec], s["B4"], x, stream)  # builds the four-column plan (untimed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = []
+            for _ in range(nr):
+                for s, x in zip(systems, xs):
+                    rc, st = L.mdp_solve(s["h"][prec], s["B4"], x, stream)
+                    if rc != L.MDP_OK:
+                        raise RuntimeError(f"{s['name']} {prec} four-column solve did not converge")
+                    its += [c["iters"] for c in st]
+            torch.cuda.synchronize()
+            dt4 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            its1 = []
+            for _ in range(nr):
+                for s, x in zip(systems, xs):
+                    for k in range(s["B4"].shape[0]):
+                        rc, st = L.mdp_solve(s["h"][prec], s["B4"][k], x[k], stream)
+                        its1.append(st[0]["iters"])
+            torch.cuda.synchronize()
+            dt1 = time.perf_counter() - t0
+            ns = nr * sum(s["B4"].shape[0] for s in systems)
+            multi_rhs[prec] = {"value": round(ns / dt4, 3), "unit": "solves/s",
+                               "one_column_at_a_time": round(ns / dt1, 3),
+                               "speedup": round(dt1 / dt4, 3), "solves": ns,
+                               "iters": sorted(set(its)), "iters_one_at_a_time": sorted(set(its1))}
+            log(f"[bench] four right-hand sides {prec}: {ns} solves in {dt4:.3f}s "
+                f"(one column at a time {dt1:.3f}s)")
+        multi_rhs["what"] = ("each system with four right-hand sides (Dirichlet data alone and with three "
+                             "uniform host source fields) in one mdp_solve call")
+
     # Roofline: the same FP64 steps again, with HIP events recorded by the
     # library around every launch of each kernel class on its launch stream
     # (kept out of the timed passes above: the events lengthen the gaps
@@ -251,6 +299,7 @@ def main():
                   "p99_ms": pct(mx["lat"], 99), "iters": sorted(set(mx["iters"])),
                   "max_rel_res": max(mx["res"]), "speedup_vs_fp64": round(mixed_value / value, 3)},
         "batched": batched or None,
+        "multi_rhs": multi_rhs or None,
         "roofline": roofline,
         "kernel_classes": classes,
         "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_setup, 2)},
