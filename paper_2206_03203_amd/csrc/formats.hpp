@@ -192,9 +192,14 @@ inline DiaLayout dia_layout(const HCsr &h, const std::vector<int32_t> &offs) {
 // Diagonals plus a CSR remainder: the entries on the offsets `offs` in
 // diagonal storage (dval, as above), every other entry in the CSR ptr / col /
 // val, in row order.
+// split: first row of the trailing run of rows that all have remainder
+// entries (nr when the last row has none, or when every row has some).  In a
+// two-block system these are the fracture rows, whose remainder entries gather
+// from far-away columns; the product dispatches them first.
 struct HybLayout {
   std::vector<int32_t> offs, ptr, col;
   std::vector<double> dval, val;
+  int32_t split = 0;
 };
 
 inline HybLayout hyb_layout(const HCsr &h, const std::vector<int32_t> &offs) {
@@ -215,6 +220,9 @@ inline HybLayout hyb_layout(const HCsr &h, const std::vector<int32_t> &offs) {
     }
     L.ptr[i + 1] = static_cast<int32_t>(L.col.size());
   }
+  L.split = h.nr;
+  while (L.split > 0 && L.ptr[L.split] > L.ptr[L.split - 1]) --L.split;
+  if (L.split == 0) L.split = h.nr;
   return L;
 }
 

@@ -319,28 +319,57 @@ __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
                             blk(y2, r * bk.ys));
 }
 
+// Row order of the diagonals-plus-remainder product.  Rows [split, nr) (the
+// rows whose remainder gathers from far away) take the first blocks, padded to
+// a multiple of kXcds blocks, so that they start first and spread over every
+// XCD; rows [0, split) follow, each XCD taking a contiguous share of them.
+// Rows past the end of their range get nr (the thread exits).
+inline int hyb_blocks(int nr, int split) {
+  const int tail = (nr - split + kThreads - 1) / kThreads;
+  return (tail + kXcds - 1) / kXcds * kXcds + (split + kThreads - 1) / kThreads;
+}
+
+__device__ __forceinline__ int hyb_row(int nr, int split) {
+  const int bid = static_cast<int>(blockIdx.x), t = static_cast<int>(threadIdx.x);
+  const int tail = (nr - split + kThreads - 1) / kThreads;
+  const int padded = (tail + kXcds - 1) / kXcds * kXcds;
+  if (bid < padded) return bid < tail ? split + bid * kThreads + t : nr;
+  const int row = xcd_block(bid - padded, static_cast<int>(gridDim.x) - padded) * kThreads + t;
+  return row < split ? row : nr;
+}
+
 // Diagonals plus a CSR remainder, one thread per row: for stencil matrices
 // with a few irregular couplings (the system matrix: the host's stencil on
 // the diagonals; host-fracture and fracture-fracture couplings in the
 // remainder).  Entry (i, i + doff[d]) of the diagonals is at dval[d * nr + i]
 // (zero where absent, or past the columns); the remainder's row i holds the
-// other entries of row i.  Diagonal terms are summed first, in offset order.
+// other entries of row i.  Diagonal terms are summed first, in offset order,
+// then the remainder's in row order.
 template <int KB, int MODE, typename TA, typename TX, typename TY>
 __global__ __launch_bounds__(kThreads) void hyb_kernel(
-    int nr, int nc, int ndiag, const int *__restrict__ doff, const TA *__restrict__ dval,
+    int nr, int nc, int split, int ndiag, const int *__restrict__ doff, const TA *__restrict__ dval,
     const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
     const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
     TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
     const GmresState *__restrict__ pst, Blocks bk) {
   if (gate && *gate) return;
   using Acc = typename AccumT<TA, TX>::type;
-  const int blk_id = xcd_block(blockIdx.x, gridDim.x);
-  const int row = blk_id * kThreads + static_cast<int>(threadIdx.x);
+  const int row = hyb_row(nr, split);
   if (row >= nr) return;
   bool live[KB], any = false;
 #pragma unroll
   for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
   if (!any) return;
+  // the remainder's bounds and first entries are loaded before the diagonals
+  // so that their latency overlaps the diagonal loads
+  const int s = ptr[row], e = ptr[row + 1];
+  int c0[kScalarBatch];
+  Acc v0[kScalarBatch];
+#pragma unroll
+  for (int k = 0; k < kScalarBatch; ++k) {
+    c0[k] = s + k < e ? col[s + k] : 0;
+    v0[k] = s + k < e ? static_cast<Acc>(val[s + k]) : Acc(0);
+  }
   Acc sum[KB];
 #pragma unroll
   for (int r = 0; r < KB; ++r) sum[r] = 0;
@@ -365,8 +394,14 @@ __global__ __launch_bounds__(kThreads) void hyb_kernel(
           sum[r] += v[k] * xv;
         }
   }
-  const int s = ptr[row], e = ptr[row + 1];
-  for (int p0 = s; p0 < e; p0 += kScalarBatch) {
+#pragma unroll
+  for (int r = 0; r < KB; ++r)
+    if (live[r])
+#pragma unroll
+      for (int k = 0; k < kScalarBatch; ++k)
+        if (s + k < e)
+          sum[r] += v0[k] * spmv_gather<MODE, Acc>(c0[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
+  for (int p0 = s + kScalarBatch; p0 < e; p0 += kScalarBatch) {
     int c[kScalarBatch];
     Acc v[kScalarBatch];
 #pragma unroll

@@ -107,6 +107,7 @@ void upload_hyb_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &of
   HybLayout L = hyb_layout(h, offs);
   d.ndiag = static_cast<int32_t>(offs.size());
   d.rem_nnz = static_cast<int64_t>(L.col.size());
+  d.split = L.split;
   upload_vec(d.doff, keep.put(std::move(L.offs)), s);
   upload_vec(d.dval, keep.put(as_type<T>(L.dval)), s);
   upload_vec(d.ptr, keep.put(std::move(L.ptr)), s);
@@ -421,11 +422,11 @@ void spmv_kb(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y,
     return;
   }
   if (A.hyb) {
-    const int blocks = (A.nr + kThreads - 1) / kThreads;
+    const int blocks = hyb_blocks(A.nr, A.split);
     timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
       hipLaunchKernelGGL((hyb_kernel<KB, MODE, TA, TX, TY>), dim3(blocks), dim3(kThreads), 0, s, A.nr, A.nc,
-                         A.ndiag, dptr<const int>(A.doff), dptr<const TA>(A.dval), A.p(), A.c(), A.v(), x, b, dinv,
-                         y, y2, gate.all, rp, gate.st, bk);
+                         A.split, A.ndiag, dptr<const int>(A.doff), dptr<const TA>(A.dval), A.p(), A.c(), A.v(), x,
+                         b, dinv, y, y2, gate.all, rp, gate.st, bk);
     });
     return;
   }

@@ -35,6 +35,7 @@ struct DCsr {
   bool hyb = false;
   int32_t ndiag = 0;
   int64_t rem_nnz = 0;
+  int32_t split = 0;  // diagonals + remainder: rows [split, nr) are dispatched first
   DevMem doff, dval;
   bool sell = false;
   bool scalar = false;

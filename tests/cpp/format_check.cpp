@@ -122,6 +122,13 @@ static void check_hyb(const char *what, const HCsr &h, const std::vector<int32_t
       if (c >= 0 && c < h.nc) y[i] += L.val[p] * x[c];
     }
   same(what, "diagonals + remainder", y, r);
+  // the rows dispatched first are exactly the trailing run of rows that all
+  // have remainder entries (none when every row has some)
+  CHECK(L.split >= 1 && L.split <= h.nr, "%s: hyb split %d", what, L.split);
+  int32_t run = h.nr;
+  while (run > 0 && L.ptr[run] > L.ptr[run - 1]) --run;
+  CHECK(L.split == (run == 0 ? h.nr : run), "%s: hyb split %d, trailing run from %d", what, L.split, run);
+  std::printf("%-12s hyb split=%d of %d\n", what, L.split, h.nr);
 }
 
 static void check_matrix(const char *what, const HCsr &h) {

@@ -63,3 +63,7 @@ def test_format_layouts_and_tiles(tmp_path):
     assert any(ln.startswith("A ") and ln.endswith("hyb=5") for ln in lines)
     assert any(ln.startswith("S[0].A") and "dia=7" in ln for ln in lines)
     assert any("sell=1" in ln for ln in lines)
+    # the fracture rows of the system matrix form its trailing run of rows
+    # with remainder entries, dispatched first
+    assert any(ln.startswith("A ") and "hyb split=" in ln and
+               int(ln.split("split=")[1].split()[0]) < int(ln.split(" of ")[1]) for ln in lines)
