@@ -22,8 +22,9 @@ Two more workloads, each printing its own JSON line:
 random fracture segments with log-uniform permeabilities in [1e-4, 1e4]),
 four right-hand sides each (Dirichlet data plus a uniform host source field),
 mixed precision, solved by mdp_solve_batch; one step = the whole batch.
-Beside it: the same pairs solved one system at a time with mdp_solve, mixed
-and plain FP64.
+Beside it: the same pairs solved one system at a time with mdp_solve (one
+call per system with its four right-hand sides, which it takes together with
+shared matrix reads), mixed and plain FP64.
 
 ``--mode serve``: a pool of 64 resident systems (32 2D as above, 32 3D with
 side 40..160 and 3..9 random planes), mixed precision, served by

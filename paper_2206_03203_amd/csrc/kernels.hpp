@@ -319,6 +319,20 @@ __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
                             blk(y2, r * bk.ys));
 }
 
+// Reads n 16-byte words and stores only if their sum equals the sentinel
+// (never, for a buffer of zeros and a nonzero sentinel): it evicts the caches
+// without leaving dirty lines behind.
+__global__ __launch_bounds__(kThreads) void cache_flush_kernel(const double2 *__restrict__ p, int64_t n,
+                                                               double sentinel, double *__restrict__ sink) {
+  double acc = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const double2 v = p[i];
+    acc += v.x + v.y;
+  }
+  if (acc == sentinel) sink[0] = acc;
+}
+
 // Row order of the diagonals-plus-remainder product.  Rows [split, nr) (the
 // rows whose remainder gathers from far away) take the first blocks, padded to
 // a multiple of kXcds blocks, so that they start first and spread over every

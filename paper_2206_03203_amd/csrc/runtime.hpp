@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "mdp.h"
 
@@ -95,6 +96,30 @@ template <typename T>
 inline T *dptr(const DevMem &m) {
   return static_cast<T *>(m.get());
 }
+
+// Owning array of timing events.
+class Events {
+ public:
+  explicit Events(size_t n) : ev_(n, nullptr) {
+    try {
+      for (auto &e : ev_) MDP_HIP(hipEventCreate(&e));
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+  ~Events() { release(); }
+  Events(const Events &) = delete;
+  Events &operator=(const Events &) = delete;
+  hipEvent_t operator[](size_t i) const { return ev_[i]; }
+
+ private:
+  void release() {
+    for (auto &e : ev_)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+  }
+  std::vector<hipEvent_t> ev_;
+};
 
 // Round a vector length up so that consecutive columns start 256-byte aligned.
 inline int64_t padded_ld(int64_t n) { return (n + 63) / 64 * 64; }

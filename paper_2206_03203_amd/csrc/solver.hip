@@ -117,12 +117,23 @@ void upload_hyb_arrays(const HCsr &h, DCsr<T> &d, const std::vector<int32_t> &of
 
 // Autotuning is on while an AutotuneScope with on = true is alive on this
 // thread (the setup paths open one from their options).
+// The scope also owns the buffer that the timing reads to flush the caches,
+// allocated on first use and freed with the scope.
 thread_local bool t_autotune = false;
+thread_local DevMem *t_flush = nullptr;
 
 struct AutotuneScope {
   bool saved;
-  explicit AutotuneScope(bool on) : saved(t_autotune) { t_autotune = on; }
-  ~AutotuneScope() { t_autotune = saved; }
+  DevMem *saved_flush;
+  DevMem flush;
+  explicit AutotuneScope(bool on) : saved(t_autotune), saved_flush(t_flush) {
+    t_autotune = on;
+    t_flush = &flush;
+  }
+  ~AutotuneScope() {
+    t_autotune = saved;
+    t_flush = saved_flush;
+  }
 };
 
 // Choices already made in this process, by matrix signature, so that equal
@@ -488,12 +499,26 @@ T *mnull() {
   return static_cast<T *>(nullptr);
 }
 
-// Time every candidate format of one matrix (kTuneReps residual products
-// each, after two untimed ones) and return the fastest.  Candidates: CSR with
-// 2..64 lanes per row and 4 or 8 entries in flight per lane, CSR with one
-// thread per row, sliced ELL when its padding stays within 2x, and the
-// diagonal layouts when the matrix has them.
+// Time every candidate format of one matrix (residual products, after two
+// untimed ones) and return the fastest.  Candidates: CSR with 2..64 lanes per
+// row and 4 entries in flight per lane (also 8 when a lane averages more than
+// 4), CSR with one thread per row, sliced ELL when its padding stays within
+// 2x, and the diagonal layouts when the matrix has them.  Each of kTuneColdReps
+// timed products starts with cold caches, as inside a solve, where a V-cycle
+// streams far more than the caches hold between two products with one matrix:
+// a read of kFlushBytes (more than the 256 MB Infinity Cache and the L2s
+// together) precedes it.  Without the flush buffer (out of memory) kTuneReps
+// products run back to back.
 constexpr int kTuneReps = 10;
+constexpr int kTuneColdReps = 4;
+constexpr size_t kFlushBytes = size_t(384) << 20;
+
+void flush_caches(const DevMem &buf, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(buf.bytes() / 16);
+  hipLaunchKernelGGL(cache_flush_kernel, dim3(2048), dim3(kThreads), 0, s, dptr<const double2>(buf), n, 1.0,
+                     dptr<double>(buf));
+  MDP_HIP(hipGetLastError());
+}
 
 template <typename T>
 FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
@@ -539,18 +564,36 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   MDP_HIP(hipMemsetAsync(bv.get(), 0, bv.bytes(), s));
   const T *x = dptr<const T>(xv), *b = dptr<const T>(bv);
   T *y = dptr<T>(yv);
-  hipEvent_t e0, e1;
-  MDP_HIP(hipEventCreate(&e0));
-  MDP_HIP(hipEventCreate(&e1));
+  DevMem *flush = t_flush;
+  if (flush && !flush->get()) {
+    try {
+      flush->alloc(kFlushBytes);
+      MDP_HIP(hipMemsetAsync(flush->get(), 0, kFlushBytes, s));
+    } catch (const Error &e) {
+      if (e.code != MDP_ENOMEM) throw;
+      (void)hipGetLastError();
+    }
+  }
+  const bool cold = flush && flush->get();
+  const int reps = cold ? kTuneColdReps : kTuneReps;
+  Events ev(2 * reps);
+  // cold: one event pair around each product; warm: one pair around them all
   auto time_one = [&](const DCsr<T> &d) {
     for (int i = 0; i < 2; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), Gate{}, s);
-    MDP_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < kTuneReps; ++i) spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), Gate{}, s);
-    MDP_HIP(hipEventRecord(e1, s));
-    MDP_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    return ms;
+    for (int i = 0; i < reps; ++i) {
+      if (cold) flush_caches(*flush, s);
+      if (cold || i == 0) MDP_HIP(hipEventRecord(ev[2 * i], s));
+      spmv<kResid>(d, x, b, cnull<T>(), y, mnull<T>(), Gate{}, s);
+      if (cold || i == reps - 1) MDP_HIP(hipEventRecord(ev[2 * i + 1], s));
+    }
+    MDP_HIP(hipEventSynchronize(ev[2 * reps - 1]));
+    float total = 0.f;
+    for (int i = 0; i < (cold ? reps : 1); ++i) {
+      float ms = 0.f;
+      MDP_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[cold ? 2 * i + 1 : 2 * reps - 1]));
+      total += ms;
+    }
+    return total / reps;
   };
   FormatChoice best = heuristic_format(h, st, !offs.empty(), !hoffs.empty());
   float tbest = std::numeric_limits<float>::max();
@@ -560,7 +603,8 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   std::vector<FormatChoice> cand;
   for (int l : {2, 4, 8, 16, 32, 64})
     for (int bt : {kCsrBatch, 8})
-      if (l <= std::max(2.0, 2.0 * avg) && 4.0 * l * bt >= avg) cand.push_back(FormatChoice{false, false, l, bt});
+      if (l <= std::max(2.0, 2.0 * avg) && 4.0 * l * bt >= avg && (bt == kCsrBatch || l * kCsrBatch < avg))
+        cand.push_back(FormatChoice{false, false, l, bt});
   cand.push_back(FormatChoice{false, true, 4, kCsrBatch});
   for (const FormatChoice &c : cand) {
     csr.scalar = c.scalar;
@@ -581,15 +625,12 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
     const float t = time_one(hyb);
     if (t < tbest) tbest = t, best = FormatChoice{false, false, 8, kCsrBatch, false, true};
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   MDP_HIP(hipStreamSynchronize(s));
   if (std::getenv("MDP_SETUP_VERBOSE"))
     std::fprintf(stderr, "[mdp] autotune %s n=%d nnz=%lld: %s lpr=%d batch=%d (%.2f us)\n",
                  sizeof(T) == 8 ? "f64" : "f32", h.nr, static_cast<long long>(h.nnz()),
                  best.dia ? "dia" : best.hyb ? "dia+csr" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
-                 best.lpr, best.batch,
-                 1e3 * tbest / kTuneReps);
+                 best.lpr, best.batch, 1e3 * tbest);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.emplace(key, best);
   return best;
