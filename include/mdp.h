@@ -169,7 +169,10 @@ int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stre
  * 3.3, with the AMG options they were built with) to the file `path`, so
  * that mdp_load can re-create the handle without repeating the setup.
  * Binary, little-endian, with a tag, a format version and a 64-bit FNV-1a
- * checksum.  EINVAL if the file cannot be written. */
+ * checksum.  Version 2 also stores each level's fused restriction
+ * R (I - A D^-1); version 1 files (without it) are still read, and their
+ * V-cycles compute the residual and restrict it in two products.  EINVAL if
+ * the file cannot be written. */
 int mdp_save(const mdp_handle *h, const char *path);
 
 /* Re-create a handle from a file written by mdp_save and upload it as
@@ -294,7 +297,9 @@ int mdp_server_destroy(mdp_server *srv);
 #define MDP_KC_ARNOLDI_AXPY 4  /* update pass of each Arnoldi step                       */
 #define MDP_KC_OTHER 5         /* casts, reductions, Givens, update of x, residual       */
 #define MDP_KC_FINE_RESID 6    /* finest S~ level: residual after the first sweep, whose
-                                  iterate D^-1 b the producer of b has written already   */
+                                  iterate D^-1 b the producer of b has written already;
+                                  where the level restricts with R (I - A D^-1), that
+                                  one product instead                                    */
 
 /* Start timing every launch of one kernel class (process-wide; not for use
  * while server slots are solving): HIP events

@@ -16,7 +16,7 @@ enum KClass : int {
   kKcArnoldiDot = 3,   // fused reduction pass of the Arnoldi step
   kKcArnoldiAxpy = 4,  // update pass of the Arnoldi step
   kKcOther = 5,        // casts, small reductions, Givens, solution update, residual
-  kKcFineResid = 6,    // finest S~ level: residual after the first sweep
+  kKcFineResid = 6,    // finest S~ level: residual after the first sweep (fused: its restriction)
   kKcCount = 7
 };
 

@@ -5,10 +5,12 @@
 //
 // Layout (little-endian): the 8-byte tag "MDPHIER1", a format version, the
 // AMG options the hierarchy was built with, the sizes and permutation, six
-// CSR matrices, the two hierarchies, and a 64-bit FNV-1a checksum of every
-// byte before it.  Reading checks the tag, version, checksum, every length
-// against the bytes left, and the structure of every matrix, and reports
-// any failure as MDP_EINVAL without touching the output.
+// CSR matrices, the two hierarchies (version 2: each level with its fused
+// restriction, 0 x 0 when unused; version 1, still read: without it), and a
+// 64-bit FNV-1a checksum of every byte before it.  Reading checks the tag,
+// version, checksum, every length against the bytes left, and the structure
+// of every matrix, and reports any failure as MDP_EINVAL without touching the
+// output.
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -21,7 +23,7 @@ namespace mdp {
 namespace {
 
 constexpr char kTag[8] = {'M', 'D', 'P', 'H', 'I', 'E', 'R', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;  // 2 adds each level's fused restriction; 1 is still read
 
 uint64_t fnv1a(const unsigned char *p, size_t n) {
   uint64_t h = 1469598103934665603ull;
@@ -62,6 +64,7 @@ struct Writer {
       csr(l.A);
       csr(l.P);
       csr(l.R);
+      csr(l.Rf);
       vec(l.dl1);
       vec(l.agg);
     }
@@ -73,6 +76,7 @@ struct Bad {};  // any malformed input
 struct Reader {
   const unsigned char *p;
   size_t left;
+  uint32_t version = kVersion;
   void raw(void *dst, size_t n) {
     if (n > left) throw Bad{};
     std::memcpy(dst, p, n);
@@ -120,6 +124,7 @@ struct Reader {
       l.A = csr();
       l.P = csr();
       l.R = csr();
+      l.Rf = version >= 2 ? csr() : HCsr::empty(0, 0);
       l.dl1 = vec<double>();
       l.agg = vec<int32_t>();
     }
@@ -130,10 +135,11 @@ struct Reader {
       if (k + 1 < nl) {
         const int32_t nc = h.lv[k + 1].A.nr;
         if (l.P.nr != l.A.nr || l.P.nc != nc || l.R.nr != nc || l.R.nc != l.A.nr) throw Bad{};
+        if (l.Rf.nr != 0 && (l.Rf.nr != nc || l.Rf.nc != l.A.nr)) throw Bad{};
         if (l.agg.size() != static_cast<size_t>(l.A.nr)) throw Bad{};
         for (int32_t a : l.agg)
           if (a < -1 || a >= nc) throw Bad{};
-      } else if (!l.agg.empty()) {
+      } else if (!l.agg.empty() || l.Rf.nr != 0) {
         throw Bad{};
       }
     }
@@ -189,7 +195,8 @@ void load_host_system(const char *path, HostSystem &out, mdp_options &amg) {
     throw SetupError{MDP_EINVAL, bad + " (checksum mismatch)"};
   Reader r{buf.data() + sizeof(kTag), buf.size() - sizeof(kTag) - sizeof(uint64_t)};
   try {
-    if (r.pod<uint32_t>() != kVersion) throw Bad{};
+    r.version = r.pod<uint32_t>();
+    if (r.version != 1 && r.version != kVersion) throw Bad{};
     amg.strength_theta = r.pod<double>();
     amg.max_coarse = r.pod<int32_t>();
     amg.max_dense = r.pod<int32_t>();

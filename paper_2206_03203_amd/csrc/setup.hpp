@@ -21,6 +21,7 @@ struct AmgParams {
 struct HLevel {
   HCsr A;                    // level operator
   HCsr P, R;                 // prolongator to this level from the next, R = P^T (not on the coarsest)
+  HCsr Rf;                   // R (I - A D^-1) when applying it beats the residual and R (else 0 x 0)
   std::vector<double> dl1;   // l1 row norms sum_j |a_ij| (smoother diagonal)
   std::vector<int32_t> agg;  // aggregate per node (-1 = none); empty on the coarsest
 };

@@ -292,6 +292,10 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     std::vector<Piece> pa, pp, pr, psw;
     std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
+    // the level restricts b with R (I - A D^-1) when every continuing system has it
+    dl.fused = dl.ncont > 0;
+    for (int p : pl.order[l])
+      if (l + 1 < hs[p]->lv.size() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
     for (int p : pl.order[l]) {
       const HHier &h = *hs[p];
       const HLevel &hl = h.lv[l];
@@ -301,7 +305,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
         const int32_t oc = static_cast<int32_t>(pl.off[l + 1][p]);
         pa.emplace_back(&hl.A, o, o);
         pp.emplace_back(&hl.P, o, oc);
-        pr.emplace_back(&hl.R, oc, o);
+        pr.emplace_back(dl.fused ? &hl.Rf : &hl.R, oc, o);
       } else if (h.dense) {
         for (int r = 0; r < kb; ++r)
           desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
@@ -325,7 +329,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     dl.x.alloc(nb);
     dl.b.alloc(nb);
     dl.t.alloc(nb);
-    dl.r.alloc(nb);
+    if (!dl.fused) dl.r.alloc(nb);
     if (dl.n > dl.sw_off) dl.pp.alloc(2 * sweep_stride(dl, kb) * sizeof(T));
     // block strides: x of A, P, R and Asw lives on levels l, l + 1, l and l;
     // their b / dinv / y on levels l, l, l + 1 and l
@@ -598,12 +602,14 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   FormatChoice best = heuristic_format(h, st, !offs.empty(), !hoffs.empty());
   float tbest = std::numeric_limits<float>::max();
   // CSR-vector shapes whose lanes are neither mostly idle (more lanes than
-  // twice the average row) nor too few (a row needing more than four steps)
+  // twice the average row) nor too few (a row needing more than four steps;
+  // the widest shape is always tried, whatever the row length)
   const double avg = static_cast<double>(h.nnz()) / h.nr;
   std::vector<FormatChoice> cand;
   for (int l : {2, 4, 8, 16, 32, 64})
     for (int bt : {kCsrBatch, 8})
-      if (l <= std::max(2.0, 2.0 * avg) && 4.0 * l * bt >= avg && (bt == kCsrBatch || l * kCsrBatch < avg))
+      if (l <= std::max(2.0, 2.0 * avg) && (4.0 * l * bt >= avg || l == 64) &&
+          (bt == kCsrBatch || l * kCsrBatch < avg))
         cand.push_back(FormatChoice{false, false, l, bt});
   cand.push_back(FormatChoice{false, true, 4, kCsrBatch});
   for (const FormatChoice &c : cand) {
@@ -691,10 +697,11 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
     const int kr = fine ? kKcFineResid : kKcVcycleOther;
     const int ko = kKcVcycleOther;
     // pre-smoothing from zero is t = D^-1 b; its residual r = b - A t
-    spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), mnull<T>(), gate, s, kr);
-    // b_c = R r and the coarse level's first iterate t_c = D_c^-1 b_c
-    spmv<kPlainScale>(L.R, dptr<const T>(L.r), cnull<T>(), dptr<const T>(C.dinv), dptr<T>(C.b), dptr<T>(C.t),
-                      gate, s, ko);
+    if (!L.fused) spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), mnull<T>(), gate, s, kr);
+    // b_c = R r (fused: R (I - A D^-1) b, the same vector) and the coarse
+    // level's first iterate t_c = D_c^-1 b_c
+    spmv<kPlainScale>(L.R, L.fused ? b : dptr<const T>(L.r), cnull<T>(), dptr<const T>(C.dinv), dptr<T>(C.b),
+                      dptr<T>(C.t), gate, s, L.fused && fine ? kr : ko);
     vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
     spmv<kAccum>(L.P, dptr<const T>(C.x), cnull<T>(), cnull<T>(), t, mnull<T>(), gate, s, ko);  // t += P x_c
     spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, mnull<T>(), gate, s, ks);       // post-smooth

@@ -62,6 +62,7 @@ struct DLevel {
   int32_t n = 0;
   int32_t ncont = 0;
   DCsr<T> A, P, R;  // A: operator of the continuing systems; P, R to/from the next level
+  bool fused = false;  // R holds R (I - A D^-1) and restricts b directly (no residual product)
   DevMem dinv;      // n entries: 1 / sum_j |a_ij|
   int32_t ndense = 0, max_dense_n = 0;
   DevMem dense;     // DenseDesc[ndense]

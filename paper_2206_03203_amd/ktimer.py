@@ -11,9 +11,10 @@ from . import _lib as L
 CLASSES = {0: "outer_spmv", 1: "fine_smooth", 2: "vcycle_other", 3: "arnoldi_dot",
            4: "arnoldi_axpy", 5: "other", 6: "fine_resid"}
 # classes whose launches are all of one kernel symbol (per precision)
-SINGLE_KERNEL = {"outer_spmv": "sell_kernel<0, double, T, double>",
+SINGLE_KERNEL = {"outer_spmv": "system-matrix product (format chosen at setup)",
                  "fine_smooth": "post-smoothing sweep on the finest S~ level",
-                 "fine_resid": "residual after the first sweep on the finest S~ level",
+                 "fine_resid": "residual after the first sweep on the finest S~ level, or, where the level "
+                               "restricts with R (I - A D^-1), that one restriction product",
                  "arnoldi_dot": "dcgs_reduce_kernel", "arnoldi_axpy": "dcgs_update_kernel"}
 
 

@@ -188,6 +188,37 @@ static void check_tiles(const char *what, const std::vector<std::vector<std::pai
               static_cast<long long>(target));
 }
 
+// A level's fused restriction restricts b to what R restricts the residual
+// of the first smoothing iterate to: Rf b = R (b - A D^-1 b), D the l1 norms.
+static int fused_levels = 0;
+static void check_fused(const char *what, const HLevel &L) {
+  if (L.Rf.nr == 0) return;
+  ++fused_levels;
+  const int32_t n = L.A.nr;
+  CHECK(L.Rf.nr == L.R.nr && L.Rf.nc == n, "%s: fused restriction shape", what);
+  std::vector<double> b(n), t(n), r(n), y1(L.R.nr, 0.0), y2(L.R.nr, 0.0);
+  for (int32_t i = 0; i < n; ++i) {
+    b[i] = std::cos(0.91 * i + 0.3) + 0.05 * (i % 11);
+    t[i] = b[i] / L.dl1[i];
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    double a = 0.0;
+    for (int32_t p = L.A.ptr[i]; p < L.A.ptr[i + 1]; ++p) a += L.A.val[p] * t[L.A.col[p]];
+    r[i] = b[i] - a;
+  }
+  double scale = 0.0;
+  for (int32_t i = 0; i < L.R.nr; ++i) {
+    for (int32_t p = L.Rf.ptr[i]; p < L.Rf.ptr[i + 1]; ++p) y1[i] += L.Rf.val[p] * b[L.Rf.col[p]];
+    for (int32_t p = L.R.ptr[i]; p < L.R.ptr[i + 1]; ++p) y2[i] += L.R.val[p] * r[L.R.col[p]];
+    scale = std::max(scale, std::fabs(y2[i]));
+  }
+  double err = 0.0;
+  for (int32_t i = 0; i < L.R.nr; ++i) err = std::max(err, std::fabs(y1[i] - y2[i]));
+  CHECK(err <= 1e-12 * std::max(scale, 1.0), "%s: fused restriction differs by %.3g (scale %.3g)", what, err, scale);
+  std::printf("%-12s fused restriction nnz=%lld (R %lld, A %lld)\n", what, static_cast<long long>(L.Rf.nnz()),
+              static_cast<long long>(L.R.nnz()), static_cast<long long>(L.A.nnz()));
+}
+
 int main(int argc, char **argv) {
   std::vector<std::vector<std::pair<int64_t, int64_t>>> batch;
   int64_t at = 0;
@@ -207,6 +238,7 @@ int main(int argc, char **argv) {
       check_matrix(name, s.Ho.lv[l].P);
       std::snprintf(name, sizeof name, "S[%zu].R", l);
       check_matrix(name, s.Ho.lv[l].R);
+      check_fused(name, s.Ho.lv[l]);
     }
     for (size_t l = 0; l < s.Hg.lv.size(); ++l) {
       std::snprintf(name, sizeof name, "G[%zu].A", l);
@@ -215,6 +247,7 @@ int main(int argc, char **argv) {
       check_matrix(name, s.Hg.lv[l].P);
       std::snprintf(name, sizeof name, "G[%zu].R", l);
       check_matrix(name, s.Hg.lv[l].R);
+      check_fused(name, s.Hg.lv[l]);
     }
     check_tiles("one system", {{{0, s.n_o}, {s.n_o, s.n_g}}});
     batch.push_back({{at, s.n_o}, {at + s.n_o, s.n_g}});
@@ -231,6 +264,7 @@ int main(int argc, char **argv) {
   std::vector<std::vector<std::pair<int64_t, int64_t>>> tiny;
   for (int p = 0; p < 1000; ++p) tiny.push_back({{p * 7, 5}, {p * 7 + 5, p % 3}});
   check_tiles("1000 small pairs", tiny);
+  std::printf("fused restrictions: %d\n", fused_levels);
   std::printf("failures: %d\n", fails);
   return fails ? 1 : 0;
 }

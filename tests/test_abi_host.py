@@ -11,6 +11,7 @@ import pytest
 import scipy.sparse as sp
 
 import synth
+from hierfile_util import to_version_1
 from oracle import amg, blocks as ob
 from oracle import assembly as oa
 from paper_2206_03203_amd import _lib as L
@@ -267,6 +268,33 @@ def test_hierarchy_file_round_trip(tmp_path):
         with pytest.raises(L.MdpError) as e:
             L.mdp_load(path, L.mdp_options_default(flags=L.MDP_HOST_ONLY, max_coarse=31))
         assert e.value.code == L.MDP_EINVAL
+    finally:
+        L.mdp_destroy(h)
+
+
+def test_hierarchy_file_version_1_still_read(tmp_path):
+    """A file of the first format version (no fused restrictions) loads and
+    gives the same hierarchy; its V-cycles restrict the residual instead."""
+    sc = synth.regular_3d(n=10, k_par=1e4, kappa=1e-4, seed=3)
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part, max_coarse=30)
+    path = tmp_path / "h.mdph"
+    try:
+        L.mdp_save(h, str(path))
+        old = tmp_path / "h1.mdph"
+        old.write_bytes(to_version_1(path.read_bytes()))
+        h1 = L.mdp_load(str(old), L.mdp_options_default(flags=L.MDP_HOST_ONLY, max_coarse=30))
+        try:
+            i0, l0 = _all_levels(h)
+            i1, l1 = _all_levels(h1)
+            assert i0 == i1
+            for a, c in zip(l0, l1):
+                if isinstance(a, tuple):
+                    assert all(np.array_equal(x, y) for x, y in zip(a[:3], c[:3])) and a[3] == c[3]
+                elif a is not None:
+                    assert np.array_equal(a, c)
+        finally:
+            L.mdp_destroy(h1)
     finally:
         L.mdp_destroy(h)
 

@@ -63,6 +63,9 @@ def test_format_layouts_and_tiles(tmp_path):
     assert any(ln.startswith("A ") and ln.endswith("hyb=5") for ln in lines)
     assert any(ln.startswith("S[0].A") and "dia=7" in ln for ln in lines)
     assert any("sell=1" in ln for ln in lines)
+    # some levels restrict with R (I - A D^-1), each checked against R applied
+    # to the residual of the first smoothing iterate
+    assert any(ln.startswith("fused restrictions: ") and int(ln.split(": ")[1]) > 0 for ln in lines)
     # the fracture rows of the system matrix form its trailing run of rows
     # with remainder entries, dispatched first
     assert any(ln.startswith("A ") and "hyb split=" in ln and
