@@ -61,6 +61,7 @@ def parse():
     p.add_argument("--n", type=int, default=100, help="host cells per side")
     p.add_argument("--seeds", type=int, default=1, help="log-normal seeds per (K_par, kappa) pair")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
+    p.add_argument("--restart", type=int, default=64, help="FGMRES restart length (at most 64)")
     p.add_argument("--max-coarse", type=int, default=400,
                    help="AMG: stop coarsening at this many unknowns (the coarsest is dense up to 2000)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,9 +132,9 @@ def main():
             fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
             o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse)
+                                        max_coarse=args.max_coarse, restart=args.restart)
             o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse)
+                                        max_coarse=args.max_coarse, restart=args.restart)
             hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
@@ -255,7 +256,7 @@ def main():
     roofline, classes = roofline_pass(lambda: run("fp64", args.steps), args.kernel_class,
                                       f"the {args.steps} FP64 steps repeated", fp["seconds"])
     if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
-            args.max_coarse == 400 and args.n == 100:
+            args.max_coarse == 400 and args.n == 100 and args.restart == 64:
         roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{args.n}")
 
     cpu = None
@@ -287,7 +288,7 @@ def main():
         "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
-                   "amg_max_coarse": args.max_coarse,
+                   "amg_max_coarse": args.max_coarse, "restart": args.restart,
                    "autotune": not args.no_autotune, "graphs": args.graphs,
                    "block_preconditioner": args.block},
         "p50_ms": pct(fp["lat"], 50),
@@ -379,7 +380,7 @@ def _pct(a, q):
     return round(1e3 * float(np.percentile(a, q)), 3) if len(a) else None
 
 
-def _setup_pool(scs, sources_per_sys, precisions, stream, tag, flags=0):
+def _setup_pool(scs, sources_per_sys, precisions, stream, tag, flags=0, restart=64):
     """Assemble and set up every scenario; returns a list of dicts holding the
     handles (one per precision, sharing the host setup), the right-hand sides
     as a (nrhs, n) device tensor and the sizes."""
@@ -397,7 +398,8 @@ def _setup_pool(scs, sources_per_sys, precisions, stream, tag, flags=0):
         hs = {}
         first = None
         for prec in precisions:
-            o = L.mdp_options_default(precision={"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[prec], flags=flags)
+            o = L.mdp_options_default(precision={"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[prec], flags=flags,
+                                      restart=restart)
             hs[prec] = L.mdp_setup(A, part, o, stream) if first is None else L.mdp_setup_like(first, o, stream)
             first = first or hs[prec]
         t2 = time.perf_counter()
@@ -429,7 +431,7 @@ def mode_batch(args):
     scs = [synth.random_2d(s) for s in range(args.systems)]
     srcs = [[synth.host_sources(sc, 4 * s + k) for k in range(args.rhs)] for s, sc in enumerate(scs)]
     pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch",
-                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0, args.restart)
     pairs = sum(p["b"].shape[0] for p in pool)
     unknowns = sum(p["n"] * p["b"].shape[0] for p in pool)
     xs = [torch.zeros_like(p["b"]) for p in pool]
@@ -488,7 +490,7 @@ def mode_batch(args):
         "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
         "config": {"workload": f"2d-uneven-batch-{args.systems}x{args.rhs}", "systems": len(pool),
                    "pairs": pairs, "unknowns_total": unknowns,
-                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8},
+                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8, "restart": args.restart},
         "iters_mean": round(float(np.mean(its_b)), 2), "iters_max": int(max(its_b)),
         "max_rel_res": max(s["rel_res_true"] for s in st_b),
         "sequential_mixed": {"value": round(pairs / t_seq, 2), "unit": "solves/s",
@@ -517,7 +519,7 @@ def mode_serve(args):
     nb = 4  # right-hand sides per system to draw requests from
     srcs = [[synth.host_sources(sc, 4 * (3000 + s) + k) for k in range(nb)] for s, sc in enumerate(scs)]
     pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed",), stream, "serve",
-                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0)
+                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0, args.restart)
     budget = int(args.budget_gb * (1 << 30))
     srv = L.mdp_server_create(budget, args.slots)
     for p in pool:

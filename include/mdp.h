@@ -196,11 +196,15 @@ int mdp_destroy(mdp_handle *h);
  * With nrhs >= 4, columns are solved four at a time as one batch of this
  * system whose sparse products read each matrix once for all four (each
  * column keeps its own Krylov process; results equal one-column solves up to
- * rounding).  That batch (a four-column Krylov workspace and a four-fold copy
- * of the system matrix) is built on first use and kept with the handle until
- * mdp_destroy; if its memory cannot be had, the columns are solved one by
- * one.  Remaining columns are solved one by one.  Synchronises hip_stream
- * before returning. */
+ * rounding).  That batch (a four-column Krylov workspace, a four-fold copy
+ * of the system matrix and one copy of the preconditioner) is built on first
+ * use and kept with the handle until mdp_destroy.  All handles' batches
+ * together hold at most MDP_MULTI_RHS_BYTES bytes of device memory (an
+ * environment variable, read at each build; default a quarter of the
+ * device's memory): a handle whose batch does not fit solves its columns one
+ * by one, and tries again once others have been destroyed; one whose build
+ * ran out of device memory stays with one column at a time.  Remaining
+ * columns are solved one by one.  Synchronises hip_stream before returning. */
 int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
               int64_t ld, void *hip_stream, mdp_stats *stats);
 

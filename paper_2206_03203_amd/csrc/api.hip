@@ -88,6 +88,55 @@ int check_options(const mdp_options &o) {
   return MDP_OK;
 }
 
+namespace {
+
+// Four-column plans of all handles together hold at most multi_rhs_cap()
+// device bytes: MDP_MULTI_RHS_BYTES when set, else a quarter of the device's
+// memory.  A handle whose plan does not fit solves its columns one at a time.
+std::mutex g_mrhs_mu;
+int64_t g_mrhs_held = 0;  // under g_mrhs_mu
+
+int64_t multi_rhs_cap() {
+  if (const char *e = std::getenv("MDP_MULTI_RHS_BYTES")) return std::max<int64_t>(0, std::atoll(e));
+  static const int64_t quarter = [] {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return int64_t{0};
+    }
+    return static_cast<int64_t>(tot / 4);
+  }();
+  return quarter;
+}
+
+// Build h's four-column plan if the budget has room (see mdp_solve).
+void build_multi_rhs(mdp_handle *h, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mrhs_mu);
+  const int64_t cap = multi_rhs_cap();
+  if (g_mrhs_held >= cap || g_mrhs_held + h->rhs4_need > cap) return;
+  const int64_t before = t_dev_net_bytes;
+  try {
+    auto bt = std::make_unique<Batch>();
+    bt->build(std::vector<const Solver *>(kMultiRhs, &h->s), s, true);
+    h->rhs4 = std::move(bt);
+  } catch (const Error &e) {
+    if (e.code != MDP_ENOMEM) throw;
+    (void)hipGetLastError();  // clear the failed allocation's error state
+    h->rhs4_failed = true;
+    return;
+  }
+  const int64_t bytes = std::max<int64_t>(0, t_dev_net_bytes - before);
+  if (g_mrhs_held + bytes > cap) {
+    h->rhs4.reset();
+    h->rhs4_need = bytes;
+    return;
+  }
+  g_mrhs_held += bytes;
+  h->rhs4_bytes = bytes;
+}
+
+}  // namespace
+
 }  // namespace mdp
 
 using namespace mdp;
@@ -245,6 +294,10 @@ int mdp_destroy(mdp_handle *h) {
     if (g_batch && std::find(g_batch->handles.begin(), g_batch->handles.end(), h) != g_batch->handles.end())
       g_batch.reset();
   }
+  if (h && h->rhs4_bytes > 0) {
+    std::lock_guard<std::mutex> lk(g_mrhs_mu);
+    g_mrhs_held -= h->rhs4_bytes;
+  }
   delete h;
   return MDP_OK;
   API_END
@@ -266,18 +319,9 @@ int mdp_solve(mdp_handle *h, const double *b, double *x, int32_t nrhs, int64_t l
   int32_t k = 0;
   // Four columns at a time run as one batch of the same system, whose
   // sparse products read each matrix once for all four (the plan is built on
-  // first use and kept with the handle); if its memory cannot be had, the
-  // columns are solved one by one.
-  if (nrhs >= kMultiRhs && !h->rhs4) {
-    try {
-      auto bt = std::make_unique<Batch>();
-      bt->build(std::vector<const Solver *>(kMultiRhs, &h->s), s, true);
-      h->rhs4 = std::move(bt);
-    } catch (const Error &e) {
-      if (e.code != MDP_ENOMEM) throw;
-      (void)hipGetLastError();  // clear the failed allocation's error state
-    }
-  }
+  // first use and kept with the handle); without room in the plans' budget,
+  // or without device memory for it, the columns are solved one by one.
+  if (nrhs >= kMultiRhs && !h->rhs4 && !h->rhs4_failed) build_multi_rhs(h, s);
   if (h->rhs4) {
     for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
       std::vector<PairIO> io;

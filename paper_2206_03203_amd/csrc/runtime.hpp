@@ -43,6 +43,10 @@ void set_alloc_hook(const AllocHook &h);
 void *dev_alloc(size_t bytes, const AllocHook &h);
 void dev_free(void *p, const AllocHook &h);
 
+// Net device bytes this thread has allocated minus freed through DevMem: the
+// difference across a build is what the built object keeps.
+inline thread_local int64_t t_dev_net_bytes = 0;
+
 // Owning, untyped device allocation.
 class DevMem {
  public:
@@ -73,9 +77,13 @@ class DevMem {
     p_ = dev_alloc(bytes, hook_);
     if (!p_) raise(MDP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     n_ = bytes;
+    t_dev_net_bytes += static_cast<int64_t>(bytes);
   }
   void reset() {
-    if (p_) dev_free(p_, hook_);
+    if (p_) {
+      dev_free(p_, hook_);
+      t_dev_net_bytes -= static_cast<int64_t>(n_);
+    }
     p_ = nullptr;
     n_ = 0;
   }

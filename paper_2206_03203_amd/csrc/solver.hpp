@@ -202,6 +202,10 @@ struct mdp_handle {
   mdp::Solver s;
   // mdp_solve with four or more columns: the same system as a batch of
   // kMultiRhs pairs sharing the preconditioner's matrix reads (built on first
-  // use, kept until mdp_destroy)
+  // use when the process-wide budget for such plans has room, kept until
+  // mdp_destroy)
   std::unique_ptr<mdp::Batch> rhs4;
+  int64_t rhs4_bytes = 0;  // device bytes the plan holds (counted in the budget)
+  int64_t rhs4_need = 0;   // a plan that did not fit: its size (retried when the budget has room)
+  bool rhs4_failed = false;  // the device ran out of memory building it: one column at a time
 };

@@ -132,6 +132,38 @@ def test_column_groups_of_four_share_matrices(prec):
             s.close()
 
 
+def test_column_groups_wait_for_room_in_the_plan_budget(monkeypatch):
+    """With no room in the budget for four-column plans (MDP_MULTI_RHS_BYTES
+    = 0), mdp_solve solves every column alone, bit for bit as one-column
+    solves; once the budget has room, the same handle builds its plan and
+    the columns still match one-column solves within the solver tolerance."""
+    sc = synth.regular_3d(n=10, k_par=1e-4, kappa=1e4, seed=4)
+    fs = [None] + [synth.host_sources(sc, 70 + k) for k in range(3)]
+    A, B, part = tpfa.assemble(sc, sources=fs)
+    s = Solver(A, part, precision="fp64", max_coarse=50)
+    say("[solve] four-column plan budget")
+    try:
+        bt = dev(B.T.copy())
+        ones = []
+        for k in range(4):
+            x1, _ = s.solve(bt[k].clone())
+            ones.append(x1)
+        monkeypatch.setenv("MDP_MULTI_RHS_BYTES", "0")
+        x = torch.zeros_like(bt)
+        rc, st = L.mdp_solve(s.handle, bt, x)
+        assert rc == L.MDP_OK
+        for k in range(4):
+            assert torch.equal(x[k], ones[k]), k
+        monkeypatch.delenv("MDP_MULTI_RHS_BYTES")
+        x = torch.zeros_like(bt)
+        rc, st = L.mdp_solve(s.handle, bt, x)
+        assert rc == L.MDP_OK
+        for k in range(4):
+            assert relerr(host(x[k]), host(ones[k])) <= 1e-6, k
+    finally:
+        s.close()
+
+
 def test_interleaved_unknown_order():
     sc = synth.regular_3d(n=12, seed=7)
     A, b, part = tpfa.assemble(sc)
