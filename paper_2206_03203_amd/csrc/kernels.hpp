@@ -164,6 +164,65 @@ __global__ __launch_bounds__(kThreads) void spmv_kernel(
                               blk(y2, r * bk.ys));
 }
 
+// CSR with one workgroup per row, for rows of hundreds to thousands of
+// entries (the fused restrictions of the coarse levels): every thread keeps
+// BATCH entries in flight, the wavefronts reduce their sums, and the first
+// thread adds the kThreads / 64 wavefront sums in order.
+template <int BATCH, int KB, int MODE, typename TA, typename TX, typename TY>
+__global__ __launch_bounds__(kThreads) void spmv_row_block_kernel(
+    int nr, const int *__restrict__ ptr, const int *__restrict__ col, const TA *__restrict__ val,
+    const TX *__restrict__ x, const TY *__restrict__ b, const TY *__restrict__ dinv,
+    TY *__restrict__ y, TY *__restrict__ y2, const int *__restrict__ gate, const int *__restrict__ rpair,
+    const GmresState *__restrict__ pst, Blocks bk) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TX>::type;
+  __shared__ Acc part[kThreads / 64][KB];
+  const int row = xcd_block(blockIdx.x, gridDim.x);
+  if (row >= nr) return;  // the whole workgroup leaves together
+  bool live[KB], any = false;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) any |= (live[r] = block_live<KB>(row, r, rpair, pst, bk));
+  if (!any) return;
+  const int t = static_cast<int>(threadIdx.x);
+  const int s = ptr[row], e = ptr[row + 1];
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
+  for (int p0 = s + t; p0 < e; p0 += BATCH * kThreads) {
+    int c[BATCH];
+    Acc v[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int p = p0 + k * kThreads;
+      // past the row end: value 0 and a column of this row (always in range)
+      c[k] = p < e ? col[p] : col[s];
+      v[k] = p < e ? static_cast<Acc>(val[p]) : Acc(0);
+    }
+#pragma unroll
+    for (int r = 0; r < KB; ++r)
+      if (live[r])
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k)
+          sum[r] += v[k] * spmv_gather<MODE, Acc>(c[k], x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys));
+  }
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = group_sum<64>(sum[r]);
+  if (t % 64 == 0)
+#pragma unroll
+    for (int r = 0; r < KB; ++r) part[t / 64][r] = sum[r];
+  __syncthreads();
+  if (t != 0) return;
+#pragma unroll
+  for (int r = 0; r < KB; ++r) {
+    if (!live[r]) continue;
+    Acc tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) tot += part[w][r];
+    spmv_store<MODE, Acc>(row, tot, x + r * bk.xs, blk(b, r * bk.ys), blk(dinv, r * bk.ys), y + r * bk.ys,
+                          blk(y2, r * bk.ys));
+  }
+}
+
 // Sliced ELL (slices of 64 rows = one wavefront, one thread per row): entry k
 // of the row at lane L of slice s is stored at soff[s] + 64 k + L, so every
 // load of indices and values is one contiguous 64-wide access.  Padding

@@ -423,6 +423,16 @@ void spmv_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY
   });
 }
 
+template <int BATCH, int KB, int MODE, typename TA, typename TX, typename TY>
+void spmv_row_block_launch(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
+                           hipStream_t s, int kind) {
+  const Blocks bk{A.bxs, A.bys, A.nsys};
+  timed_launch(kind, s, spmv_bytes<MODE, TA, TX, TY>(A), [&] {
+    hipLaunchKernelGGL((spmv_row_block_kernel<BATCH, KB, MODE, TA, TX, TY>), dim3(A.nr), dim3(kThreads), 0, s, A.nr,
+                       A.p(), A.c(), A.v(), x, b, dinv, y, y2, gate.all, gate.st ? A.rp() : nullptr, gate.st, bk);
+  });
+}
+
 template <int KB, int MODE, typename TA, typename TX, typename TY>
 void spmv_kb(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y, TY *y2, Gate gate,
              hipStream_t s, int kind) {
@@ -477,6 +487,12 @@ void spmv_kb(const DCsr<TA> &A, const TX *x, const TY *b, const TY *dinv, TY *y,
     MDP_LPR_CASE(32)
     MDP_LPR_CASE(64)
 #undef MDP_LPR_CASE
+    case kThreads:  // one workgroup per row
+      if (b8)
+        spmv_row_block_launch<8, KB, MODE>(A, x, b, dinv, y, y2, gate, s, kind);
+      else
+        spmv_row_block_launch<kCsrBatch, KB, MODE>(A, x, b, dinv, y, y2, gate, s, kind);
+      break;
     default: raise(MDP_EINVAL, "unsupported lanes per row");
   }
 }
@@ -505,8 +521,8 @@ T *mnull() {
 
 // Time every candidate format of one matrix (residual products, after two
 // untimed ones) and return the fastest.  Candidates: CSR with 2..64 lanes per
-// row and 4 entries in flight per lane (also 8 when a lane averages more than
-// 4), CSR with one thread per row, sliced ELL when its padding stays within
+// row or a whole workgroup per row, and 4 entries in flight per lane (also 8
+// when a lane averages more than 4), CSR with one thread per row, sliced ELL when its padding stays within
 // 2x, and the diagonal layouts when the matrix has them.  Each of kTuneColdReps
 // timed products starts with cold caches, as inside a solve, where a V-cycle
 // streams far more than the caches hold between two products with one matrix:
@@ -603,10 +619,11 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   float tbest = std::numeric_limits<float>::max();
   // CSR-vector shapes whose lanes are neither mostly idle (more lanes than
   // twice the average row) nor too few (a row needing more than four steps;
-  // the widest shape is always tried, whatever the row length)
+  // the 64-lane shape is always tried, whatever the row length); a workgroup
+  // per row when rows average at least 128 entries
   const double avg = static_cast<double>(h.nnz()) / h.nr;
   std::vector<FormatChoice> cand;
-  for (int l : {2, 4, 8, 16, 32, 64})
+  for (int l : {2, 4, 8, 16, 32, 64, kThreads})
     for (int bt : {kCsrBatch, 8})
       if (l <= std::max(2.0, 2.0 * avg) && (4.0 * l * bt >= avg || l == 64) &&
           (bt == kCsrBatch || l * kCsrBatch < avg))
