@@ -24,7 +24,9 @@ class Solver:
         self.precision = precision
 
     def solve(self, b, x=None, stream=None):
-        """b: CUDA float64 tensor (n,) or (nrhs, n).  Returns (x, stats list)."""
+        """b: CUDA float64 tensor (n,) or (nrhs, n).  Returns (x, stats list).
+        With four or more right-hand sides, mdp_solve takes them four at a time
+        with shared matrix reads while its memory budget allows."""
         import torch
         if x is None:
             x = torch.zeros_like(b)
