@@ -26,13 +26,21 @@ following reading is used (every rule below is deterministic):
   (2000), else by four l1-Jacobi sweeps from zero;
 * smoother: l1-Jacobi (Baker, Falgout, Kolev, Yang 2011) with one-row
   blocks, d_i = sum_j |a_ij|, undamped; one sweep before (from a zero
-  guess, so x = b / d) and one after the coarse correction.
+  guess, so x = b / d) and one after the coarse correction.  Section 4 uses
+  one smoothing step on each side; the counts are options (pre_sweeps,
+  post_sweeps), each further sweep being x <- x + (b - A x) / d.
 
 Pins: tentative columns orthonormal; coarse operators symmetric; constant
 vector preserved on a pure-Neumann graph; one-level hierarchy is an exact
-solve; a two-level cycle equals the textbook two-grid error propagator; the
-V-cycle operator is symmetric positive definite; hand-computed aggregates
-on small graphs (tests/test_oracle_amg.py, tests/golden/).
+solve; a two-level cycle equals the textbook two-grid error propagator; a
+V-cycle of any depth, with any sweep counts and a dense or swept coarsest
+level, equals the operator of the textbook multigrid recursion
+B_l = (I - E_l) A_l^-1, E_l = S_l^post (I - P B_{l+1} R A_l) S_l^pre with
+S_l = I - D_l^-1 A_l; k l1-Jacobi sweeps from zero equal
+(I - S^k) A^-1 b; nu cycles as a stationary iteration equal
+(I - E_0^nu) A^-1 b; the V-cycle operator is symmetric positive definite;
+hand-computed aggregates on small graphs (tests/test_oracle_amg.py,
+tests/golden/).
 """
 
 from __future__ import annotations
@@ -51,6 +59,8 @@ class AMGOptions:
     max_dense: int = 2000
     max_levels: int = 10
     coarse_sweeps: int = 4
+    pre_sweeps: int = 1
+    post_sweeps: int = 1
 
 
 @dataclass
@@ -196,10 +206,13 @@ def vcycle(H: Hierarchy, b: np.ndarray, lvl: int = 0) -> np.ndarray:
         return _coarse_solve(H, b)
     lv = H.levels[lvl]
     x = b / lv.d_l1                      # pre-smoothing from zero
+    for _ in range(H.opts.pre_sweeps - 1):
+        x = x + (b - lv.A @ x) / lv.d_l1
     r = b - lv.A @ x
     xc = vcycle(H, lv.R @ r, lvl + 1)   # coarse-grid correction
     x = x + lv.P @ xc
-    x = x + (b - lv.A @ x) / lv.d_l1     # post-smoothing
+    for _ in range(H.opts.post_sweeps):  # post-smoothing
+        x = x + (b - lv.A @ x) / lv.d_l1
     return x
 
 

@@ -192,3 +192,77 @@ def test_smoothed_prolongator_closed_form_chain():
 def test_l1_diagonal_definition():
     A = sp.csr_matrix(np.array([[4.0, -1.5, 0.0], [-1.5, 3.0, 2.0], [0.0, 2.0, -5.0]]))
     assert np.array_equal(amg.l1_diagonal(A), [5.5, 6.5, 7.0])
+
+
+def _recursion_operator(H, lvl, pre, post, sweeps):
+    """B_l of the textbook multigrid recursion (operator algebra, not the
+    oracle's update sequence): B_L = A_L^-1 (dense coarsest) or
+    (I - S_L^sweeps) A_L^-1 (swept coarsest); for l < L,
+    I - B_l A_l = S_l^post (I - P_l B_{l+1} R_l A_l) S_l^pre, S_l = I - D_l^-1 A_l."""
+    lv = H.levels[lvl]
+    A = lv.A.toarray()
+    n = A.shape[0]
+    I = np.eye(n)
+    Ainv = np.linalg.inv(A)
+    S = I - A / lv.d_l1[:, None]
+    if lvl == len(H.levels) - 1:
+        if H.coarse_dense is not None:
+            return Ainv
+        return (I - np.linalg.matrix_power(S, sweeps)) @ Ainv
+    Bc = _recursion_operator(H, lvl + 1, pre, post, sweeps)
+    P, R = lv.P.toarray(), lv.R.toarray()
+    E = np.linalg.matrix_power(S, post) @ (I - P @ Bc @ R @ A) @ np.linalg.matrix_power(S, pre)
+    return (I - E) @ Ainv
+
+
+@pytest.mark.parametrize("pre,post", [(1, 1), (2, 1), (1, 3), (2, 2)])
+@pytest.mark.parametrize("dense", [True, False])
+def test_vcycle_equals_multigrid_recursion(pre, post, dense):
+    """A V-cycle over three or more levels, with the given sweep counts and a
+    dense or swept (four l1-Jacobi sweeps) coarsest level, applies exactly the
+    operator of the textbook recursion."""
+    S, _ = _system_blocks(synth.tiny_3d(6, seed=2))
+    n = S.shape[0]
+    opts = amg.AMGOptions(max_coarse=10, max_dense=2000 if dense else 2, pre_sweeps=pre, post_sweeps=post)
+    H = amg.setup(S, opts)
+    assert len(H.levels) >= 3 and (H.coarse_dense is not None) == dense
+    B = _recursion_operator(H, 0, pre, post, opts.coarse_sweeps)
+    V = _operator(H, n)
+    assert np.allclose(V, B, rtol=0, atol=1e-10 * np.abs(B).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 7])
+def test_l1_jacobi_sweeps_closed_form(k):
+    """k undamped l1-Jacobi sweeps from zero are the truncated Neumann series
+    of A^-1 in the smoothing matrix: x_k = (I - (I - D^-1 A)^k) A^-1 b.  The
+    coarsest level without a dense inverse runs coarse_sweeps of them."""
+    S, _ = _system_blocks(synth.tiny_2d(12))
+    H = amg.setup(S, amg.AMGOptions(max_dense=10, max_levels=1, coarse_sweeps=k))
+    assert H.coarse_dense is None and len(H.levels) == 1
+    A = S.toarray()
+    d = H.levels[0].d_l1
+    b = synth.random_vector(S.shape[0], 4)
+    G = np.eye(A.shape[0]) - A / d[:, None]
+    expect = (np.eye(A.shape[0]) - np.linalg.matrix_power(G, k)) @ np.linalg.solve(A, b)
+    x = amg.vcycle(H, b)
+    assert np.allclose(x, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("cycles", [2, 3])
+@pytest.mark.parametrize("dense", [True, False])
+def test_cycles_closed_form(cycles, dense):
+    """nu V-cycles as a stationary iteration from zero: the error after nu
+    steps is E^nu times the initial error, so x_nu = (I - E^nu) A^-1 b with
+    E = I - B A and B the recursion operator (independent of the oracle's
+    update sequence)."""
+    S, _ = _system_blocks(synth.tiny_3d(6, seed=2))
+    n = S.shape[0]
+    opts = amg.AMGOptions(max_coarse=10, max_dense=2000 if dense else 2)
+    H = amg.setup(S, opts)
+    A = S.toarray()
+    B = _recursion_operator(H, 0, 1, 1, opts.coarse_sweeps)
+    E = np.eye(n) - B @ A
+    b = synth.random_vector(n, 9)
+    expect = (np.eye(n) - np.linalg.matrix_power(E, cycles)) @ np.linalg.solve(A, b)
+    x = amg.apply_cycles(H, b, cycles)
+    assert np.allclose(x, expect, rtol=0, atol=1e-10 * np.abs(expect).max())
