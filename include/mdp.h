@@ -113,8 +113,8 @@ typedef struct {
 typedef struct {
   int32_t precision;      /* MDP_FP64 (default) or MDP_MIXED                          */
   int32_t vcycles;        /* V-cycles per Q application (default 1, Section 3.3)      */
-  int32_t pre_sweeps;     /* l1-Jacobi sweeps before the coarse correction (1)        */
-  int32_t post_sweeps;    /* l1-Jacobi sweeps after it (1)                             */
+  int32_t pre_sweeps;     /* l1-Jacobi sweeps before the coarse correction (1; 1..8)  */
+  int32_t post_sweeps;    /* l1-Jacobi sweeps after it (1; 1..8)                       */
   double strength_theta;  /* SA strength threshold (0.08)                              */
   int32_t max_coarse;     /* stop coarsening at or below this size (400)               */
   int32_t max_dense;      /* coarsest solved densely up to this size (2000)            */
@@ -295,7 +295,8 @@ int mdp_server_destroy(mdp_server *srv);
 
 /* Kernel classes for mdp_ktimer_*. */
 #define MDP_KC_OUTER_SPMV 0    /* w = A z_j with the FP64 system matrix                  */
-#define MDP_KC_FINE_SMOOTH 1   /* finest S~ level: the post-smoothing l1-Jacobi sweep     */
+#define MDP_KC_FINE_SMOOTH 1   /* finest S~ level: the l1-Jacobi sweeps after the first
+                                  (post-smoothing, and pre-smoothing beyond one sweep)    */
 #define MDP_KC_VCYCLE_OTHER 2  /* the rest of both V-cycles and the A_GO update          */
 #define MDP_KC_ARNOLDI_DOT 3   /* fused reduction pass of each Arnoldi step              */
 #define MDP_KC_ARNOLDI_AXPY 4  /* update pass of each Arnoldi step                       */

@@ -76,7 +76,8 @@ int check_options(const mdp_options &o) {
   };
   if (o.precision != MDP_FP64 && o.precision != MDP_MIXED) return bad("precision must be MDP_FP64 or MDP_MIXED");
   if (o.vcycles < 1) return bad("vcycles must be >= 1");
-  if (o.pre_sweeps != 1 || o.post_sweeps != 1) return bad("only one pre- and one post-smoothing sweep are supported");
+  if (o.pre_sweeps < 1 || o.pre_sweeps > kMaxSweeps || o.post_sweeps < 1 || o.post_sweeps > kMaxSweeps)
+    return bad("pre_sweeps and post_sweeps must be in [1, 8]");
   if (!(o.strength_theta >= 0.0)) return bad("strength_theta must be >= 0");
   if (o.max_coarse < 1 || o.max_dense < 0 || o.max_levels < 1) return bad("bad coarsening limits");
   if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
@@ -365,6 +366,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
       return MDP_EINVAL;
     }
     if (si.opt.precision != s0.opt.precision || si.opt.vcycles != s0.opt.vcycles ||
+        si.opt.pre_sweeps != s0.opt.pre_sweeps || si.opt.post_sweeps != s0.opt.post_sweeps ||
         si.opt.restart != s0.opt.restart || si.opt.max_iter != s0.opt.max_iter || si.opt.rtol != s0.opt.rtol ||
         si.opt.block_form != s0.opt.block_form ||
         (si.opt.flags & MDP_USE_X0) != (s0.opt.flags & MDP_USE_X0)) {  // graphs are not used in batches

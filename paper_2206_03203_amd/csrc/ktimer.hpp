@@ -11,7 +11,7 @@ namespace mdp {
 
 enum KClass : int {
   kKcOuterSpmv = 0,    // w = A z_j, FP64 system matrix
-  kKcFineSmooth = 1,   // finest S~ level: post-smoothing sweep
+  kKcFineSmooth = 1,   // finest S~ level: sweeps after the first (post-smoothing, extra pre-smoothing)
   kKcVcycleOther = 2,  // other V-cycle kernels (restriction, prolongation, coarser levels, A_GG, A_GO)
   kKcArnoldiDot = 3,   // fused reduction pass of the Arnoldi step
   kKcArnoldiAxpy = 4,  // update pass of the Arnoldi step

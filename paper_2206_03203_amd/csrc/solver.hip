@@ -277,11 +277,13 @@ int64_t sweep_stride(const DLevel<T> &L, int kb) {
 // pairs' rows (pair of a row in block r = r * nsys + its system).
 template <typename T>
 void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep,
-                 const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
+                 int pre, int post, const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
   const size_t L = pl.order.size();
   d.lv.clear();
   d.lv.resize(L);
   d.kb = kb;
+  d.pre = pre;
+  d.post = post;
   std::vector<double> cinv;
   for (size_t l = 0; l < L; ++l) {
     DLevel<T> &dl = d.lv[l];
@@ -292,8 +294,9 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     std::vector<Piece> pa, pp, pr, psw;
     std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
-    // the level restricts b with R (I - A D^-1) when every continuing system has it
-    dl.fused = dl.ncont > 0;
+    // the level restricts b with R (I - A D^-1) when every continuing system
+    // has it and the pre-smoothing is the single sweep from zero D^-1 b
+    dl.fused = dl.ncont > 0 && pre == 1;
     for (int p : pl.order[l])
       if (l + 1 < hs[p]->lv.size() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
     for (int p : pl.order[l]) {
@@ -329,7 +332,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     dl.x.alloc(nb);
     dl.b.alloc(nb);
     dl.t.alloc(nb);
-    if (!dl.fused) dl.r.alloc(nb);
+    if (!dl.fused || post > 1) dl.r.alloc(nb);  // residual; sweep ping-pong
     if (dl.n > dl.sw_off) dl.pp.alloc(2 * sweep_stride(dl, kb) * sizeof(T));
     // block strides: x of A, P, R and Asw lives on levels l, l + 1, l and l;
     // their b / dinv / y on levels l, l, l + 1 and l
@@ -707,21 +710,36 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
   DLevel<T> &L = H.lv[l];
   if (L.ncont > 0) {
     DLevel<T> &C = H.lv[l + 1];
-    T *t = dptr<T>(L.t);
+    T *t = dptr<T>(L.t), *r = dptr<T>(L.r);
     const T *dinv = dptr<const T>(L.dinv);
     const bool fine = H.is_omega && l == 0;
     const int ks = fine ? kKcFineSmooth : kKcVcycleOther;
     const int kr = fine ? kKcFineResid : kKcVcycleOther;
     const int ko = kKcVcycleOther;
-    // pre-smoothing from zero is t = D^-1 b; its residual r = b - A t
-    if (!L.fused) spmv<kResid>(L.A, static_cast<const T *>(t), b, dinv, dptr<T>(L.r), mnull<T>(), gate, s, kr);
-    // b_c = R r (fused: R (I - A D^-1) b, the same vector) and the coarse
+    // pre-smoothing from zero: the first iterate is t = D^-1 b; further
+    // sweeps alternate between t and r
+    T *cur = t;
+    for (int k = 1; k < H.pre; ++k) {
+      T *nxt = cur == t ? r : t;
+      spmv<kSmooth>(L.A, static_cast<const T *>(cur), b, dinv, nxt, mnull<T>(), gate, s, ks);
+      cur = nxt;
+    }
+    // residual b - A cur, in the buffer of t and r that cur does not hold
+    T *res = cur == t ? r : t;
+    if (!L.fused) spmv<kResid>(L.A, static_cast<const T *>(cur), b, dinv, res, mnull<T>(), gate, s, kr);
+    // b_c = R res (fused: R (I - A D^-1) b, the same vector) and the coarse
     // level's first iterate t_c = D_c^-1 b_c
-    spmv<kPlainScale>(L.R, L.fused ? b : dptr<const T>(L.r), cnull<T>(), dptr<const T>(C.dinv), dptr<T>(C.b),
-                      dptr<T>(C.t), gate, s, L.fused && fine ? kr : ko);
+    spmv<kPlainScale>(L.R, L.fused ? b : static_cast<const T *>(res), cnull<T>(), dptr<const T>(C.dinv),
+                      dptr<T>(C.b), dptr<T>(C.t), gate, s, L.fused && fine ? kr : ko);
     vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
-    spmv<kAccum>(L.P, dptr<const T>(C.x), cnull<T>(), cnull<T>(), t, mnull<T>(), gate, s, ko);  // t += P x_c
-    spmv<kSmooth>(L.A, static_cast<const T *>(t), b, dinv, x, mnull<T>(), gate, s, ks);       // post-smooth
+    spmv<kAccum>(L.P, dptr<const T>(C.x), cnull<T>(), cnull<T>(), cur, mnull<T>(), gate, s, ko);  // cur += P x_c
+    // post-smoothing: the last sweep writes x, earlier ones alternate
+    // between t and r
+    for (int k = 0; k < H.post; ++k) {
+      T *nxt = k + 1 == H.post ? x : (cur == t ? r : t);
+      spmv<kSmooth>(L.A, static_cast<const T *>(cur), b, dinv, nxt, mnull<T>(), gate, s, ks);
+      cur = nxt;
+    }
   }
   if (L.ncont < L.n) coarse_solve(H, L, b, x, gate, s);
 }
@@ -790,12 +808,13 @@ void apply_ml(Precond<T> &P, const T *r, T *z, Gate gate, hipStream_t s) {
 // the matrices; the preconditioner's vectors are [Omega blocks; Gamma blocks].
 template <typename T>
 std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *> &sys, const LevelPlan &plan_o,
-                                           const LevelPlan &plan_g, const std::vector<int> &gsys, int vcycles,
-                                           int form, hipStream_t s, int kb = 1) {
+                                           const LevelPlan &plan_g, const std::vector<int> &gsys,
+                                           const mdp_options &opt, hipStream_t s, int kb = 1) {
   auto p = std::make_unique<Precond<T>>();
   Keep keep;
-  p->vcycles = vcycles;
-  p->form = form;
+  p->vcycles = opt.vcycles;
+  p->form = opt.block_form;
+  const int form = opt.block_form;
   std::vector<const HHier *> ho, hg;
   for (const HostSystem *h : sys) ho.push_back(&h->Ho);
   for (int q : gsys) hg.push_back(&sys[q]->Hg);
@@ -804,12 +823,12 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
   for (size_t q = 0; q < sys.size(); ++q) sys_o[q] = static_cast<int>(q);
   const int nsys = static_cast<int>(sys.size());
   const bool maps = nsys > 1;
-  upload_hier(ho, plan_o, p->Ho, s, keep, maps ? &sys_o : nullptr, kb, nsys);
+  upload_hier(ho, plan_o, p->Ho, s, keep, opt.pre_sweeps, opt.post_sweeps, maps ? &sys_o : nullptr, kb, nsys);
   p->Ho.is_omega = true;
   const int32_t no1 = p->Ho.n();
   p->n_o = static_cast<int32_t>(p->Ho.nfull());
   if (!gsys.empty()) {
-    upload_hier(hg, plan_g, p->Hg, s, keep, maps ? &gsys : nullptr, kb, nsys);
+    upload_hier(hg, plan_g, p->Hg, s, keep, opt.pre_sweeps, opt.post_sweeps, maps ? &gsys : nullptr, kb, nsys);
     const int32_t ng1 = p->Hg.n();
     p->n_g = static_cast<int32_t>(p->Hg.nfull());
     auto blocks = [&](DCsr<T> &M, int64_t xs, int64_t ys) {
@@ -1252,9 +1271,9 @@ void Solver::upload(hipStream_t s) {
   const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
   const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(sys, po, pg, gp, opt.vcycles, opt.block_form, s);
+    pc32 = upload_precond<float>(sys, po, pg, gp, opt, s);
   else
-    pc64 = upload_precond<double>(sys, po, pg, gp, opt.vcycles, opt.block_form, s);
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt, s);
   layout.build({{{0, n}}}, n, s);
   const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
   ws.alloc(n, opt.restart, 1, layout.ntiles, tsz, s);
@@ -1457,9 +1476,9 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
   upload_vec(gpair, keep.put(std::move(gpair_h)), s);
   if (npairs > 1) A.rowpair = dptr<const int>(gpair);
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(hsys, po, pg, gsys, opt.vcycles, opt.block_form, s, kb);
+    pc32 = upload_precond<float>(hsys, po, pg, gsys, opt, s, kb);
   else
-    pc64 = upload_precond<double>(hsys, po, pg, gsys, opt.vcycles, opt.block_form, s, kb);
+    pc64 = upload_precond<double>(hsys, po, pg, gsys, opt, s, kb);
   layout.build(ranges, n, s);
   if (std::getenv("MDP_SETUP_VERBOSE"))
     std::fprintf(stderr, "[mdp] batch: %d pairs, %d right-hand-side blocks of %d systems, n=%d\n", npairs, kb, nsys,

@@ -68,7 +68,7 @@ struct DLevel {
   DevMem dense;     // DenseDesc[ndense]
   int32_t sw_off = 0;
   DCsr<T> Asw;      // swept coarsest systems, indices relative to sw_off
-  DevMem x, b, t, r;  // unknown, right-hand side, smoothing scratch, residual
+  DevMem x, b, t, r;  // unknown, right-hand side, smoothing iterate, residual (and sweep ping-pong)
   DevMem pp;          // ping-pong for the swept coarsest systems
 };
 
@@ -80,6 +80,7 @@ template <typename T>
 struct DHier {
   std::vector<DLevel<T>> lv;
   int kb = 1;
+  int pre = 1, post = 1;        // l1-Jacobi sweeps before and after the coarse correction
   std::vector<DevMem> rowpair;  // batched: per level, the pair of each row
   DevMem cinv;            // dense FP64 inverses of the coarsest levels
   DevMem tmp_res, tmp_dz; // extra cycles: residual and correction at level 0

@@ -11,6 +11,7 @@ constexpr int kMaxCols = 64;      // Krylov basis columns handled by one Arnoldi
 constexpr int kCsrBatch = 4;       // CSR-vector entries in flight per lane under the fixed rule
 constexpr int kMaxDiag = 16;       // most offsets of the diagonal layouts
 constexpr int kMultiRhs = 4;       // right-hand sides that share one matrix read in a batch
+constexpr int kMaxSweeps = 8;      // l1-Jacobi sweeps before / after the coarse correction, at most
 constexpr int kDotU = 9;          // elements per thread in the Arnoldi passes (tiles of up to 2304)
 constexpr int kTileElems = 256 * kDotU;
 

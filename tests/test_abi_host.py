@@ -151,6 +151,8 @@ def test_input_validation_errors():
     _expect(L.MDP_EINVAL, A, part, restart=65)
     _expect(L.MDP_EINVAL, A, part, precision=7)
     _expect(L.MDP_EINVAL, A, part, rtol=0.0)
+    _expect(L.MDP_EINVAL, A, part, pre_sweeps=0)
+    _expect(L.MDP_EINVAL, A, part, post_sweeps=9)
 
 
 def test_singular_system_is_reported():

@@ -112,3 +112,31 @@ def test_operator_runs_are_bitwise_deterministic():
         assert np.array_equal(z1, z2)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("pre,post", [(2, 1), (1, 2), (3, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sweep_counts_match_oracle(pre, post, prec):
+    """pre_sweeps / post_sweeps l1-Jacobi sweeps around each coarse
+    correction (the fused restriction only serves the single pre-sweep from
+    zero): M_L and a whole solve against the oracle with the same counts."""
+    from oracle import solve as osv
+    sc = synth.regular_3d(n=12, seed=5, k_par=1e4, kappa=1e-4)
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    say(f"[operators] sweeps pre={pre} post={post} {prec}")
+    ao = amg.AMGOptions(max_coarse=30, pre_sweeps=pre, post_sweeps=post)
+    s = Solver(A, part, precision=prec, max_coarse=30, pre_sweeps=pre, post_sweeps=post)
+    M = precond.ML(Ao, po, cycles=1, amg_opts=ao)
+    try:
+        x = synth.random_vector(A.shape[0], 15)
+        z = host(s.apply(L.MDP_OP_ML, dev(x)))
+        assert relerr(z, M.apply(x)) <= TOL[prec]
+        ref, _, _ = osv.solve(Ao, bo, po, osv.SolveOptions(amg=ao), M=M)
+        xs, st = s.solve(dev(b))
+        xh = host(xs)
+        assert st[0]["converged"] == 1 and abs(st[0]["iters"] - ref.iters) <= 2, (st[0], ref.iters)
+        assert np.linalg.norm(bo - Ao @ xh) <= 1e-8 * np.linalg.norm(bo)
+        assert relerr(xh, ref.x) <= 1e-6
+    finally:
+        s.close()
