@@ -322,8 +322,31 @@ def mdp_server_destroy(srv: int) -> None:
         del _inflight[key]
 
 
-def mdp_set_allocator(alloc=None, free=None, ctx=None) -> None:
-    _check(lib.mdp_set_allocator(alloc, free, ctx), "mdp_set_allocator")
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# Every C callback pair ever installed stays alive: blocks keep the allocator
+# that made them and are freed through it even after another is installed.
+_allocators = []
+
+
+def mdp_set_allocator(alloc=None, free=None) -> None:
+    """alloc(nbytes) -> device pointer (int, 0 on failure) and free(ptr):
+    Python callables, wrapped as the C callbacks of mdp_set_allocator.  Both
+    None restores hipMalloc / hipFree."""
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both be None")
+    if alloc is None:
+        _check(lib.mdp_set_allocator(None, None, None), "mdp_set_allocator")
+        return
+    def _alloc(n, ctx):
+        try:
+            return alloc(n) or None
+        except Exception:  # the library reports MDP_ENOMEM for NULL
+            return None
+
+    cbs = (ALLOC_FN(_alloc), FREE_FN(lambda p, ctx: free(p)))
+    _allocators.append(cbs)
+    _check(lib.mdp_set_allocator(C.cast(cbs[0], _vp), C.cast(cbs[1], _vp), None), "mdp_set_allocator")
 
 
 def mdp_last_error() -> str:

@@ -553,17 +553,25 @@ __global__ __launch_bounds__(kThreads) void scale_copy_kernel(int64_t n, const T
     out[i] = static_cast<TO>(static_cast<double>(in[i]) * s);
 }
 
-// rin = (float) u for all n entries; t[i] = rin[i] * dinv[i] for the first no
-// (the host block's first smoother iterate), when t is given.
-__global__ __launch_bounds__(kThreads) void cast_start_kernel(int64_t n, int no, const double *__restrict__ u,
+// First preconditioner input of a cycle, one tile per workgroup: rin =
+// (float)(u * scale[pair]) over the tile (the cycle's unnormalised residual
+// brought to unit norm before the FP32 cast, so that no entry leaves FP32's
+// range; FGMRES is unchanged by the scale of a preconditioned direction,
+// since A z_j is formed from the stored z_j); t[i] = rin[i] * dinv[i] on the
+// first no entries (the host block's first smoother iterate), when t is given.
+__global__ __launch_bounds__(kThreads) void cast_start_kernel(const Tile *__restrict__ tiles, int64_t no,
+                                                              const double *__restrict__ u,
+                                                              const double *__restrict__ scale,
                                                               float *__restrict__ rin,
                                                               const float *__restrict__ dinv,
                                                               float *__restrict__ t,
                                                               const int *__restrict__ gate) {
   if (gate && *gate) return;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const float v = static_cast<float>(u[i]);
+  const Tile tl = tiles[blockIdx.x];
+  const double sc = scale[tl.pair];
+  for (int k = threadIdx.x; k < tl.len; k += kThreads) {
+    const int64_t i = tl.start + k;
+    const float v = static_cast<float>(u[i] * sc);
     rin[i] = v;
     if (t && i < no) t[i] = v * dinv[i];
   }
@@ -1011,7 +1019,7 @@ __global__ __launch_bounds__(kThreads) void dcgs_update_kernel(const Tile *__res
       u[e] = qj;
       const double next = (ww[k] - hj * qj) * inv_nu;
       un[e] = next;
-      if (nin.rin) {  // same arithmetic as cast_start_kernel
+      if (nin.rin) {  // FP32 copy; u_{j+1} is already scaled to unit norm
         const float v = static_cast<float>(next);
         nin.rin[e] = v;
         if (nin.t32 && e < nin.n_o) nin.t32[e] = v * nin.dinv32[e];

@@ -193,10 +193,13 @@ std::vector<double> dense_inverse(const HCsr &a) {
   return inv;
 }
 
-// For a symmetric matrix with non-positive off-diagonals (an M-matrix
-// candidate, as two-point flux produces), a connected component whose rows all
-// sum to zero is singular: nothing ties its pressure level (no Dirichlet
-// contact).  Such input cannot be solved and is rejected up front.
+// For a matrix with non-positive off-diagonals (an M-matrix candidate, as
+// two-point flux produces; symmetric or not), call row i grounded when its
+// row sum is positive (a Dirichlet contact).  The rows that cannot reach a
+// grounded row along their nonzeros (i -> j for a_ij != 0) form a set U
+// closed under that relation whose rows all sum to zero, so A[U, U] 1 = 0 and
+// the rows of U couple only to U: A is singular, nothing ties the level of
+// U.  Such input cannot be solved and is rejected up front.
 void check_grounded(const HCsr &a) {
   const int32_t n = a.nr;
   std::vector<double> rs(static_cast<size_t>(n), 0.0), dg(static_cast<size_t>(n), 0.0);
@@ -206,28 +209,32 @@ void check_grounded(const HCsr &a) {
       rs[i] += a.val[p];
       if (a.col[p] == i) dg[i] = a.val[p];
     }
-  std::vector<int32_t> comp(static_cast<size_t>(n), -1), stack;
-  for (int32_t s0 = 0; s0 < n; ++s0) {
-    if (comp[s0] >= 0) continue;
-    bool grounded = false;
-    stack.assign(1, s0);
-    comp[s0] = s0;
-    while (!stack.empty()) {
-      const int32_t i = stack.back();
-      stack.pop_back();
-      if (rs[i] > 1e-10 * dg[i]) grounded = true;
-      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
-        const int32_t j = a.col[p];
-        if (a.val[p] != 0.0 && comp[j] < 0) {
-          comp[j] = s0;
-          stack.push_back(j);
-        }
+  // walk the transpose from the grounded rows: row j reaches ground when
+  // a_ji != 0 for a row i that does
+  const HCsr t = transpose(a);
+  std::vector<char> reach(static_cast<size_t>(n), 0);
+  std::vector<int32_t> stack;
+  for (int32_t i = 0; i < n; ++i)
+    if (rs[i] > 1e-10 * dg[i]) {
+      reach[i] = 1;
+      stack.push_back(i);
+    }
+  while (!stack.empty()) {
+    const int32_t i = stack.back();
+    stack.pop_back();
+    for (int32_t p = t.ptr[i]; p < t.ptr[i + 1]; ++p) {  // rows j with a_ji != 0
+      const int32_t j = t.col[p];
+      if (t.val[p] != 0.0 && !reach[j]) {
+        reach[j] = 1;
+        stack.push_back(j);
       }
     }
-    if (!grounded)
-      fail(MDP_ESINGULAR, "a connected group of unknowns (starting at row " + std::to_string(s0) +
-                              ") has zero row sums: no boundary condition fixes its level");
   }
+  for (int32_t i = 0; i < n; ++i)
+    if (!reach[i])
+      fail(MDP_ESINGULAR, "row " + std::to_string(i) +
+                              " cannot reach a row with a positive row sum: no boundary condition fixes the level "
+                              "of the unknowns it couples to");
 }
 
 }  // namespace
@@ -330,7 +337,7 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
     HCsr t = transpose(A);
     s.symmetric = (t.col == A.col && t.val == A.val);
   }
-  if (s.symmetric) check_grounded(A);
+  check_grounded(A);
   clk.lap("symmetry + grounding");
 
   std::vector<int32_t> rows_o(static_cast<size_t>(s.n_o)), rows_g(static_cast<size_t>(s.n_g));

@@ -933,7 +933,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   const Gate g_apply{gate_apply, np > 1 ? static_cast<const GmresState *>(dst) : nullptr};
   const Tile *tiles = dptr<const Tile>(L.tiles);
 
-  std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0);
+  std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0), scale0(np, 1.0);
   std::vector<int> iters(np, 0), cycles(np, 0), code(np, MDP_OK), active(np, 0), kmax_h(np, 0);
   pair_norms(ws, L, bg, s);
   for (int p = 0; p < np; ++p) {
@@ -971,6 +971,11 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     MDP_HIP(hipMemcpyAsync(ws.active.get(), active.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     MDP_HIP(hipMemcpyAsync(ws.kmaxp.get(), kmax_h.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     MDP_HIP(hipMemcpyAsync(ws.tolp.get(), tol.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    if constexpr (!std::is_same<T, double>::value) {
+      // mixed: the cycle's first FP32 preconditioner input is the residual / beta
+      for (int p = 0; p < np; ++p) scale0[p] = active[p] && beta[p] > 0.0 ? 1.0 / beta[p] : 1.0;
+      MDP_HIP(hipMemcpyAsync(ws.scale0.get(), scale0.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    }
     hipLaunchKernelGGL(cycle_init_kernel, dim3(np), dim3(64), 0, s, dst, ctl, np, nactive,
                        dptr<const int>(ws.active), dptr<double>(ws.g), ws.ldv);
     // V[:, 0] holds every pair's residual at the cycle start, unnormalised.
@@ -997,7 +1002,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
           const int no = P.n_o;
           const bool need_t = !P.Ho.dense_only();
           timed_launch(kKcOther, s, 12.0 * n + 8.0 * no, [&] {
-            hipLaunchKernelGGL(cast_start_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, n, no, uj, rin,
+            hipLaunchKernelGGL(cast_start_kernel, dim3(L.ntiles), dim3(kThreads), 0, s, tiles,
+                               static_cast<int64_t>(no), uj, dptr<const double>(ws.scale0), rin,
                                dptr<const float>(P.Ho.lv[0].dinv), need_t ? dptr<float>(P.Ho.lv[0].t) : nullptr,
                                gate_apply);
           });
@@ -1187,6 +1193,7 @@ void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t
   ctl.alloc(sizeof(BatchCtl));
   kmaxp.alloc(static_cast<size_t>(np) * sizeof(int));
   tolp.alloc(static_cast<size_t>(np) * sizeof(double));
+  scale0.alloc(static_cast<size_t>(np) * sizeof(double));
   active.alloc(static_cast<size_t>(np) * sizeof(int));
   norms.alloc(static_cast<size_t>(np) * sizeof(double));
   // written by the update kernel through its device address (mapped, coherent)
@@ -1227,14 +1234,14 @@ void Workspace::release() {
   host_state = nullptr;
   host_norms = nullptr;
   for (DevMem *d : {&V, &Z, &w, &rin, &bp, &xp, &Hr, &cs, &sn, &g, &y, &hist, &hprev, &coef, &sums, &partial, &npart,
-                    &state, &ctl, &kmaxp, &tolp, &active, &norms})
+                    &state, &ctl, &kmaxp, &tolp, &scale0, &active, &norms})
     d->reset();
 }
 
 size_t Workspace::device_bytes() const {
   size_t b = 0;
   for (const DevMem *d : {&V, &Z, &w, &rin, &bp, &xp, &Hr, &cs, &sn, &g, &y, &hist, &hprev, &coef, &sums, &partial,
-                          &npart, &state, &ctl, &kmaxp, &tolp, &active, &norms})
+                          &npart, &state, &ctl, &kmaxp, &tolp, &scale0, &active, &norms})
     b += d->bytes();
   return b;
 }

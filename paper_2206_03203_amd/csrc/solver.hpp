@@ -126,7 +126,7 @@ struct Workspace {
   DevMem V, Z, w, rin, bp, xp;
   DevMem Hr, cs, sn, g, y, hist, hprev, coef, sums;
   DevMem partial, npart;
-  DevMem state, ctl, kmaxp, tolp, active, norms;
+  DevMem state, ctl, kmaxp, tolp, scale0, active, norms;  // scale0: per pair, 1 / beta of the cycle (mixed)
   BatchCtl *host_ctl = nullptr;      // pinned, one slot per step
   BatchCtl *host_ctl_dev = nullptr;  // its device address
   GmresState *host_state = nullptr;  // pinned, npairs

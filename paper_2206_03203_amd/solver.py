@@ -50,3 +50,15 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Route the library's device allocations made from now on through
+    PyTorch's caching allocator (on the calling thread's current stream), or
+    back to hipMalloc.  Memory already held keeps the allocator that made it."""
+    import torch
+    if on:
+        L.mdp_set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                            lambda p: torch.cuda.caching_allocator_delete(p))
+    else:
+        L.mdp_set_allocator(None, None)

@@ -165,6 +165,40 @@ def test_singular_system_is_reported():
     _expect(L.MDP_ESINGULAR, A, part)
 
 
+def test_singular_nonsymmetric_system_is_reported():
+    """The same pure-Neumann system with its rows scaled by positive factors
+    (nonsymmetric, A_OG != A_GO^T): still A 1 = 0, still rejected.  With a
+    Dirichlet boundary the row-scaled system is accepted."""
+    sc0 = synth.tiny_2d(8)
+    sc = synth.Scenario(2, sc0.n, sc0.k_host, sc0.fractures, {})
+    A, b, part = tpfa.assemble(sc)
+    rs = 1.0 + 3.0 * synth.random_vector(A.shape[0], 2) ** 2
+    As = sp.csr_matrix(sp.diags(rs) @ A)
+    assert abs(As - As.T).max() > 0
+    _expect(L.MDP_ESINGULAR, As, part)
+    A2, b2, part2 = tpfa.assemble(sc0)
+    h = _host_handle(sp.csr_matrix(sp.diags(rs) @ A2), part2)
+    L.mdp_destroy(h)
+
+
+def test_singular_part_of_a_grounded_system_is_reported():
+    """Directed coupling: rows 0..k-1 (zero row sums) reference only each
+    other, while the rest is grounded and references them.  Row-wise the
+    first block cannot reach a Dirichlet row, so A is singular although the
+    whole graph is connected."""
+    n, k = 6, 3
+    A = np.zeros((n, n))
+    for i in range(k):  # closed, zero-row-sum block (a directed ring)
+        A[i, i] = 1.0
+        A[i, (i + 1) % k] = -1.0
+    for i in range(k, n):  # grounded rows that also couple to the block
+        A[i, i] = 3.0
+        A[i, i - 1] = -1.0
+    part = np.zeros(n, dtype=np.int32)
+    assert abs(np.linalg.det(A)) < 1e-12
+    _expect(L.MDP_ESINGULAR, sp.csr_matrix(A), part)
+
+
 def test_no_fracture_unknowns_allowed():
     n = 12
     sc = synth.Scenario(2, n, np.ones(n * n), [], {(0, 0): 1.0, (0, 1): 0.0})

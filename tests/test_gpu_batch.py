@@ -127,3 +127,48 @@ def test_batch_split_into_chunks(monkeypatch, capfd):
     finally:
         for s in solvers:
             s.close()
+
+
+@pytest.mark.timeout(600)
+def test_batch_at_uneven_2d_workload_sizes():
+    """The uneven 2D batch workload at its own sizes: 16 systems with sides
+    drawn from 64..512 and 1..20 fracture segments (log-uniform K_par, kappa
+    in [1e-4, 1e4]), four right-hand sides each (Dirichlet data alone and
+    with three host source fields), mixed precision, one mdp_solve_batch call
+    (the four-block layout that shares the preconditioner's matrices).  Every
+    pair: converged, residual of the oracle's own matrix and right-hand side
+    at most 1e-8, iterations within 2 of the pair solved alone (one column
+    through mdp_solve), and the two solutions within 1e-6."""
+    scs = [synth.random_2d(s) for s in range(16)]
+    solvers, bs, xs, srcs = [], [], [], []
+    for i, sc in enumerate(scs):
+        fs = [None] + [synth.host_sources(sc, 4 * i + k) for k in range(1, 4)]
+        A, B, part = tpfa.assemble(sc, sources=fs)
+        solvers.append(Solver(A, part, precision="mixed"))
+        bs.append(dev(np.ascontiguousarray(B.T)))
+        xs.append(torch.zeros_like(bs[-1]))
+        srcs.append(fs)
+    say(f"[batch] workload sizes: sides {[sc.n for sc in scs]}, segments {[len(sc.fractures) for sc in scs]}")
+    try:
+        rc, st = L.mdp_solve_batch([s.handle for s in solvers], bs, xs)
+        assert rc == L.MDP_OK
+        k = 0
+        worst = 0.0
+        for i, sc in enumerate(scs):
+            for r in range(4):
+                Ao, bo, po = oa.assemble(sc.with_source(srcs[i][r]))
+                xb = host(xs[i][r])
+                res = np.linalg.norm(bo - Ao @ xb) / np.linalg.norm(bo)
+                x1, st1 = solvers[i].solve(bs[i][r].clone())
+                d = relerr(xb, host(x1))
+                worst = max(worst, d)
+                say(f"    sys={i} n={Ao.shape[0]} rhs={r} iters batch={st[k]['iters']} alone={st1[0]['iters']} "
+                    f"res={res:.2e} diff={d:.2e}")
+                assert st[k]["converged"] == 1 and res <= 1e-8
+                assert abs(st[k]["iters"] - st1[0]["iters"]) <= 2
+                assert d <= 1e-6
+                k += 1
+        say(f"[batch] workload sizes: largest batch-vs-alone difference {worst:.2e}")
+    finally:
+        for s in solvers:
+            s.close()

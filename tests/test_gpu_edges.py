@@ -141,3 +141,39 @@ def test_iteration_budget_exhausted():
                 assert abs(r - st[0]["rel_res_true"]) <= 1e-12 and r < 1.0
         finally:
             s.close()
+
+
+@pytest.mark.parametrize("scale", [1e-40, 1e30])
+@pytest.mark.parametrize("batched", [False, True])
+def test_right_hand_sides_outside_fp32_range_in_mixed_mode(scale, batched):
+    """Mixed precision with b scaled far outside what FP32 holds at the
+    right-hand side's own size (1e-40: below FP32's normal range; 1e30: the
+    preconditioner's products would overflow).  The cycle's residual is
+    brought to unit norm before the FP32 cast, so the solve is that of the
+    unscaled b times the scale: same iteration count, the oracle's solution
+    of the scaled system within 1e-6, residual of the oracle's matrix <= 1e-8."""
+    sc = synth.regular_3d(n=10, seed=3, k_par=1e4, kappa=1e-4)
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    say(f"[edges] mixed scale={scale:g} batched={batched}")
+    ref, _, _ = osv.solve(Ao, bo * scale, po, osv.SolveOptions(tol=1e-12))
+    s = Solver(A, part, precision="mixed")
+    try:
+        _, st1 = s.solve(dev(b))
+        bt = dev(b * scale)
+        if batched:
+            s2 = Solver(A, part, precision="mixed")
+            xs = [torch.zeros_like(bt), torch.zeros_like(bt)]
+            rc, sts = L.mdp_solve_batch([s.handle, s2.handle], [bt, dev(b)], xs, None)
+            s2.close()
+            x, st = host(xs[0]), sts[0]
+            assert sts[1]["iters"] == st1[0]["iters"]
+        else:
+            xt, sts = s.solve(bt)
+            x, st = host(xt), sts[0]
+        assert st["converged"] == 1 and st["status"] == L.MDP_OK, st
+        assert abs(st["iters"] - st1[0]["iters"]) <= 1, (st, st1)
+        assert np.linalg.norm(bo * scale - Ao @ x) <= 1e-8 * np.linalg.norm(bo * scale)
+        assert relerr(x, ref.x) <= 1e-6
+    finally:
+        s.close()
