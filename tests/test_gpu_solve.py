@@ -242,3 +242,47 @@ def test_no_fractures():
         assert np.linalg.norm(bo - Ao @ host(x)) <= 1e-8 * np.linalg.norm(bo)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["2d-four-lines-32", "3d-regular-20-hi-lo", "2d-random-s9"])
+def test_nonsymmetric_system_matches_oracle(name, prec):
+    """Section 3.1 keeps A_OG and A_GO apart (symmetry is not used): the
+    system with its rows scaled by seeded positive factors (fracture rows by
+    100 more) is nonsymmetric, so A_OG != A_GO^T and S~ of eq. (7) is
+    nonsymmetric too.  The library and the oracle set it up independently;
+    M_L on a seeded vector and the whole solve must agree: the GPU's iterate
+    against the oracle's at the same tolerance (the same iteration count
+    within 2, solution within 1e-6).  The row scaling makes the system worse
+    conditioned, so a 1e-8 residual bounds the error against the exact
+    solution only by cond(A) 1e-8; that error is reported, not bounded."""
+    from oracle import amg, precond
+    import scipy.sparse as sp
+    sc = CASES[name]()
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    rs = 1.0 + 3.0 * synth.random_vector(A.shape[0], 31) ** 2
+    rs[np.asarray(part) == 1] *= 100.0
+    As, bs = sp.csr_matrix(sp.diags(rs) @ A), rs * b
+    Aos, bos = sp.csr_matrix(sp.diags(rs) @ Ao), rs * bo
+    assert abs(As - As.T).max() > 0
+    say(f"[solve] nonsymmetric {name} {prec} n={A.shape[0]}")
+    M = precond.ML(Aos, po, cycles=1)
+    ref, _, _ = osv.solve(Aos, bos, po, osv.SolveOptions(tol=1e-12), M=M)
+    ref8, _, _ = osv.solve(Aos, bos, po, osv.SolveOptions(tol=1e-8), M=M)
+    s = Solver(As, part, precision=prec)
+    try:
+        x = synth.random_vector(A.shape[0], 32)
+        z = host(s.apply(L.MDP_OP_ML, dev(x)))
+        assert relerr(z, M.apply(x)) <= (1e-11 if prec == "fp64" else 3e-5)
+        xt, st = s.solve(dev(bs))
+        xh = host(xt)
+        res = np.linalg.norm(bos - Aos @ xh) / np.linalg.norm(bos)
+        err8, err = relerr(xh, ref8.x), relerr(xh, ref.x)
+        say(f"    iters {st[0]['iters']} (oracle {ref8.iters}) residual {res:.2e} error vs the oracle at 1e-8 "
+            f"{err8:.2e}, vs the oracle at 1e-12 {err:.2e}")
+        assert st[0]["converged"] == 1 and res <= 1e-8
+        assert abs(st[0]["iters"] - ref8.iters) <= 2
+        assert err8 <= 1e-6
+    finally:
+        s.close()
