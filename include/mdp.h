@@ -233,6 +233,21 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b_
  * Synchronises hip_stream. */
 int mdp_apply(mdp_handle *h, int32_t op, const double *x_dev, double *y_dev, void *hip_stream);
 
+/* mdp_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same operators and kernels as mdp_apply (the results are identical), but
+ * the call allocates nothing and does not synchronise: it only enqueues the
+ * launches on hip_stream, and y is complete when the stream reaches that
+ * point.  In mixed precision the FP32 copies of x and y live in a fixed
+ * device array of 64 MiB that the library holds on each GPU it runs on until
+ * the process ends, so the operator's length (n, n_Omega or n_Gamma) is at
+ * most 8,388,608 there (EINVAL beyond); FP64 operators use no extra memory.
+ * All calls on one GPU share that array: calls that overlap in time on one
+ * GPU (different streams, or threads) race on it and must be serialised by
+ * the caller; calls on one stream are ordered and safe.  Refused (EINVAL)
+ * for host-only handles, unknown operators and while kernel timers run. */
+int mdp_apply_noalloc(mdp_handle *h, int32_t op, const double *x_dev, double *y_dev, void *hip_stream);
+
 /* ---- introspection (host memory; works for MDP_HOST_ONLY handles) ---------- */
 
 /* Sizes: n, n_Omega, n_Gamma and the number of levels of each hierarchy. */

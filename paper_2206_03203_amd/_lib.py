@@ -95,6 +95,7 @@ _sig = {
     "mdp_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _ip, _vp,
                                   C.POINTER(mdp_stats)]),
     "mdp_apply": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
+    "mdp_apply_noalloc": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "mdp_info": (C.c_int, [_vp, _ip, _ip, _ip, _ip, _ip]),
     "mdp_level_shape": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_int64)]),
     "mdp_level_export": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_double)]),
@@ -236,6 +237,11 @@ def mdp_solve_batch(hs: Sequence[int], bs, xs, stream=None, ok=(MDP_OK, MDP_NOT_
 
 def mdp_apply(h: int, op: int, x, y, stream=None) -> None:
     _check(lib.mdp_apply(h, op, _dptr(x), _dptr(y), _stream_ptr(stream)), "mdp_apply")
+
+
+def mdp_apply_noalloc(h: int, op: int, x, y, stream=None) -> None:
+    """Enqueues only (no synchronisation): y is ready once the stream has run."""
+    _check(lib.mdp_apply_noalloc(h, op, _dptr(x), _dptr(y), _stream_ptr(stream)), "mdp_apply_noalloc")
 
 
 def mdp_info(h: int) -> dict:

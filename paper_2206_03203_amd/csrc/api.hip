@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 
+#include "ktimer.hpp"
 #include "mdp.h"
 #include "solver.hpp"
 
@@ -32,6 +33,33 @@ struct BatchCache {
 };
 std::mutex g_batch_mu;
 std::unique_ptr<BatchCache> g_batch;
+
+// Device memory of mdp_apply_noalloc: the FP32 copies of its input and
+// output in mixed precision.  Every GPU the library runs on holds its own
+// copy, for the life of the process; kernels reach it through the address
+// that hipGetSymbolAddress returns on that device (the array's name in host
+// code is not a device address).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};  // per device, under g_scratch_mu
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device.
+float *scratch_on_current_device() {
+  int dev = 0;
+  MDP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) raise(MDP_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    MDP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) raise(MDP_EHIP, "no device address for the scratch array");
+    g_scratch[dev] = p;
+  }
+  return static_cast<float *>(g_scratch[dev]);
+}
 
 int64_t batch_max_unknowns() {
   const char *e = std::getenv("MDP_BATCH_MAX_UNKNOWNS");
@@ -465,6 +493,37 @@ int mdp_apply(mdp_handle *h, int32_t op, const double *x, double *y, void *hip_s
     return MDP_EINVAL;
   }
   h->s.apply(op, x, y, static_cast<hipStream_t>(hip_stream));
+  return MDP_OK;
+  API_END
+}
+
+int mdp_apply_noalloc(mdp_handle *h, int32_t op, const double *x, double *y, void *hip_stream) {
+  API_BEGIN
+  if (!h || !x || !y) {
+    set_last_error("bad apply arguments");
+    return MDP_EINVAL;
+  }
+  if (op != MDP_OP_A && op != MDP_OP_ML && op != MDP_OP_QOO && op != MDP_OP_QGG) {
+    set_last_error("unknown operator");
+    return MDP_EINVAL;
+  }
+  const int64_t len = op == MDP_OP_QOO ? h->s.n_o : (op == MDP_OP_QGG ? h->s.n_g : h->s.n);
+  const bool staged = h->s.opt.precision == MDP_MIXED && op != MDP_OP_A;
+  if (staged && 2 * len * static_cast<int64_t>(sizeof(float)) > static_cast<int64_t>(kScratchBytes)) {
+    set_last_error("operator of " + std::to_string(len) + " unknowns exceeds the no-allocation limit of " +
+                   std::to_string(kScratchBytes / (2 * sizeof(float))) + " in mixed precision");
+    return MDP_EINVAL;
+  }
+  if (!h->s.on_device) {
+    set_last_error("handle was set up host-only");
+    return MDP_EINVAL;
+  }
+  if (ktimer_any_on()) {
+    set_last_error("kernel timers are running (they create events); stop them first");
+    return MDP_EINVAL;
+  }
+  float *in = scratch_on_current_device();
+  h->s.enqueue_apply(op, x, y, static_cast<hipStream_t>(hip_stream), in, in + len);
   return MDP_OK;
   API_END
 }

@@ -1336,8 +1336,13 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
 }
 
 void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
-  const int64_t nn = n;
   ensure_workspace(s);
+  enqueue_apply(op, x, y, s, dptr<float>(ws.rin), dptr<float>(ws.Z));
+  MDP_HIP(hipStreamSynchronize(s));
+}
+
+void Solver::enqueue_apply(int op, const double *x, double *y, hipStream_t s, float *in, float *out) {
+  const int64_t nn = n;
   switch (op) {
     case MDP_OP_A:
       spmv<kPlain>(A, x, cnull<double>(), cnull<double>(), y, mnull<double>(), Gate{}, s);
@@ -1348,8 +1353,6 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
       const int64_t len = op == MDP_OP_ML ? nn : (op == MDP_OP_QOO ? n_o : n_g);
       if (len == 0) break;
       if (opt.precision == MDP_MIXED) {
-        float *in = dptr<float>(ws.rin);
-        float *out = dptr<float>(ws.Z);
         hipLaunchKernelGGL((scale_copy_kernel<double, float>), dim3(grid_for(len)), dim3(kThreads), 0, s, len, x,
                            cnull<double>(), in, nullptr);
         auto &H = op == MDP_OP_QGG ? pc32->Hg : pc32->Ho;
@@ -1374,7 +1377,6 @@ void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
       raise(MDP_EINVAL, "unknown operator");
   }
   MDP_HIP(hipGetLastError());
-  MDP_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------

@@ -170,6 +170,9 @@ struct Solver {
   size_t workspace_bytes_needed() const;
   int solve(const double *b, double *x, hipStream_t s, mdp_stats *st);
   void apply(int op, const double *x, double *y, hipStream_t s);
+  // The launches of apply, without allocation or synchronisation; in mixed
+  // precision `in` and `out` stage the FP32 copies of x and y (n entries each)
+  void enqueue_apply(int op, const double *x, double *y, hipStream_t s, float *in, float *out);
 };
 
 // A block-diagonal batch of pairs (a system appears once per right-hand side).

@@ -375,3 +375,21 @@ def test_hierarchy_file_rejects_damage(tmp_path):
     good = tmp_path / "good"
     good.write_bytes(data[:-8] + fnv(data[:-8]).to_bytes(8, "little"))
     L.mdp_destroy(L.mdp_load(str(good), o))  # the checksum is FNV-1a 64 over the body
+
+
+def test_noalloc_apply_refuses_operators_beyond_its_scratch():
+    """mdp_apply_noalloc stages mixed-precision operators in a fixed 64 MiB
+    array: at most 8,388,608 unknowns.  A host-only handle of 8,410,000
+    unknowns is refused for its size before anything touches a device."""
+    import ctypes
+    n = 2900
+    sc = synth.Scenario(2, n, np.ones(n * n), [], {(0, 0): 1.0, (0, 1): 0.0})
+    A, b, part = tpfa.assemble(sc)
+    h = _host_handle(A, part, precision=L.MDP_MIXED)
+    try:
+        rc = L.lib.mdp_apply_noalloc(h, L.MDP_OP_ML, ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+        assert rc == L.MDP_EINVAL and "exceeds the no-allocation limit of 8388608" in L.mdp_last_error()
+        rc = L.lib.mdp_apply_noalloc(h, L.MDP_OP_A, ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+        assert rc == L.MDP_EINVAL and "host-only" in L.mdp_last_error()
+    finally:
+        L.mdp_destroy(h)
