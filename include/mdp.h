@@ -332,6 +332,16 @@ int mdp_ktimer_begin(int32_t kind);
  * launches and the algorithmic bytes.  Waits for the recorded events. */
 int mdp_ktimer_end(int32_t kind, double *total_ms, int64_t *launches, double *bytes);
 
+/* Keep the device-format autotuner's choices (see MDP_NO_AUTOTUNE) in the
+ * text file `path`, one line per matrix signature (value size, rows,
+ * columns, longest row, entries, sliced-ELL size) and format.  Choices
+ * already recorded there are loaded now and used instead of timing, when the
+ * matrix has that layout; every new choice is appended.  Setups in later
+ * processes then pick the same formats, so their results are bit-identical
+ * and their set-up skips the timing.  NULL stops recording (loaded choices
+ * stay in use).  EINVAL if the file can neither be read nor created. */
+int mdp_tune_file(const char *path);
+
 /* ---- memory ----------------------------------------------------------- */
 
 /* Route device allocations through the caller's allocator (e.g. a framework

@@ -108,6 +108,7 @@ _sig = {
     "mdp_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(mdp_stats)]),
     "mdp_server_destroy": (C.c_int, [_vp]),
     "mdp_set_allocator": (C.c_int, [_vp, _vp, _vp]),
+    "mdp_tune_file": (C.c_int, [C.c_char_p]),
     "mdp_ktimer_begin": (C.c_int, [C.c_int32]),
     "mdp_ktimer_end": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mdp_last_error": (C.c_char_p, []),
@@ -353,6 +354,10 @@ def mdp_set_allocator(alloc=None, free=None) -> None:
     cbs = (ALLOC_FN(_alloc), FREE_FN(lambda p, ctx: free(p)))
     _allocators.append(cbs)
     _check(lib.mdp_set_allocator(C.cast(cbs[0], _vp), C.cast(cbs[1], _vp), None), "mdp_set_allocator")
+
+
+def mdp_tune_file(path: Optional[str]) -> None:
+    _check(lib.mdp_tune_file(path.encode() if path is not None else None), "mdp_tune_file")
 
 
 def mdp_last_error() -> str:

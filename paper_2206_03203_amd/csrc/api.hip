@@ -590,6 +590,13 @@ int mdp_level_aggregates(const mdp_handle *h, int32_t block, int32_t level, int3
   return MDP_OK;
 }
 
+int mdp_tune_file(const char *path) {
+  API_BEGIN
+  set_tune_file(path);
+  return MDP_OK;
+  API_END
+}
+
 int mdp_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx) {
   if ((alloc == nullptr) != (free_ == nullptr)) {
     set_last_error("alloc and free must both be set or both be NULL");

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <string>
 #include <mutex>
 #include <tuple>
 #include <type_traits>
@@ -147,7 +148,21 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, FormatChoice> g_tune;
+std::map<TuneKey, FormatChoice> g_tune;  // under g_tune_mu
+std::string g_tune_path;                 // file that records the choices ("" = none), under g_tune_mu
+
+// One choice per line: "vsize nr nc maxlen nnz padded  dia hyb sell scalar lpr batch".
+void tune_record(const TuneKey &k, const FormatChoice &f) {
+  if (g_tune_path.empty()) return;
+  if (FILE *fp = std::fopen(g_tune_path.c_str(), "a")) {
+    std::fprintf(fp, "%d %d %d %d %lld %lld  %d %d %d %d %d %d\n", k.vsize, k.nr, k.nc, k.maxlen,
+                 static_cast<long long>(k.nnz), static_cast<long long>(k.padded), f.dia, f.hyb, f.sell, f.scalar,
+                 f.lpr, f.batch);
+    std::fclose(fp);
+  }
+}
+
+bool valid_lpr(int l) { return l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64 || l == kThreads; }
 
 template <typename T>
 FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
@@ -548,9 +563,15 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
                              const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep) {
   const TuneKey key{static_cast<int>(sizeof(T)), h.nr, h.nc, st.maxlen, h.nnz(), st.padded};
   {
+    // a recorded choice is used when this matrix has that layout
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const auto it = g_tune.find(key);
-    if (it != g_tune.end()) return it->second;
+    if (it != g_tune.end()) {
+      const FormatChoice &f = it->second;
+      if ((!f.dia || !offs.empty()) && (!f.hyb || !hoffs.empty()) && (!f.sell || sell_possible(st, h.nnz(), 2.0)))
+        return f;
+      g_tune.erase(it);
+    }
   }
   DCsr<T> csr;
   csr.nr = h.nr;
@@ -658,9 +679,43 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
                  best.dia ? "dia" : best.hyb ? "dia+csr" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
                  best.lpr, best.batch, 1e3 * tbest);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune.emplace(key, best);
+  if (g_tune.emplace(key, best).second) tune_record(key, best);
   return best;
 }
+
+}  // namespace
+
+void set_tune_file(const char *path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_path.clear();
+  if (!path) return;
+  if (FILE *fp = std::fopen(path, "r")) {
+    // earlier choices take precedence over timing; malformed lines are skipped
+    char line[256];
+    while (std::fgets(line, sizeof line, fp)) {
+      TuneKey k{};
+      long long nnz = 0, padded = 0;
+      int dia = 0, hyb = 0, sell = 0, scalar = 0, lpr = 0, batch = 0;
+      if (std::sscanf(line, "%d %d %d %d %lld %lld %d %d %d %d %d %d", &k.vsize, &k.nr, &k.nc, &k.maxlen, &nnz,
+                      &padded, &dia, &hyb, &sell, &scalar, &lpr, &batch) != 12)
+        continue;
+      if ((k.vsize != 4 && k.vsize != 8) || dia + hyb + sell + scalar > 1 || !valid_lpr(lpr) ||
+          (batch != kCsrBatch && batch != 8))
+        continue;
+      k.nnz = nnz;
+      k.padded = padded;
+      g_tune[k] = FormatChoice{sell != 0, scalar != 0, lpr, batch, dia != 0, hyb != 0};
+    }
+    std::fclose(fp);
+  } else if (FILE *fp2 = std::fopen(path, "a")) {
+    std::fclose(fp2);
+  } else {
+    raise(MDP_EINVAL, std::string("cannot open the tuning file ") + path);
+  }
+  g_tune_path = path;
+}
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // V-cycle (Section 3.3): l1-Jacobi pre-smoothing from zero, residual,

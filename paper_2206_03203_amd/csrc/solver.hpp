@@ -200,6 +200,10 @@ struct Batch {
   int solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st);
 };
 
+// Record the autotuner's choices in the text file `path` and use the ones
+// already recorded there (NULL: stop recording).
+void set_tune_file(const char *path);
+
 }  // namespace mdp
 
 struct mdp_handle {

@@ -393,3 +393,15 @@ def test_noalloc_apply_refuses_operators_beyond_its_scratch():
         assert rc == L.MDP_EINVAL and "host-only" in L.mdp_last_error()
     finally:
         L.mdp_destroy(h)
+
+
+def test_tune_file_errors(tmp_path):
+    """A tuning file that cannot be created is refused; an unreadable line
+    is skipped; NULL stops recording."""
+    with pytest.raises(L.MdpError) as e:
+        L.mdp_tune_file(str(tmp_path / "no" / "such" / "dir" / "t.txt"))
+    assert e.value.code == L.MDP_EINVAL
+    p = tmp_path / "t.txt"
+    p.write_text("8 10 10 3 28 64  1 0 0 0 8 4\ngarbage\n8 10 10 3 28 64  1 1 0 0 8 4\n")
+    L.mdp_tune_file(str(p))
+    L.mdp_tune_file(None)
