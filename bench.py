@@ -1,35 +1,35 @@
 """Benchmark: solves/s of the solve phase on one MI355X.
 
-Workload (default): the 3D unit cube with a 100^3 two-point-flux host grid,
-log-normal host permeability (sigma = 1, seed 0) and nine full fracture
-planes (three per axis) with aperture 1e-4, for the four fracture
+Headline workload (``value``): the 3D unit cube with a 100^3 two-point-flux
+host grid, log-normal host permeability (sigma = 1, seed 0) and nine full
+fracture planes (three per axis) with aperture 1e-4, for the four fracture
 permeability pairs (K_par, kappa) in {1e-4, 1e4}^2; Dirichlet p = 1 / 0 on
 x = 0 / 1.  One step = one complete solve (zero initial guess to true
-relative residual 1e-8) of the next system in rotation.  Inputs and
-hierarchies are resident in HBM before the clock starts.
+relative residual 1e-8) of the next system in rotation, plain FP64.  Inputs
+and hierarchies are resident in HBM before the clock starts.
 
-The JSON line reports the plain-FP64 method as ``value`` and, beside it, the
-mixed mode (FP32 preconditioner, FP64 outer loop and coarse solve) on the
-same systems, per-solve latency percentiles, the same four systems solved
-together as one batch (``batched``, both precisions), each system with four
-right-hand sides in one call (``multi_rhs``), the roofline position
-of the dominant kernel (timed with HIP events inside the library on the
-launch stream) and the CPU oracle timed on a bounded sample on this host.
+Beside it on the same JSON line: the mixed mode (FP32 preconditioner, FP64
+outer loop and coarse solve) on the same systems, per-solve latency
+percentiles, the four systems as one batch (``batched``), four right-hand
+sides per call (``multi_rhs``), the error of every GPU result against the
+FP64 oracle's solution of the same system (``err_vs_oracle``), the roofline
+position of the dominant kernel and of every kernel class (HIP events inside
+the library on the launch stream), and the CPU oracle timed on this host.
+Further sections, each with its own set-up outside its clock:
 
-Two more workloads, each printing its own JSON line:
+* ``config1``: the 2D 32x32 grid with four full fracture lines, FP64;
+* ``cube160``: the same cube at 160^3 (4.33M unknowns), FP64 and mixed,
+  with its own roofline pass;
+* ``batch``: 256 uneven 2D systems (side uniform in 64..512, 1..20 random
+  fracture segments, log-uniform permeabilities in [1e-4, 1e4]), four
+  right-hand sides each, mixed, one mdp_solve_batch call per step, beside the
+  same pairs solved one system at a time;
+* ``serve``: a pool of resident systems (half 2D as above, half 3D with side
+  40..160 and 3..9 random planes), mixed, served by mdp_submit/mdp_poll under
+  open-loop Poisson arrivals at 0.5, 0.8 and 0.95 of the saturated rate.
 
-``--mode batch``: 256 uneven 2D systems (side uniform in 64..512, 1..20
-random fracture segments with log-uniform permeabilities in [1e-4, 1e4]),
-four right-hand sides each (Dirichlet data plus a uniform host source field),
-mixed precision, solved by mdp_solve_batch; one step = the whole batch.
-Beside it: the same pairs solved one system at a time with mdp_solve (one
-call per system with its four right-hand sides, which it takes together with
-shared matrix reads), mixed and plain FP64.
-
-``--mode serve``: a pool of 64 resident systems (32 2D as above, 32 3D with
-side 40..160 and 3..9 random planes), mixed precision, served by
-mdp_submit/mdp_poll under open-loop Poisson arrivals at 0.5, 0.8 and 0.95 of
-the measured saturated throughput; latency is submit to final poll.
+``--mode batch`` and ``--mode serve`` print those workloads alone, at full
+size (serving: 64 systems, 2000 requests per rate).
 """
 
 from __future__ import annotations
@@ -87,6 +87,11 @@ def parse():
     p.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: workspace memory budget")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="solve time after which the CPU oracle sample stops taking further systems")
+    p.add_argument("--sections", default="config1,cube160,batch,serve",
+                   help="default mode: further workloads on the JSON line (comma list of config1, cube160, "
+                        "batch, serve; empty = the headline only)")
+    p.add_argument("--tune-file", default=None,
+                   help="record the autotuner's format choices here and reuse the ones recorded (mdp_tune_file)")
     return p.parse_args()
 
 
@@ -110,11 +115,58 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
         return
 
-    if args.mode == "batch":
-        return mode_batch(args)
-    if args.mode == "serve":
-        return mode_serve(args)
+    from paper_2206_03203_amd import _lib as L
+    if args.tune_file:
+        L.mdp_tune_file(args.tune_file)
 
+    if args.mode == "batch":
+        print(json.dumps(mode_batch(args)), flush=True)
+        return
+    if args.mode == "serve":
+        print(json.dumps(mode_serve(args)), flush=True)
+        return
+
+    t_start = time.perf_counter()
+    line = run_cube(args, args.n, args.steps, args.warmup, headline=True)
+    sections = [x for x in args.sections.split(",") if x]
+    if "config1" in sections:
+        line["config1"] = run_config1(args)
+    if "cube160" in sections and args.n != 160:
+        c = run_cube(args, 160, 8, 4, headline=False)
+        line["cube160"] = {k: c[k] for k in ("value", "unit", "ms_per_step", "p50_ms", "p99_ms", "iters",
+                                              "max_rel_res", "mixed", "roofline", "roofline_classes",
+                                              "config", "setup_s")}
+        line["cube160"]["what"] = ("the same four (K_par, kappa) systems at 160^3; value = FP64 solves/s, "
+                                   "mixed beside it; eight timed solves per precision after four untimed")
+    if "batch" in sections:
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps, bargs.warmup, bargs.no_cpu_baseline = 3, 1, True
+        b = mode_batch(bargs, seq_steps=1)
+        line["batch"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "iters_mean", "iters_max",
+                                           "max_rel_res", "sequential_mixed", "sequential_fp64",
+                                           "speedup_vs_sequential_fp64", "speedup_vs_sequential_mixed",
+                                           "roofline", "config", "setup_s")}
+        line["batch"]["what"] = "256 uneven 2D systems x 4 right-hand sides, mixed, one mdp_solve_batch per step"
+    if "serve" in sections:
+        sargs = argparse.Namespace(**vars(args))
+        sargs.pool, sargs.requests, sargs.no_cpu_baseline = 32, 200, True
+        v = mode_serve(sargs)
+        line["serve"] = {k: v[k] for k in ("value", "unit", "saturated", "poisson", "alone_service_ms",
+                                           "config", "setup_s")}
+        line["serve"]["what"] = ("served solves/s, mixed, pool of 32 resident systems (16 2D, 16 3D), "
+                                 "200 Poisson requests per arrival rate; --mode serve runs 64 systems and "
+                                 "2000 requests per rate")
+    line["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+    print(json.dumps(line), flush=True)
+
+
+def run_cube(args, n, steps, warmup, headline):
+    """The 3D cube workload at n^3: the four (K_par, kappa) systems set up in
+    both precisions, timed FP64 and mixed passes of `steps` solves in
+    rotation, a roofline pass, and (headline only) the batched and
+    four-right-hand-side forms, the CPU oracle and the error of each result
+    against the oracle's solution."""
+    import torch
     import synth
     from paper_2206_03203_amd import _lib as L
     from paper_2206_03203_amd import tpfa
@@ -123,9 +175,9 @@ def main():
     stream = torch.cuda.current_stream()
     systems = []
     t_asm = t_setup = 0.0
-    for seed in range(args.seeds):
+    for seed in range(args.seeds if headline else 1):
         for kp, ka in PAIRS:
-            sc = synth.regular_3d(n=args.n, k_par=kp, kappa=ka, seed=seed)
+            sc = synth.regular_3d(n=n, k_par=kp, kappa=ka, seed=seed)
             t0 = time.perf_counter()
             A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
@@ -165,25 +217,25 @@ def main():
 
     out = {}
     for prec in ("fp64", "mixed"):
-        run(prec, args.warmup)
+        run(prec, warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lat, iters, res = run(prec, args.steps)
+        lat, iters, res = run(prec, steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         out[prec] = {"seconds": t1 - t0, "lat": lat, "iters": iters, "res": res}
-        log(f"[bench] {prec}: {args.steps} solves in {t1 - t0:.3f}s, iters={sorted(set(iters))}")
+        log(f"[bench] {n}^3 {prec}: {steps} solves in {t1 - t0:.3f}s, iters={sorted(set(iters))}")
 
     fp = out["fp64"]
     mx = out["mixed"]
-    value = args.steps / fp["seconds"]
-    mixed_value = args.steps / mx["seconds"]
+    value = steps / fp["seconds"]
+    mixed_value = steps / mx["seconds"]
 
     # Beside the one-at-a-time solves: the same systems solved together as
     # one block-diagonal batch (mdp_solve_batch), one launch per operation.
     batched = {}
-    if args.block == "lower":
-        nb = max(1, args.steps // len(systems))
+    if headline and args.block == "lower":
+        nb = max(1, steps // len(systems))
         for prec in ("fp64", "mixed"):
             hs = [s["h"][prec] for s in systems]
             bs = [s["b"] for s in systems]
@@ -209,7 +261,7 @@ def main():
     # the columns four at a time with each matrix read once for all four,
     # against the same columns solved one at a time.
     multi_rhs = {}
-    if args.block == "lower" and args.multi_rhs:
+    if headline and args.block == "lower" and args.multi_rhs:
         for s in systems:
             fs = [None] + [synth.host_sources(s["sc"], 100 + k) for k in range(3)]
             _, B, _ = tpfa.assemble(s["sc"], sources=fs)
@@ -253,17 +305,28 @@ def main():
     # library around every launch of each kernel class on its launch stream
     # (kept out of the timed passes above: the events lengthen the gaps
     # between kernels, not the kernels).
-    roofline, classes = roofline_pass(lambda: run("fp64", args.steps), args.kernel_class,
-                                      f"the {args.steps} FP64 steps repeated", fp["seconds"])
+    roofline, classes = roofline_pass(lambda: run("fp64", steps), args.kernel_class,
+                                      f"the {steps} FP64 steps repeated", fp["seconds"])
     if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
-            args.max_coarse == 400 and args.n == 100 and args.restart == 64:
-        roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{args.n}")
+            args.max_coarse == 400 and args.restart == 64:
+        roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import synth
-        items = [(synth.regular_3d(n=args.n, k_par=kp, kappa=ka, seed=0), None) for kp, ka in PAIRS]
-        cpu = cpu_full_solves(args, items, "seed 0")
+    # Each system's solution in both precisions against the oracle's solution
+    # of the same system (the oracle solves are the CPU baseline's).
+    cpu, errs = None, None
+    if headline and not args.no_cpu_baseline:
+        items = [(synth.regular_3d(n=n, k_par=kp, kappa=ka, seed=0), None) for kp, ka in PAIRS]
+        cpu, xo = cpu_full_solves(args, items, "seed 0")
+        errs = []
+        for s, (name, xor, it_o) in zip(systems, xo):
+            e = {"system": name, "oracle_iters": it_o}
+            for prec in ("fp64", "mixed"):
+                x = torch.zeros_like(s["b"])
+                rc, st = L.mdp_solve(s["h"][prec], s["b"], x, stream)
+                xh = x.cpu().numpy()
+                e[prec] = float(np.linalg.norm(xh - xor) / np.linalg.norm(xor))
+                e[prec + "_iters"] = st[0]["iters"]
+            errs.append(e)
 
     for s in systems:
         for h in s["h"].values():
@@ -277,15 +340,15 @@ def main():
         "value": round(value, 3),
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * fp["seconds"] / args.steps, 3),
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(1e3 * fp["seconds"] / steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3d-unit-cube-{args.n}^3-9-planes-lognormal-host",
+        "config": {"workload": f"3d-unit-cube-{n}^3-9-planes-lognormal-host",
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
                    "amg_max_coarse": args.max_coarse, "restart": args.restart,
@@ -297,17 +360,55 @@ def main():
         "max_rel_res": max(fp["res"]),
         "not_converged": sorted(failed),
         "mixed": {"value": round(mixed_value, 3), "unit": "solves/s", "dtype": "f32 preconditioner / f64 outer",
-                  "ms_per_step": round(1e3 * mx["seconds"] / args.steps, 3), "p50_ms": pct(mx["lat"], 50),
+                  "ms_per_step": round(1e3 * mx["seconds"] / steps, 3), "p50_ms": pct(mx["lat"], 50),
                   "p99_ms": pct(mx["lat"], 99), "iters": sorted(set(mx["iters"])),
                   "max_rel_res": max(mx["res"]), "speedup_vs_fp64": round(mixed_value / value, 3)},
         "batched": batched or None,
         "multi_rhs": multi_rhs or None,
+        "err_vs_oracle": errs,
         "roofline": roofline,
-        "kernel_classes": classes,
+        "roofline_classes": classes,
         "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_setup, 2)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_config1(args):
+    """The 2D 32x32 grid with four full fracture lines (K_par = kappa = 1e4,
+    aperture 1e-4), FP64 and mixed: solves/s over 200 solves each, and the
+    error against the oracle's solution."""
+    import torch
+    import synth
+    from oracle import assembly as oa, solve as osv
+    from paper_2206_03203_amd import _lib as L
+    from paper_2206_03203_amd import tpfa
+
+    stream = torch.cuda.current_stream()
+    sc = synth.grid_2d_four_lines(32)
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    ref, _, _ = osv.solve(Ao, bo, po, osv.SolveOptions())
+    bt = torch.tensor(b, dtype=torch.float64, device="cuda:0")
+    out = {"workload": "2d-32x32-four-lines", "unknowns": A.shape[0], "nnz": A.nnz, "oracle_iters": ref.iters}
+    for prec, pv in (("fp64", L.MDP_FP64), ("mixed", L.MDP_MIXED)):
+        h = L.mdp_setup(A, part, L.mdp_options_default(precision=pv), stream)
+        x = torch.zeros_like(bt)
+        for _ in range(10):
+            L.mdp_solve(h, bt, x, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            rc, st = L.mdp_solve(h, bt, x, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xh = x.cpu().numpy()
+        out[prec] = {"value": round(200 / dt, 2), "unit": "solves/s", "iters": st[0]["iters"],
+                     "rel_res": st[0]["rel_res_true"],
+                     "err_vs_oracle": float(np.linalg.norm(xh - ref.x) / np.linalg.norm(ref.x))}
+        L.mdp_destroy(h)
+    log(f"[bench] config1: {out}")
+    return out
 
 
 def roofline_pass(fn, kernel_class, what, seconds_plain, exact=None):
@@ -336,10 +437,19 @@ def roofline_pass(fn, kernel_class, what, seconds_plain, exact=None):
                 "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1)),
                 "timed_region": f"{what} with per-launch HIP events "
                                 f"({t_ev:.3f}s with events vs {seconds_plain:.3f}s without)"}
-    classes = {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                   "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
-                   if v["ms"] > 0 and (exact is None or c in exact) else None}
-               for c, v in kt.items()}
+    # every class against the same peak: the classes that are one kernel symbol,
+    # and vcycle_other / other, which gather several kernels (their figure is
+    # the class's bytes over its summed launch time)
+    dom = max(kt, key=lambda c: kt[c]["ms"])
+    classes = {}
+    for c, v in kt.items():
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 and (exact is None or c in exact) else None
+        classes[c] = {"ms": round(v["ms"], 3), "launches": v["launches"],
+                      "avg_launch_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
+                      "GB/s": round(gbs, 1) if gbs is not None else None,
+                      "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs is not None else None,
+                      "kernels": "one symbol" if c in ktimer.SINGLE_KERNEL else "several"}
+    classes["largest_by_time"] = dom
     return roofline, classes
 
 
@@ -421,8 +531,9 @@ def _destroy_pool(pool):
             L.mdp_destroy(h)
 
 
-def mode_batch(args):
-    """Uneven 2D batch with several right-hand sides per system."""
+def mode_batch(args, seq_steps=None):
+    """Uneven 2D batch with several right-hand sides per system; returns the
+    JSON object."""
     import torch
     import synth
     from paper_2206_03203_amd import _lib as L
@@ -464,9 +575,10 @@ def mode_batch(args):
     log(f"[bench] batch: {len(pool)} systems, {pairs} pairs, {unknowns} unknowns in all")
     t_batch, st_b = timed(batch, args.steps, args.warmup)
     log(f"[bench] batch: {1e3 * t_batch:.1f} ms per batch")
-    t_seq, st_s = timed(lambda: seq("mixed"), max(1, args.steps // 2), 1)
+    ns = seq_steps or max(1, args.steps // 2)
+    t_seq, st_s = timed(lambda: seq("mixed"), ns, 1)
     log(f"[bench] sequential mixed: {1e3 * t_seq:.1f} ms per batch")
-    t_seq64, st_64 = timed(lambda: seq("fp64"), max(1, args.steps // 2), 1)
+    t_seq64, st_64 = timed(lambda: seq("fp64"), ns, 1)
     log(f"[bench] sequential fp64: {1e3 * t_seq64:.1f} ms per batch")
     # In a batch the sparse products skip the rows of pairs that have stopped,
     # so only the Arnoldi classes (corrected per pair by the library) have
@@ -476,7 +588,7 @@ def mode_batch(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
+        cpu, _ = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
     _destroy_pool(pool)
     its_b = [s["iters"] for s in st_b]
     its_s = [s["iters"] for s in st_s]
@@ -499,15 +611,16 @@ def mode_batch(args):
                             "iters_mean": round(float(np.mean([s["iters"] for s in st_64])), 2)},
         "speedup_vs_sequential_fp64": round(t_seq64 / t_batch, 3),
         "speedup_vs_sequential_mixed": round(t_seq / t_batch, 3),
-        "roofline": roofline, "kernel_classes": classes,
+        "roofline": roofline, "roofline_classes": classes,
         "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_set, 2)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def mode_serve(args):
-    """Open-loop Poisson arrivals over a pool of resident systems."""
+    """Open-loop Poisson arrivals over a pool of resident systems; returns
+    the JSON object."""
     import torch
     import synth
     from paper_2206_03203_amd import _lib as L
@@ -595,7 +708,7 @@ def mode_serve(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
+        cpu, _ = cpu_full_solves(args, [(p["sc"], p["fs"][0]) for p in pool], "first right-hand side")
     _destroy_pool(pool)
     line = {
         "metric": "served solves/s to 1e-8 rel residual with p50/p99 latency (mixed precision)",
@@ -616,17 +729,18 @@ def mode_serve(args):
         "setup_s": {"assembly": round(t_asm, 2), "host_setup_and_upload": round(t_set, 2)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def cpu_full_solves(args, items, which):
     """The FP64 oracle on this host, one core: full solves of the listed
     (scenario, source) items in order, each set up untimed, until
-    ``cpu_seconds`` of solve time has been spent; returns solves/s."""
+    ``cpu_seconds`` of solve time has been spent.  Returns the baseline
+    object (solves/s) and the (name, solution, iterations) of each solve."""
     from oracle import assembly as oa, solve as osv
     from threadpoolctl import threadpool_limits
 
-    spent, done, names = 0.0, 0, []
+    spent, done, names, sols = 0.0, 0, [], []
     for sc, f in items:
         A, b, part = oa.assemble(sc.with_source(f))
         M = osv.setup(A, part)
@@ -636,6 +750,7 @@ def cpu_full_solves(args, items, which):
             spent += time.perf_counter() - t0
         done += 1
         names.append(f"{sc.name}({A.shape[0]})")
+        sols.append((sc.name, res.x, res.iters))
         log(f"[bench] cpu oracle: {sc.name} solved in {res.iters} iterations; {spent:.1f}s so far")
         if spent >= args.cpu_seconds:
             break
@@ -643,7 +758,7 @@ def cpu_full_solves(args, items, which):
     return {"value": round(done / spent, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"FP64 oracle, full solves of the first {done} systems ({which}): "
                       f"{shown}; {spent:.1f}s of solve time, setup not timed",
-            "host_cpu_count": os.cpu_count()}
+            "host_cpu_count": os.cpu_count()}, sols
 
 
 if __name__ == "__main__":
