@@ -81,6 +81,8 @@ def parse():
                    help="rounds over the systems with four right-hand sides each (0 = skip)")
     p.add_argument("--systems", type=int, default=256, help="batch mode: number of 2D systems")
     p.add_argument("--rhs", type=int, default=4, help="batch mode: right-hand sides per system")
+    p.add_argument("--side-range", type=int, nargs=2, default=[64, 512],
+                   help="batch mode: range of the 2D systems' side")
     p.add_argument("--pool", type=int, default=64, help="serve mode: resident systems (half 2D, half 3D)")
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per arrival rate")
     p.add_argument("--slots", type=int, default=4, help="serve mode: server slots")
@@ -539,10 +541,10 @@ def mode_batch(args, seq_steps=None):
     from paper_2206_03203_amd import _lib as L
 
     stream = torch.cuda.current_stream()
-    scs = [synth.random_2d(s) for s in range(args.systems)]
+    scs = [synth.random_2d(s, n_range=tuple(args.side_range)) for s in range(args.systems)]
     srcs = [[synth.host_sources(sc, 4 * s + k) for k in range(args.rhs)] for s, sc in enumerate(scs)]
-    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch",
-                                     L.MDP_NO_AUTOTUNE if args.no_autotune else 0, args.restart)
+    fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
+    pool, t_asm, t_set = _setup_pool(scs, srcs, ("mixed", "fp64"), stream, "batch", fl, args.restart)
     pairs = sum(p["b"].shape[0] for p in pool)
     unknowns = sum(p["n"] * p["b"].shape[0] for p in pool)
     xs = [torch.zeros_like(p["b"]) for p in pool]
@@ -601,8 +603,8 @@ def mode_batch(args, seq_steps=None):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
         "config": {"workload": f"2d-uneven-batch-{args.systems}x{args.rhs}", "systems": len(pool),
-                   "pairs": pairs, "unknowns_total": unknowns,
-                   "side_range": [64, 512], "segments_max": 20, "rtol": 1e-8, "restart": args.restart},
+                   "pairs": pairs, "unknowns_total": unknowns, "side_range": list(args.side_range),
+                   "segments_max": 20, "rtol": 1e-8, "restart": args.restart, "graphs": args.graphs},
         "iters_mean": round(float(np.mean(its_b)), 2), "iters_max": int(max(its_b)),
         "max_rel_res": max(s["rel_res_true"] for s in st_b),
         "sequential_mixed": {"value": round(pairs / t_seq, 2), "unit": "solves/s",

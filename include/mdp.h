@@ -57,13 +57,15 @@ extern "C" {
 #define MDP_HOST_ONLY 2u   /* mdp_setup: build the hierarchy on the host only
                               (no device upload); for inspection on machines
                               without a GPU.  Solve calls then return EINVAL. */
-#define MDP_GRAPHS 8u      /* mdp_solve: replay each Arnoldi step from a HIP graph
-                              captured on first use instead of launching its
-                              kernels one by one (single-system solves; never
-                              while kernel timers run).  Same kernels and
-                              results.  Measured on small, launch-bound systems
-                              (4k-70k unknowns): 5-20% less time per iteration;
-                              on 100^3 systems: about 2% more. */
+#define MDP_GRAPHS 8u      /* mdp_solve, mdp_solve_batch: replay each Arnoldi
+                              step from a HIP graph captured on first use
+                              instead of launching its kernels one by one
+                              (never while kernel timers run; a solve handed
+                              the legacy stream runs on a stream of its own).
+                              Same kernels and results.  Measured on small,
+                              launch-bound systems (4k-70k unknowns): 5-20%
+                              less time per iteration; on 100^3 systems: about
+                              2% more. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,
@@ -211,7 +213,8 @@ int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
 /* Solve several independent systems together: system s has nrhs[s]
  * right-hand sides in b_dev[s] / x_dev[s] (column-major, leading dimension
  * its own n).  All handles must share precision, block form, V-cycles,
- * restart, max_iter, rtol and MDP_USE_X0 (EINVAL otherwise).  The pairs
+ * sweep counts, restart, max_iter, rtol, MDP_USE_X0 and MDP_GRAPHS (EINVAL
+ * otherwise).  The pairs
  * (system, rhs) are concatenated block-diagonally and every sparse product
  * runs once for all of them; each pair has its own Krylov process (per-pair
  * reductions never mix pairs), so its iterates are those of a solve of its

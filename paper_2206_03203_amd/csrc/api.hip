@@ -397,7 +397,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
         si.opt.pre_sweeps != s0.opt.pre_sweeps || si.opt.post_sweeps != s0.opt.post_sweeps ||
         si.opt.restart != s0.opt.restart || si.opt.max_iter != s0.opt.max_iter || si.opt.rtol != s0.opt.rtol ||
         si.opt.block_form != s0.opt.block_form ||
-        (si.opt.flags & MDP_USE_X0) != (s0.opt.flags & MDP_USE_X0)) {  // graphs are not used in batches
+        (si.opt.flags & (MDP_USE_X0 | MDP_GRAPHS)) != (s0.opt.flags & (MDP_USE_X0 | MDP_GRAPHS))) {
       set_last_error("all handles of a batch need the same solve options");
       return MDP_EINVAL;
     }

@@ -955,6 +955,7 @@ struct Problem {
   const Layout *L;
   Workspace *ws;
   const mdp_options *opt;
+  StepGraphs *graphs;  // where this solve keeps its step graphs (MDP_GRAPHS)
 };
 
 // Per-pair norms of v (device) into ws.host_norms (synchronises s).
@@ -1006,11 +1007,16 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     beta = bnorm;
   }
 
-  // With MDP_GRAPHS, single-system solves replay each step from a captured
-  // graph (not on the legacy stream, which cannot be captured, and not while
-  // timers run).
-  bool use_graphs = np == 1 && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed && s != nullptr;
-  if (use_graphs && ws.gexec.size() != static_cast<size_t>(2 * (m + 1))) ws.gexec.assign(2 * (m + 1), nullptr);
+  // With MDP_GRAPHS, each step is replayed from a graph captured on its first
+  // use (not on the legacy stream, which cannot be captured, and not while
+  // timers run).  Graphs captured with another workspace are dropped.
+  StepGraphs *sg = pb.graphs;
+  bool use_graphs = sg && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !sg->failed && s != nullptr;
+  if (use_graphs && (sg->ws != &ws || sg->exec.size() != static_cast<size_t>(2 * (m + 1)))) {
+    sg->clear();
+    sg->exec.assign(2 * (m + 1), nullptr);
+    sg->ws = &ws;
+  }
   while (true) {
     int nactive = 0, kmax_all = 0;
     for (int p = 0; p < np; ++p) {
@@ -1119,9 +1125,9 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
       ++counted;
       const int zcol = std::min(j, kmax_all - 1);
       if (use_graphs) {
-        hipGraphExec_t &ge = ws.gexec[(zcol == j ? 0 : m + 1) + j];
+        hipGraphExec_t &ge = sg->exec[(zcol == j ? 0 : m + 1) + j];
         if (!ge && !capture_step(ge, s, [&] { enqueue_step(j, zcol); })) {
-          ws.graphs_failed = true;
+          sg->failed = true;
           use_graphs = false;
         }
         if (ge) MDP_HIP(hipGraphLaunch(ge, s));
@@ -1262,6 +1268,14 @@ void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t
   MDP_HIP(hipStreamSynchronize(s));
 }
 
+void StepGraphs::clear() {
+  for (hipGraphExec_t g : exec)
+    if (g) (void)hipGraphExecDestroy(g);
+  exec.clear();
+  ws = nullptr;
+  failed = false;
+}
+
 hipStream_t Workspace::own_stream() {
   if (!own) {
     MDP_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
@@ -1271,10 +1285,7 @@ hipStream_t Workspace::own_stream() {
 }
 
 void Workspace::release() {
-  for (hipGraphExec_t g : gexec)
-    if (g) (void)hipGraphExecDestroy(g);
-  gexec.clear();
-  graphs_failed = false;
+  graphs.clear();
   if (handoff) (void)hipEventDestroy(handoff);
   if (own) (void)hipStreamDestroy(own);
   handoff = nullptr;
@@ -1353,7 +1364,7 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   // The legacy stream cannot be captured: a solve handed it runs on the
   // workspace's own stream, after the caller's earlier work on s.
   const hipStream_t caller = s;
-  if (s == nullptr && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs_failed) {
+  if (s == nullptr && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !ws.graphs.failed) {
     s = ws.own_stream();
     MDP_HIP(hipEventRecord(ws.handoff, caller));
     MDP_HIP(hipStreamWaitEvent(s, ws.handoff, 0));
@@ -1373,10 +1384,10 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   mdp_stats out{};
   int rc;
   if (opt.precision == MDP_MIXED) {
-    Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt};
+    Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt, &ws.graphs};
     rc = fgmres<float>(pb, bp, xp, use_x0, s, &out);
   } else {
-    Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt};
+    Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt, &ws.graphs};
     rc = fgmres<double>(pb, bp, xp, use_x0, s, &out);
   }
   if (!host.identity)
@@ -1563,6 +1574,14 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   if (!W.allocated() || W.ld < n || W.npairs < npairs || W.ntiles < layout.ntiles || W.m != opt.restart ||
       !W.bp.get())
     raise(MDP_EINVAL, "batch workspace missing or too small");
+  // As for single solves: graph replay cannot capture the legacy stream, so
+  // the batch then runs on the workspace's own stream after the caller's work.
+  const hipStream_t caller = s;
+  if (s == nullptr && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !graphs.failed) {
+    s = W.own_stream();
+    MDP_HIP(hipEventRecord(W.handoff, caller));
+    MDP_HIP(hipStreamWaitEvent(s, W.handoff, 0));
+  }
   std::vector<const double *> bptr(static_cast<size_t>(npairs));
   std::vector<double *> xptr(static_cast<size_t>(npairs));
   for (int q = 0; q < npairs; ++q) {  // internal order
@@ -1582,10 +1601,10 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   int rc;
   std::vector<mdp_stats> sti(st ? static_cast<size_t>(npairs) : 0);  // internal order
   if (opt.precision == MDP_MIXED) {
-    Problem<float> pb{&A, pc32.get(), &layout, &W, &opt};
+    Problem<float> pb{&A, pc32.get(), &layout, &W, &opt, &graphs};
     rc = fgmres<float>(pb, bg, xg, use_x0, s, st ? sti.data() : nullptr);
   } else {
-    Problem<double> pb{&A, pc64.get(), &layout, &W, &opt};
+    Problem<double> pb{&A, pc64.get(), &layout, &W, &opt, &graphs};
     rc = fgmres<double>(pb, bg, xg, use_x0, s, st ? sti.data() : nullptr);
   }
   hipLaunchKernelGGL(scatter_pairs_kernel, dim3(g), dim3(kThreads), 0, s, static_cast<int64_t>(n),

@@ -116,6 +116,19 @@ struct Layout {
              hipStream_t s);
 };
 
+// Arnoldi steps replayed from captured HIP graphs (MDP_GRAPHS): exec[j] for
+// step j, exec[m + 1 + j] for a cycle's last step j (which reuses the
+// preconditioned column j - 1).  A graph holds the addresses of the
+// workspace and of the solve's matrices, so it is valid for the workspace
+// `ws` it was captured with and for the life of its owner.
+struct StepGraphs {
+  std::vector<hipGraphExec_t> exec;
+  const void *ws = nullptr;
+  bool failed = false;  // capture or instantiation failed once: launch directly
+  void clear();
+  ~StepGraphs() { clear(); }
+};
+
 struct Workspace {
   int64_t ld = 0;  // leading dimension of V / Z columns
   int m = 0;       // restart length
@@ -132,11 +145,7 @@ struct Workspace {
   GmresState *host_state = nullptr;  // pinned, npairs
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
-  // With MDP_GRAPHS, single-system solves replay each Arnoldi step from a captured graph:
-  // gexec[j] for step j, gexec[m + 1 + j] for a cycle's last step j (which
-  // reuses preconditioned column j - 1).  Valid while the workspace lives.
-  std::vector<hipGraphExec_t> gexec;
-  bool graphs_failed = false;      // capture or instantiation failed once: launch directly
+  StepGraphs graphs;               // single-system solves on this workspace (MDP_GRAPHS)
   hipStream_t own = nullptr;       // non-blocking stream for solves handed the legacy stream
   hipEvent_t handoff = nullptr;
   hipStream_t own_stream();        // created on first use
@@ -195,6 +204,7 @@ struct Batch {
   Layout layout;
   Workspace ws;              // own workspace (left empty when `wsp` is set)
   Workspace *wsp = nullptr;  // shared workspace of at least this batch's sizes
+  StepGraphs graphs;         // this batch's Arnoldi steps (MDP_GRAPHS)
   // alloc_ws = false: leave the workspace to the caller (set wsp before solve)
   void build(const std::vector<const Solver *> &pairs, hipStream_t s, bool alloc_ws = true);
   int solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st);
