@@ -89,9 +89,12 @@ def parse():
     p.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: workspace memory budget")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="solve time after which the CPU oracle sample stops taking further systems")
-    p.add_argument("--sections", default="config1,cube160,batch,serve",
-                   help="default mode: further workloads on the JSON line (comma list of config1, cube160, "
-                        "batch, serve; empty = the headline only)")
+    p.add_argument("--sections", default="config1,flux,cube160,batch,serve",
+                   help="default mode: further workloads on the JSON line (comma list of config1, flux, "
+                        "cube160, batch, serve; empty = the headline only)")
+    p.add_argument("--formulation", choices=["pressure", "flux"], default="pressure",
+                   help="cube workload: host/fracture pressures (Gamma = fracture cells), or the paper's own "
+                        "reading with explicit intersections and interface fluxes as Gamma")
     p.add_argument("--tune-file", default=None,
                    help="record the autotuner's format choices here and reuse the ones recorded (mdp_tune_file)")
     return p.parse_args()
@@ -133,6 +136,13 @@ def main():
     sections = [x for x in args.sections.split(",") if x]
     if "config1" in sections:
         line["config1"] = run_config1(args)
+    if "flux" in sections and args.formulation == "pressure":
+        c = run_cube(args, args.n, 8, 4, headline=False, formulation="flux")
+        line["flux"] = {k: c[k] for k in ("value", "unit", "ms_per_step", "p50_ms", "p99_ms", "iters",
+                                          "max_rel_res", "mixed", "roofline", "config", "setup_s")}
+        line["flux"]["what"] = ("the same four systems in the paper's own block reading: Omega = pressures of "
+                                "host, fracture, intersection-line and point cells, Gamma = interface fluxes; "
+                                "value = FP64 solves/s, mixed beside it")
     if "cube160" in sections and args.n != 160:
         c = run_cube(args, 160, 8, 4, headline=False)
         line["cube160"] = {k: c[k] for k in ("value", "unit", "ms_per_step", "p50_ms", "p99_ms", "iters",
@@ -162,7 +172,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_cube(args, n, steps, warmup, headline):
+def run_cube(args, n, steps, warmup, headline, formulation=None):
     """The 3D cube workload at n^3: the four (K_par, kappa) systems set up in
     both precisions, timed FP64 and mixed passes of `steps` solves in
     rotation, a roofline pass, and (headline only) the batched and
@@ -171,17 +181,22 @@ def run_cube(args, n, steps, warmup, headline):
     import torch
     import synth
     from paper_2206_03203_amd import _lib as L
-    from paper_2206_03203_amd import tpfa
+    from paper_2206_03203_amd import tpfa, tpfa_flux
 
+    formulation = formulation or args.formulation
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     systems = []
+    info = None
     t_asm = t_setup = 0.0
     for seed in range(args.seeds if headline else 1):
         for kp, ka in PAIRS:
             sc = synth.regular_3d(n=n, k_par=kp, kappa=ka, seed=seed)
             t0 = time.perf_counter()
-            A, b, part = tpfa.assemble(sc)
+            if formulation == "flux":
+                A, b, part, info = tpfa_flux.assemble_flux(sc)
+            else:
+                A, b, part = tpfa.assemble(sc)
             t1 = time.perf_counter()
             fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
@@ -263,7 +278,7 @@ def run_cube(args, n, steps, warmup, headline):
     # the columns four at a time with each matrix read once for all four,
     # against the same columns solved one at a time.
     multi_rhs = {}
-    if headline and args.block == "lower" and args.multi_rhs:
+    if headline and args.block == "lower" and args.multi_rhs and formulation == "pressure":
         for s in systems:
             fs = [None] + [synth.host_sources(s["sc"], 100 + k) for k in range(3)]
             _, B, _ = tpfa.assemble(s["sc"], sources=fs)
@@ -310,13 +325,13 @@ def run_cube(args, n, steps, warmup, headline):
     roofline, classes = roofline_pass(lambda: run("fp64", steps), args.kernel_class,
                                       f"the {steps} FP64 steps repeated", fp["seconds"])
     if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
-            args.max_coarse == 400 and args.restart == 64:
+            args.max_coarse == 400 and args.restart == 64 and formulation == "pressure":
         roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}")
 
     # Each system's solution in both precisions against the oracle's solution
     # of the same system (the oracle solves are the CPU baseline's).
     cpu, errs = None, None
-    if headline and not args.no_cpu_baseline:
+    if headline and not args.no_cpu_baseline and formulation == "pressure":
         items = [(synth.regular_3d(n=n, k_par=kp, kappa=ka, seed=0), None) for kp, ka in PAIRS]
         cpu, xo = cpu_full_solves(args, items, "seed 0")
         errs = []
@@ -350,7 +365,9 @@ def run_cube(args, n, steps, warmup, headline):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3d-unit-cube-{n}^3-9-planes-lognormal-host",
+        "config": {"workload": f"3d-unit-cube-{n}^3-9-planes-lognormal-host" +
+                               ("-interface-fluxes" if formulation == "flux" else ""),
+                   "formulation": formulation, "unknown_kinds": info,
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
                    "amg_max_coarse": args.max_coarse, "restart": args.restart,

@@ -39,7 +39,8 @@ extern "C" {
 #define MDP_NOT_CONVERGED 1 /* iteration budget spent; x holds the last iterate */
 #define MDP_PENDING 2       /* mdp_poll: request not finished yet              */
 #define MDP_EINVAL (-1)     /* bad argument, malformed CSR, part not in {0,1}   */
-#define MDP_ENONPOS_DIAG (-2) /* a diagonal entry <= 0 (the smoother divides)  */
+#define MDP_ENONPOS_DIAG (-2) /* a diagonal entry of A_GG or S~ <= 0 (eq. (7) and
+                                 the smoothers divide by them)                  */
 #define MDP_ESINGULAR (-3)  /* coarsest dense factorisation failed             */
 #define MDP_ENAN (-4)       /* NaN/Inf in the input or during the iteration    */
 #define MDP_ENOMEM (-5)     /* device allocation failed / budget exceeded       */
@@ -143,8 +144,13 @@ typedef struct {
  * (NULL). */
 int mdp_options_default(mdp_options *opt);
 
-/* Build the solver for A (eq. 4).  part[i] = 0 marks a host-domain (Omega)
- * unknown, 1 a fracture/interface (Gamma) unknown.  Setup (host C++):
+/* Build the solver for A (eq. 4).  part[i] = 0 marks an Omega unknown, 1 a
+ * Gamma unknown.  Two readings of Section 3.1 are served the same way:
+ * Omega = host-cell pressures and Gamma = fracture-cell pressures (the
+ * primal pressure system), or Omega = the pressures of every subdomain
+ * (host, fractures, intersection lines and points) and Gamma = the interface
+ * fluxes of eq. (2) (the paper's own reading; A_GG is then diagonal and
+ * A_GO = -A_OG^T).  Setup (host C++):
  * stable [Omega; Gamma] permutation, the four blocks, S~ of eq. (7) with
  * diag(A_GG), SA-AMG hierarchies on S~ and A_GG (Section 3.3), dense inverse
  * of each coarsest level, then one upload to the device on hip_stream, where

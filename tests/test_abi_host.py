@@ -62,14 +62,28 @@ SCEN = [
 ]
 
 
+def _flux(assemble):
+    def f(sc):
+        out = assemble(sc)
+        return out[0], out[1], out[2]
+    return f
+
+
+@pytest.mark.parametrize("form", ["pressure", "flux"])
 @pytest.mark.parametrize("make", SCEN)
-def test_host_hierarchy_matches_oracle(make):
+def test_host_hierarchy_matches_oracle(make, form):
+    """Both block readings: the primal pressure system, and the paper's
+    own with interface fluxes as Gamma (oracle/mixed_dim.py)."""
+    from oracle import mixed_dim as md
+    from paper_2206_03203_amd import tpfa_flux
     sc = make()
-    A, b, part = tpfa.assemble(sc)
+    lib_asm, ora_asm = (tpfa.assemble, oa.assemble) if form == "pressure" else \
+        (_flux(tpfa_flux.assemble_flux), _flux(md.assemble_flux))
+    A, b, part = lib_asm(sc)
     opts = amg.AMGOptions(max_coarse=40)
     h = _host_handle(A, part, max_coarse=40)
     try:
-        Ao, bo, po = oa.assemble(sc)
+        Ao, bo, po = ora_asm(sc)
         _, _, Aoo, Aog, Ago, Agg = ob.split(Ao, po)
         S = ob.approx_schur(Aoo, Aog, Ago, Agg)
         info = L.mdp_info(h)
