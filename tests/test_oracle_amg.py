@@ -266,3 +266,90 @@ def test_cycles_closed_form(cycles, dense):
     expect = (np.eye(n) - np.linalg.matrix_power(E, cycles)) @ np.linalg.solve(A, b)
     x = amg.apply_cycles(H, b, cycles)
     assert np.allclose(x, expect, rtol=0, atol=1e-10 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("make,expect", [
+    (lambda: _chain(7), [0, 1, 0, 1, 0, 1, 0]),
+    (_pass2_graph, [0, 1, 0, 0, 1, 2]),  # edges 0-1, 1-2, 2-5, 3-4, 4-5, worked by hand in natural order
+    (lambda: _grid(4), [(i + j) % 2 for j in range(4) for i in range(4)]),  # red-black
+])
+def test_greedy_colours_by_hand(make, expect):
+    assert np.array_equal(amg.greedy_colours(make()), expect)
+
+
+def _gs_dense(A, colour):
+    """Forward / backward multicolour Gauss-Seidel as dense triangular
+    operators in the (colour, index) order: x -> (D+L)^-1 (b - U x) and
+    x -> (D+U)^-1 (b - L x), mapped back to the natural order."""
+    import scipy.linalg as la
+    n = A.shape[0]
+    P = np.lexsort((np.arange(n), colour))  # rows sorted by colour, then index
+    Ap = A[np.ix_(P, P)]
+    Lo, Up = np.tril(Ap), np.triu(Ap)
+
+    def fwd(b, x):
+        y = la.solve_triangular(Lo, b[P] - np.triu(Ap, 1) @ x[P], lower=True)
+        out = np.empty(n)
+        out[P] = y
+        return out
+
+    def bwd(b, x):
+        y = la.solve_triangular(Up, b[P] - np.tril(Ap, -1) @ x[P], lower=False)
+        out = np.empty(n)
+        out[P] = y
+        return out
+    return fwd, bwd
+
+
+@pytest.mark.parametrize("make", [lambda: _system_blocks(synth.tiny_3d(6, seed=2))[0],
+                                  lambda: _system_blocks(synth.random_2d(3, n_range=(12, 16)))[0]])
+def test_multicolour_sweep_is_gauss_seidel_in_colour_order(make):
+    """A valid colouring (no two coupled nodes share a colour); one forward
+    and one backward sweep equal the dense triangular solves of
+    Gauss-Seidel in the (colour, index) order."""
+    S = sp.csr_matrix(make())
+    col = amg.greedy_colours(S)
+    G = (abs(S) + abs(S.T)).tocoo()
+    assert all(col[i] != col[j] for i, j in zip(G.row, G.col) if i != j)
+    A = S.toarray()
+    fwd, bwd = _gs_dense(A, col)
+    b = synth.random_vector(S.shape[0], 12)
+    x0 = synth.random_vector(S.shape[0], 13)
+    scale = np.abs(fwd(b, x0)).max()
+    assert np.allclose(amg.gs_sweep(S, b, x0, col, True), fwd(b, x0), rtol=0, atol=1e-12 * scale)
+    assert np.allclose(amg.gs_sweep(S, b, x0, col, False), bwd(b, x0), rtol=0, atol=1e-12 * scale)
+
+
+def _gs_recursion_operator(H, lvl, pre, post):
+    lv = H.levels[lvl]
+    A = lv.A.toarray()
+    n = A.shape[0]
+    I = np.eye(n)
+    Ainv = np.linalg.inv(A)
+    if lvl == len(H.levels) - 1:
+        return Ainv  # dense coarsest
+    fwd, bwd = _gs_dense(A, lv.colour)
+    # smoothing matrices I - M A with M the sweep's operator on b from x = 0
+    Mf = np.column_stack([fwd(e, np.zeros(n)) for e in I])
+    Mb = np.column_stack([bwd(e, np.zeros(n)) for e in I])
+    Sf, Sb = I - Mf @ A, I - Mb @ A
+    Bc = _gs_recursion_operator(H, lvl + 1, pre, post)
+    P, R = lv.P.toarray(), lv.R.toarray()
+    E = np.linalg.matrix_power(Sb, post) @ (I - P @ Bc @ R @ A) @ np.linalg.matrix_power(Sf, pre)
+    return (I - E) @ Ainv
+
+
+@pytest.mark.parametrize("pre,post", [(1, 1), (2, 1), (1, 2)])
+def test_gauss_seidel_vcycle_equals_recursion_and_is_symmetric(pre, post):
+    """With multicolour Gauss-Seidel (forward before, backward after) the
+    V-cycle applies the textbook recursion's operator; with equal sweep
+    counts it is symmetric, as the forward and backward sweeps are adjoint."""
+    S, _ = _system_blocks(synth.tiny_3d(6, seed=2))
+    n = S.shape[0]
+    H = amg.setup(S, amg.AMGOptions(max_coarse=10, smoother="gs", pre_sweeps=pre, post_sweeps=post))
+    assert len(H.levels) >= 3 and H.coarse_dense is not None
+    B = _gs_recursion_operator(H, 0, pre, post)
+    V = _operator(H, n)
+    assert np.allclose(V, B, rtol=0, atol=1e-10 * np.abs(B).max())
+    if pre == post:
+        assert np.allclose(V, V.T, rtol=0, atol=1e-10 * np.abs(V).max())
