@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--mode", choices=["solve", "batch", "serve"], default="solve")
     p.add_argument("--block", choices=["lower", "diag", "upper"], default="lower",
                    help="block preconditioner: M_L (eq. 8, the paper's), or the inexact B_D / B_U of Section 3.2")
+    p.add_argument("--smoother", choices=["l1jacobi", "gs"], default="l1jacobi",
+                   help="V-cycle smoother: l1-Jacobi, or multicolour Gauss-Seidel (the paper's smoothing, Section 4)")
     p.add_argument("--graphs", action="store_true",
                    help="replay each Arnoldi step from a captured HIP graph instead of launching its kernels")
     p.add_argument("--no-autotune", action="store_true",
@@ -200,10 +202,11 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
             t1 = time.perf_counter()
             fl = (L.MDP_NO_AUTOTUNE if args.no_autotune else 0) | (L.MDP_GRAPHS if args.graphs else 0)
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
+            sm = L.MDP_SMOOTH_GS if args.smoother == "gs" else L.MDP_SMOOTH_L1JACOBI
             o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse, restart=args.restart)
+                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
             o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse, restart=args.restart)
+                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
             hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
@@ -325,7 +328,7 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
     roofline, classes = roofline_pass(lambda: run("fp64", steps), args.kernel_class,
                                       f"the {steps} FP64 steps repeated", fp["seconds"])
     if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
-            args.max_coarse == 400 and args.restart == 64 and formulation == "pressure":
+            args.max_coarse == 400 and args.restart == 64 and formulation == "pressure" and args.smoother == "l1jacobi":
         roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}")
 
     # Each system's solution in both precisions against the oracle's solution
@@ -371,7 +374,7 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
                    "amg_max_coarse": args.max_coarse, "restart": args.restart,
-                   "autotune": not args.no_autotune, "graphs": args.graphs,
+                   "autotune": not args.no_autotune, "graphs": args.graphs, "smoother": args.smoother,
                    "block_preconditioner": args.block},
         "p50_ms": pct(fp["lat"], 50),
         "p99_ms": pct(fp["lat"], 99),

@@ -87,6 +87,15 @@ extern "C" {
 #define MDP_BLOCK_DIAG 1  /* M_D: Q_OO and Q_GG on their blocks, independently     */
 #define MDP_BLOCK_UPPER 2 /* M_U: Q_GG, then r_O - A_OG z_G, then Q_OO             */
 
+/* ---- smoother of the V-cycles (options.smoother) --------------------------- */
+#define MDP_SMOOTH_L1JACOBI 0 /* l1-Jacobi, d_i = sum_j |a_ij| (default)             */
+#define MDP_SMOOTH_GS 1       /* multicolour Gauss-Seidel, the smoothing of Section 4:
+                                 greedy natural-order colouring of every level;
+                                 forward sweeps (colours ascending) before the
+                                 coarse correction, backward sweeps after; one
+                                 launch per colour.  The swept coarsest level
+                                 keeps l1-Jacobi. */
+
 /* ---- operators for mdp_apply ---------------------------------------------- */
 #define MDP_OP_A 0    /* y = A x, the full system matrix (FP64)                     */
 #define MDP_OP_ML 1   /* y = M x, one application of the handle's block preconditioner
@@ -127,6 +136,7 @@ typedef struct {
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
   uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS */
   int32_t block_form;     /* MDP_BLOCK_LOWER (default), MDP_BLOCK_DIAG, MDP_BLOCK_UPPER */
+  int32_t smoother;       /* MDP_SMOOTH_L1JACOBI (default) or MDP_SMOOTH_GS             */
 } mdp_options;
 
 typedef struct {
@@ -219,8 +229,8 @@ int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
 /* Solve several independent systems together: system s has nrhs[s]
  * right-hand sides in b_dev[s] / x_dev[s] (column-major, leading dimension
  * its own n).  All handles must share precision, block form, V-cycles,
- * sweep counts, restart, max_iter, rtol, MDP_USE_X0 and MDP_GRAPHS (EINVAL
- * otherwise).  The pairs
+ * smoother and sweep counts, restart, max_iter, rtol, MDP_USE_X0 and
+ * MDP_GRAPHS (EINVAL otherwise).  The pairs
  * (system, rhs) are concatenated block-diagonally and every sparse product
  * runs once for all of them; each pair has its own Krylov process (per-pair
  * reductions never mix pairs), so its iterates are those of a solve of its

@@ -46,6 +46,7 @@ MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP
 MDP_FP64, MDP_MIXED = 0, 1
 MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS = 1, 2, 4, 8
 MDP_BLOCK_LOWER, MDP_BLOCK_DIAG, MDP_BLOCK_UPPER = 0, 1, 2
+MDP_SMOOTH_L1JACOBI, MDP_SMOOTH_GS = 0, 1
 MDP_OP_A, MDP_OP_ML, MDP_OP_QOO, MDP_OP_QGG = 0, 1, 2, 3
 MDP_BLOCK_OMEGA, MDP_BLOCK_GAMMA = 0, 1
 MDP_MAT_A, MDP_MAT_P, MDP_MAT_R = 0, 1, 2
@@ -65,7 +66,7 @@ class mdp_options(C.Structure):
                 ("post_sweeps", C.c_int32), ("strength_theta", C.c_double), ("max_coarse", C.c_int32),
                 ("max_dense", C.c_int32), ("max_levels", C.c_int32), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("rtol", C.c_double), ("flags", C.c_uint32),
-                ("block_form", C.c_int32)]
+                ("block_form", C.c_int32), ("smoother", C.c_int32)]
 
 
 class mdp_stats(C.Structure):

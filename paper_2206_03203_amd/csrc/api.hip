@@ -114,6 +114,8 @@ int check_options(const mdp_options &o) {
   if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS)) return bad("unknown bits in flags");
   if (o.block_form != MDP_BLOCK_LOWER && o.block_form != MDP_BLOCK_DIAG && o.block_form != MDP_BLOCK_UPPER)
     return bad("block_form must be MDP_BLOCK_LOWER, MDP_BLOCK_DIAG or MDP_BLOCK_UPPER");
+  if (o.smoother != MDP_SMOOTH_L1JACOBI && o.smoother != MDP_SMOOTH_GS)
+    return bad("smoother must be MDP_SMOOTH_L1JACOBI or MDP_SMOOTH_GS");
   return MDP_OK;
 }
 
@@ -210,6 +212,7 @@ int mdp_options_default(mdp_options *o) {
   o->rtol = 1e-8;
   o->flags = 0;
   o->block_form = MDP_BLOCK_LOWER;
+  o->smoother = MDP_SMOOTH_L1JACOBI;
   return MDP_OK;
 }
 
@@ -395,6 +398,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     }
     if (si.opt.precision != s0.opt.precision || si.opt.vcycles != s0.opt.vcycles ||
         si.opt.pre_sweeps != s0.opt.pre_sweeps || si.opt.post_sweeps != s0.opt.post_sweeps ||
+        si.opt.smoother != s0.opt.smoother ||
         si.opt.restart != s0.opt.restart || si.opt.max_iter != s0.opt.max_iter || si.opt.rtol != s0.opt.rtol ||
         si.opt.block_form != s0.opt.block_form ||
         (si.opt.flags & (MDP_USE_X0 | MDP_GRAPHS)) != (s0.opt.flags & (MDP_USE_X0 | MDP_GRAPHS))) {

@@ -141,6 +141,29 @@ inline HCsr transpose(const HCsr &a) {
 // C = A * B (Gustavson row-by-row with a dense accumulator).  Each output
 // entry sums a_ik * b_kj over A's row in stored order, then B's row in stored
 // order.  Output columns sorted; entries that sum to exactly zero are dropped.
+// Greedy colouring for multicolour Gauss-Seidel: in natural order, node i
+// takes the smallest colour not used by an already coloured neighbour in the
+// pattern of a + a^T (diagonal and stored zeros excluded).  Returns the
+// colour of each node.
+inline std::vector<int32_t> greedy_colours(const HCsr &a) {
+  const HCsr t = transpose(a);
+  std::vector<int32_t> col(static_cast<size_t>(a.nr), -1);
+  std::vector<int32_t> seen;  // seen[c] == i: colour c is used by a neighbour of i
+  for (int32_t i = 0; i < a.nr; ++i) {
+    for (const HCsr *m : {&a, &t})
+      for (int32_t p = m->ptr[i]; p < m->ptr[i + 1]; ++p) {
+        const int32_t j = m->col[p];
+        if (j == i || col[j] < 0 || m->val[p] == 0.0) continue;
+        if (static_cast<size_t>(col[j]) >= seen.size()) seen.resize(static_cast<size_t>(col[j]) + 1, -1);
+        seen[col[j]] = i;
+      }
+    int32_t c = 0;
+    while (static_cast<size_t>(c) < seen.size() && seen[c] == i) ++c;
+    col[i] = c;
+  }
+  return col;
+}
+
 inline HCsr spgemm(const HCsr &a, const HCsr &b) {
   if (a.nc != b.nr) throw std::invalid_argument("spgemm shape mismatch");
   const int T = setup_workers();

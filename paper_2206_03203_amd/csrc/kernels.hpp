@@ -378,6 +378,43 @@ __global__ __launch_bounds__(kThreads) void csr_scalar_kernel(
                             blk(y2, r * bk.ys));
 }
 
+// One colour of a multicolour Gauss-Seidel sweep (Section 4's smoother in a
+// parallel order): the listed rows share a colour, so none of them reads
+// another's update, and each is relaxed in place,
+// x_i <- x_i + (b_i - sum_j a_ij x_j) / a_ii, LPR lanes per row, for KB
+// right-hand-side blocks (strides as for the sparse products).
+template <int LPR, int KB, typename TA, typename TY>
+__global__ __launch_bounds__(kThreads) void gs_colour_kernel(int nrows, const int *__restrict__ rows,
+                                                             const int *__restrict__ ptr, const int *__restrict__ col,
+                                                             const TA *__restrict__ val, const TY *__restrict__ dg,
+                                                             const TY *__restrict__ b, TY *x,
+                                                             const int *__restrict__ gate, Blocks bk) {
+  if (gate && *gate) return;
+  using Acc = typename AccumT<TA, TY>::type;
+  const int k = static_cast<int>((static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) / LPR);
+  const int lane = threadIdx.x % LPR;
+  if (k >= nrows) return;  // whole LPR groups leave together
+  const int row = rows[k];
+  const int s = ptr[row], e = ptr[row + 1];
+  Acc sum[KB];
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = 0;
+  for (int p = s + lane; p < e; p += LPR) {
+    const int c = col[p];
+    const Acc v = static_cast<Acc>(val[p]);
+#pragma unroll
+    for (int r = 0; r < KB; ++r) sum[r] += v * static_cast<Acc>(x[r * bk.xs + c]);
+  }
+#pragma unroll
+  for (int r = 0; r < KB; ++r) sum[r] = group_sum<LPR>(sum[r]);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < KB; ++r) {
+      const int64_t i = r * bk.ys + row;
+      x[i] = static_cast<TY>(static_cast<Acc>(x[i]) + static_cast<Acc>(dg[i]) * (static_cast<Acc>(b[i]) - sum[r]));
+    }
+}
+
 // Reads n 16-byte words and stores only if their sum equals the sentinel
 // (never, for a buffer of zeros and a nonzero sentinel): it evicts the caches
 // without leaving dirty lines behind.

@@ -292,13 +292,14 @@ int64_t sweep_stride(const DLevel<T> &L, int kb) {
 // pairs' rows (pair of a row in block r = r * nsys + its system).
 template <typename T>
 void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep,
-                 int pre, int post, const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
+                 int pre, int post, bool gs, const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
   const size_t L = pl.order.size();
   d.lv.clear();
   d.lv.resize(L);
   d.kb = kb;
   d.pre = pre;
   d.post = post;
+  d.gs = gs;
   std::vector<double> cinv;
   for (size_t l = 0; l < L; ++l) {
     DLevel<T> &dl = d.lv[l];
@@ -310,8 +311,8 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
     // the level restricts b with R (I - A D^-1) when every continuing system
-    // has it and the pre-smoothing is the single sweep from zero D^-1 b
-    dl.fused = dl.ncont > 0 && pre == 1;
+    // has it and the pre-smoothing is the single l1-Jacobi sweep from zero D^-1 b
+    dl.fused = dl.ncont > 0 && pre == 1 && !gs;
     for (int p : pl.order[l])
       if (l + 1 < hs[p]->lv.size() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
     for (int p : pl.order[l]) {
@@ -334,7 +335,45 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
       }
     }
     for (int r = 1; r < kb; ++r) std::copy(dinv.begin(), dinv.begin() + dl.n, dinv.begin() + r * dl.n);
-    upload_csr(concat_blocks(dl.ncont, dl.ncont, pa), dl.A, s, keep);
+    const HCsr Acat = concat_blocks(dl.ncont, dl.ncont, pa);
+    upload_csr(Acat, dl.A, s, keep);
+    if (gs && dl.ncont > 0) {
+      // each continuing system coloured on its own; a colour of the level is
+      // that colour's rows of every system, ascending
+      std::vector<std::vector<int32_t>> by_colour;
+      for (int p : pl.order[l]) {
+        if (l + 1 >= hs[p]->lv.size()) continue;
+        const std::vector<int32_t> col = greedy_colours(hs[p]->lv[l].A);
+        const int32_t o = static_cast<int32_t>(pl.off[l][p]);
+        for (size_t i = 0; i < col.size(); ++i) {
+          if (static_cast<size_t>(col[i]) >= by_colour.size()) by_colour.resize(static_cast<size_t>(col[i]) + 1);
+          by_colour[col[i]].push_back(o + static_cast<int32_t>(i));
+        }
+      }
+      std::vector<int32_t> rows;
+      dl.gs_off.assign(1, 0);
+      dl.gs_nnz.clear();
+      for (auto &c : by_colour) {
+        std::sort(c.begin(), c.end());
+        int64_t nz = 0;
+        for (int32_t r : c) nz += Acat.ptr[r + 1] - Acat.ptr[r];
+        rows.insert(rows.end(), c.begin(), c.end());
+        dl.gs_off.push_back(static_cast<int32_t>(rows.size()));
+        dl.gs_nnz.push_back(nz);
+      }
+      dl.Ag.nr = dl.Ag.nc = dl.ncont;
+      dl.Ag.nnz = Acat.nnz();
+      upload_csr_arrays(Acat, dl.Ag, s, keep);
+      upload_vec(dl.gs_rows, keep.put(std::move(rows)), s);
+      std::vector<T> dg(nfull, T(0));
+      for (int32_t i = 0; i < dl.ncont; ++i)
+        for (int32_t q = Acat.ptr[i]; q < Acat.ptr[i + 1]; ++q)
+          if (Acat.col[q] == i) dg[i] = static_cast<T>(1.0 / Acat.val[q]);
+      for (int r = 1; r < kb; ++r) std::copy(dg.begin(), dg.begin() + dl.n, dg.begin() + r * dl.n);
+      upload_vec(dl.dg, keep.put(std::move(dg)), s);
+      const double avg = static_cast<double>(Acat.nnz()) / std::max<int32_t>(dl.ncont, 1);
+      dl.gs_lpr = avg <= 12.0 ? 1 : (avg <= 96.0 ? 8 : 32);
+    }
     if (l + 1 < L) {
       upload_csr(concat_blocks(dl.ncont, pl.n[l + 1], pp), dl.P, s, keep);
       upload_csr(concat_blocks(pl.n[l + 1], dl.ncont, pr), dl.R, s, keep);
@@ -347,7 +386,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     dl.x.alloc(nb);
     dl.b.alloc(nb);
     dl.t.alloc(nb);
-    if (!dl.fused || post > 1) dl.r.alloc(nb);  // residual; sweep ping-pong
+    if (!dl.fused || post > 1 || gs) dl.r.alloc(nb);  // residual; sweep ping-pong
     if (dl.n > dl.sw_off) dl.pp.alloc(2 * sweep_stride(dl, kb) * sizeof(T));
     // block strides: x of A, P, R and Asw lives on levels l, l + 1, l and l;
     // their b / dinv / y on levels l, l, l + 1 and l
@@ -760,10 +799,65 @@ void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, Gate gate, hipStr
   }
 }
 
+// One multicolour Gauss-Seidel sweep on level L (forward: colours ascending).
+template <int LPR, int KB, typename T>
+void gs_launch(DLevel<T> &L, int c, const T *b, T *x, Gate gate, hipStream_t s, int kind) {
+  const int nrows = L.gs_off[c + 1] - L.gs_off[c];
+  if (nrows == 0) return;
+  const int64_t threads = static_cast<int64_t>(nrows) * LPR;
+  const int blocks = static_cast<int>((threads + kThreads - 1) / kThreads);
+  const Blocks bk{L.A.bxs, L.A.bys, L.A.nsys};
+  const double bytes = (sizeof(T) + 4.0) * L.gs_nnz[c] + 12.0 * nrows + 3.0 * sizeof(T) * KB * nrows;
+  timed_launch(kind, s, bytes, [&] {
+    hipLaunchKernelGGL((gs_colour_kernel<LPR, KB, T, T>), dim3(blocks), dim3(kThreads), 0, s, nrows,
+                       dptr<const int>(L.gs_rows) + L.gs_off[c], L.Ag.p(), L.Ag.c(), L.Ag.v(),
+                       dptr<const T>(L.dg), b, x, gate.all, bk);
+  });
+}
+
+template <int KB, typename T>
+void gs_sweep_kb(DLevel<T> &L, bool forward, const T *b, T *x, Gate gate, hipStream_t s, int kind) {
+  const int nc = static_cast<int>(L.gs_off.size()) - 1;
+  for (int k = 0; k < nc; ++k) {
+    const int c = forward ? k : nc - 1 - k;
+    if (L.gs_lpr == 1)
+      gs_launch<1, KB>(L, c, b, x, gate, s, kind);
+    else if (L.gs_lpr == 8)
+      gs_launch<8, KB>(L, c, b, x, gate, s, kind);
+    else
+      gs_launch<32, KB>(L, c, b, x, gate, s, kind);
+  }
+}
+
+template <typename T>
+void gs_sweep(DHier<T> &H, DLevel<T> &L, bool forward, const T *b, T *x, Gate gate, hipStream_t s, int kind) {
+  if (H.kb == kMultiRhs)
+    gs_sweep_kb<kMultiRhs>(L, forward, b, x, gate, s, kind);
+  else
+    gs_sweep_kb<1>(L, forward, b, x, gate, s, kind);
+}
+
 template <typename T>
 void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
   DLevel<T> &L = H.lv[l];
-  if (L.ncont > 0) {
+  if (L.ncont > 0 && H.gs) {
+    // Gauss-Seidel: forward sweeps from zero in place on x, the residual and
+    // its restriction, the coarse correction, backward sweeps
+    DLevel<T> &C = H.lv[l + 1];
+    const bool fine = H.is_omega && l == 0;
+    const int ks = fine ? kKcFineSmooth : kKcVcycleOther;
+    const int kr = fine ? kKcFineResid : kKcVcycleOther;
+    const int ko = kKcVcycleOther;
+    const int64_t nf = static_cast<int64_t>(H.kb) * L.n;
+    hipLaunchKernelGGL(zero_kernel<T>, dim3(grid_for(nf)), dim3(kThreads), 0, s, static_cast<int>(nf), x, gate.all);
+    for (int k = 0; k < H.pre; ++k) gs_sweep(H, L, true, b, x, gate, s, ks);
+    spmv<kResid>(L.A, static_cast<const T *>(x), b, dptr<const T>(L.dinv), dptr<T>(L.r), mnull<T>(), gate, s, kr);
+    spmv<kPlainScale>(L.R, dptr<const T>(L.r), cnull<T>(), dptr<const T>(C.dinv), dptr<T>(C.b), dptr<T>(C.t), gate, s,
+                      ko);
+    vcycle(H, l + 1, dptr<const T>(C.b), dptr<T>(C.x), gate, s);
+    spmv<kAccum>(L.P, dptr<const T>(C.x), cnull<T>(), cnull<T>(), x, mnull<T>(), gate, s, ko);  // x += P x_c
+    for (int k = 0; k < H.post; ++k) gs_sweep(H, L, false, b, x, gate, s, ks);
+  } else if (L.ncont > 0) {
     DLevel<T> &C = H.lv[l + 1];
     T *t = dptr<T>(L.t), *r = dptr<T>(L.r);
     const T *dinv = dptr<const T>(L.dinv);
@@ -878,12 +972,14 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
   for (size_t q = 0; q < sys.size(); ++q) sys_o[q] = static_cast<int>(q);
   const int nsys = static_cast<int>(sys.size());
   const bool maps = nsys > 1;
-  upload_hier(ho, plan_o, p->Ho, s, keep, opt.pre_sweeps, opt.post_sweeps, maps ? &sys_o : nullptr, kb, nsys);
+  const bool gs = opt.smoother == MDP_SMOOTH_GS;
+  upload_hier(ho, plan_o, p->Ho, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, maps ? &sys_o : nullptr, kb, nsys);
   p->Ho.is_omega = true;
   const int32_t no1 = p->Ho.n();
   p->n_o = static_cast<int32_t>(p->Ho.nfull());
   if (!gsys.empty()) {
-    upload_hier(hg, plan_g, p->Hg, s, keep, opt.pre_sweeps, opt.post_sweeps, maps ? &gsys : nullptr, kb, nsys);
+    upload_hier(hg, plan_g, p->Hg, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, maps ? &gsys : nullptr, kb,
+                nsys);
     const int32_t ng1 = p->Hg.n();
     p->n_g = static_cast<int32_t>(p->Hg.nfull());
     auto blocks = [&](DCsr<T> &M, int64_t xs, int64_t ys) {

@@ -70,6 +70,13 @@ struct DLevel {
   DCsr<T> Asw;      // swept coarsest systems, indices relative to sw_off
   DevMem x, b, t, r;  // unknown, right-hand side, smoothing iterate, residual (and sweep ping-pong)
   DevMem pp;          // ping-pong for the swept coarsest systems
+  // multicolour Gauss-Seidel (MDP_SMOOTH_GS): the continuing systems'
+  // operator in plain CSR, its rows grouped by colour, and 1 / a_ii
+  DCsr<T> Ag;
+  DevMem gs_rows, dg;
+  std::vector<int32_t> gs_off;  // colour c: gs_rows[gs_off[c] .. gs_off[c + 1])
+  std::vector<int64_t> gs_nnz;  // entries in the rows of each colour
+  int gs_lpr = 1;               // lanes per row of the sweep kernel
 };
 
 // With kb > 1 (several right-hand sides per system in a batch) every level
@@ -80,7 +87,8 @@ template <typename T>
 struct DHier {
   std::vector<DLevel<T>> lv;
   int kb = 1;
-  int pre = 1, post = 1;        // l1-Jacobi sweeps before and after the coarse correction
+  int pre = 1, post = 1;        // smoothing sweeps before and after the coarse correction
+  bool gs = false;              // multicolour Gauss-Seidel instead of l1-Jacobi
   std::vector<DevMem> rowpair;  // batched: per level, the pair of each row
   DevMem cinv;            // dense FP64 inverses of the coarsest levels
   DevMem tmp_res, tmp_dz; // extra cycles: residual and correction at level 0

@@ -140,3 +140,43 @@ def test_sweep_counts_match_oracle(pre, post, prec):
         assert relerr(xh, ref.x) <= 1e-6
     finally:
         s.close()
+
+
+GS_CASES = {
+    "2d-four-lines-32": lambda: synth.grid_2d_four_lines(32),
+    "3d-regular-12": lambda: synth.regular_3d(n=12, seed=1),
+    "3d-regular-20-Klo-khi": lambda: synth.regular_3d(n=20, k_par=1e-4, kappa=1e4, seed=2),
+    "2d-random-s3": lambda: synth.random_2d(3, n_range=(60, 90)),
+}
+
+
+@pytest.mark.parametrize("name", list(GS_CASES))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("sweeps", [(1, 1), (2, 1)])
+def test_gauss_seidel_smoother_matches_oracle(name, prec, sweeps):
+    """MDP_SMOOTH_GS (Section 4's Gauss-Seidel as multicolour sweeps: forward
+    before, backward after the coarse correction): M_L on a seeded vector and
+    the whole solve against the oracle with the same smoother."""
+    from oracle import solve as osv
+    sc = GS_CASES[name]()
+    A, b, part = tpfa.assemble(sc)
+    Ao, bo, po = oa.assemble(sc)
+    pre, post = sweeps
+    say(f"[operators] gauss-seidel {name} {prec} pre={pre} post={post}")
+    ao = amg.AMGOptions(max_coarse=50, smoother="gs", pre_sweeps=pre, post_sweeps=post)
+    s = Solver(A, part, precision=prec, max_coarse=50, smoother=L.MDP_SMOOTH_GS, pre_sweeps=pre,
+               post_sweeps=post)
+    M = precond.ML(Ao, po, cycles=1, amg_opts=ao)
+    try:
+        x = synth.random_vector(A.shape[0], 17)
+        z = host(s.apply(L.MDP_OP_ML, dev(x)))
+        assert relerr(z, M.apply(x)) <= TOL[prec]
+        ref, _, _ = osv.solve(Ao, bo, po, osv.SolveOptions(amg=ao), M=M)
+        xs, st = s.solve(dev(b))
+        xh = host(xs)
+        say(f"    iters {st[0]['iters']} (oracle {ref.iters}; l1-Jacobi would need the same or more)")
+        assert st[0]["converged"] == 1 and abs(st[0]["iters"] - ref.iters) <= 2, (st[0], ref.iters)
+        assert np.linalg.norm(bo - Ao @ xh) <= 1e-8 * np.linalg.norm(bo)
+        assert relerr(xh, ref.x) <= 1e-6
+    finally:
+        s.close()
