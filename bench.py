@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--sections", default="config1,flux,cube160,batch,serve",
                    help="default mode: further workloads on the JSON line (comma list of config1, flux, "
                         "cube160, batch, serve; empty = the headline only)")
+    p.add_argument("--dim-aware", action="store_true",
+                   help="flux formulation: dimension-aware aggregation (mdp_setup_labeled, Section 3.3)")
     p.add_argument("--formulation", choices=["pressure", "flux"], default="pressure",
                    help="cube workload: host/fracture pressures (Gamma = fracture cells), or the paper's own "
                         "reading with explicit intersections and interface fluxes as Gamma")
@@ -207,7 +209,8 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
                                         max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
             o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf,
                                         max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
-            hs = {"fp64": L.mdp_setup(A, part, o64, stream)}
+            labels = info["labels"] if (formulation == "flux" and args.dim_aware) else None
+            hs = {"fp64": L.mdp_setup(A, part, o64, stream, labels=labels)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
             t2 = time.perf_counter()
             t_asm += t1 - t0
@@ -370,7 +373,8 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
         "data": "synthetic",
         "config": {"workload": f"3d-unit-cube-{n}^3-9-planes-lognormal-host" +
                                ("-interface-fluxes" if formulation == "flux" else ""),
-                   "formulation": formulation, "unknown_kinds": info,
+                   "formulation": formulation, "dim_aware": bool(formulation == "flux" and args.dim_aware),
+                   "unknown_kinds": {k: v for k, v in info.items() if k != "labels"} if info else None,
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
                    "amg_max_coarse": args.max_coarse, "restart": args.restart,

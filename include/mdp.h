@@ -174,6 +174,17 @@ int mdp_options_default(mdp_options *opt);
 int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt,
               void *hip_stream, mdp_handle **out);
 
+/* mdp_setup with dimension-aware aggregation (Section 3.3, last paragraph:
+ * aggregates built inside the subdomains of one dimension before crossing
+ * dimensions): label[i] (n entries, host memory) is the dimension of the
+ * subdomain of unknown i (any integers; equal labels share a subdomain
+ * dimension).  On the finest level of each hierarchy a strong neighbour must
+ * carry the same label; coarser levels are not restricted.  label = NULL is
+ * mdp_setup.  Meant for the interface-flux reading, whose Omega block mixes
+ * host, fracture, line and point unknowns.  Same errors as mdp_setup. */
+int mdp_setup_labeled(const mdp_csr *A, const int32_t *part, const int32_t *label, const mdp_options *opt,
+                      void *hip_stream, mdp_handle **out);
+
 /* A second handle for the same system as src with other solve options
  * (typically the other precision), reusing src's host-built blocks and AMG
  * hierarchies instead of repeating the setup of eq. (7) and Section 3.3.

@@ -8,6 +8,11 @@ following reading is used (every rule below is deterministic):
 
 * strength: j != i is a strong neighbour of i iff
   |a_ij| >= theta * sqrt(|a_ii a_jj|), theta = 0.08 on every level;
+* dimension-aware aggregation (Section 3.3, last paragraph: aggregates
+  built inside subdomains of one dimension first, crossing dimensions only
+  later): when the finest level's unknowns carry labels (the dimension of
+  their subdomain), a strong neighbour must also carry the same label there;
+  coarser levels are not restricted;
 * aggregation in natural order.  Pass 1: a node with at least one strong
   neighbour that is itself unaggregated and whose strong neighbours are all
   unaggregated starts a new aggregate {i} + N_i.  Pass 2: every remaining
@@ -136,8 +141,9 @@ def l1_diagonal(A) -> np.ndarray:
     return np.asarray(abs(sp.csr_matrix(A)).sum(axis=1)).ravel()
 
 
-def strong_neighbours(A, theta: float):
-    """Per row, the ascending list of strong neighbours (see module header)."""
+def strong_neighbours(A, theta: float, labels=None):
+    """Per row, the ascending list of strong neighbours (see module header);
+    with labels, only neighbours of the same label."""
     A = sp.csr_matrix(A)
     diag = A.diagonal()
     out = []
@@ -146,7 +152,7 @@ def strong_neighbours(A, theta: float):
         row = []
         for p in range(lo, hi):
             j = int(A.indices[p])
-            if j == i:
+            if j == i or (labels is not None and labels[j] != labels[i]):
                 continue
             if abs(A.data[p]) >= theta * np.sqrt(abs(diag[i] * diag[j])):
                 row.append(j)
@@ -211,7 +217,9 @@ def smoothed_prolongator(A, P_tent):
     return P
 
 
-def setup(A, opts: Optional[AMGOptions] = None) -> Hierarchy:
+def setup(A, opts: Optional[AMGOptions] = None, labels=None) -> Hierarchy:
+    """labels: optional label per unknown of A (dimension-aware aggregation
+    on the finest level)."""
     opts = opts or AMGOptions()
     H = Hierarchy(opts=opts)
     Acur = sp.csr_matrix(A)
@@ -223,7 +231,7 @@ def setup(A, opts: Optional[AMGOptions] = None) -> Hierarchy:
         H.levels.append(lv)
         if n <= opts.max_coarse or len(H.levels) >= opts.max_levels:
             break
-        agg, n_agg = aggregate(strong_neighbours(Acur, opts.theta))
+        agg, n_agg = aggregate(strong_neighbours(Acur, opts.theta, labels if len(H.levels) == 1 else None))
         if n_agg == 0 or n_agg > 0.9 * n:
             break
         P = smoothed_prolongator(Acur, tentative(agg, n_agg))

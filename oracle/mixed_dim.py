@@ -310,6 +310,14 @@ def assemble_flux(sc, int_kappa_inf=False, line_k=None):
             cen[off_i + i, d] += 0.5
     for p, v in enumerate(point_keys):
         cen[off_p + p] = v
+    # dimension of each unknown's subdomain (an interface: its lower side's)
+    labels = np.zeros(n_tot, dtype=np.int32)
+    labels[:n_host] = dim
+    labels[off_f:off_i] = dim - 1
+    labels[off_i:off_p] = dim - 2
+    labels[off_p:n_cells] = dim - 3
+    labels[n_cells:] = [labels[lo] for _, lo, _ in ifaces]
     info = {"host": n_host, "fracture": nf, "intersection": ni, "point": npt, "interface": n_if,
-            "cells": n_cells, "centres": cen * h, "interfaces": [(hi, lo) for hi, lo, _ in ifaces]}
+            "cells": n_cells, "centres": cen * h, "interfaces": [(hi, lo) for hi, lo, _ in ifaces],
+            "labels": labels}
     return A, rhs, part, info

@@ -37,14 +37,18 @@ from . import amg, blocks
 class ML:
     """M_L of eq. (8) with Q_OO, Q_GG = ``cycles`` SA-AMG V-cycles."""
 
-    def __init__(self, A, part, cycles: int = 1, amg_opts: Optional[amg.AMGOptions] = None):
+    def __init__(self, A, part, cycles: int = 1, amg_opts: Optional[amg.AMGOptions] = None, labels=None):
+        """labels: optional label per unknown of A (the dimension of its
+        subdomain) for dimension-aware aggregation on each block's finest level."""
         self.n = A.shape[0]
         (self.omega, self.gamma, self.Aoo, self.Aog,
          self.Ago, self.Agg) = blocks.split(A, part)
         self.S = blocks.approx_schur(self.Aoo, self.Aog, self.Ago, self.Agg)
         self.cycles = cycles
-        self.H_omega = amg.setup(self.S, amg_opts)
-        self.H_gamma = amg.setup(self.Agg, amg_opts) if self.gamma.size else None
+        lo = None if labels is None else np.asarray(labels)[self.omega]
+        lg = None if labels is None else np.asarray(labels)[self.gamma]
+        self.H_omega = amg.setup(self.S, amg_opts, lo)
+        self.H_gamma = amg.setup(self.Agg, amg_opts, lg) if self.gamma.size else None
 
     def q_omega(self, r):
         return amg.apply_cycles(self.H_omega, r, self.cycles)

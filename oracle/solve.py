@@ -33,9 +33,10 @@ class SolveOptions:
     form: str = "lower"  # block preconditioner: "lower" (M_L), "diag" (M_D) or "upper" (M_U)
 
 
-def setup(A, part, opts: Optional[SolveOptions] = None) -> precond.ML:
+def setup(A, part, opts: Optional[SolveOptions] = None, labels=None) -> precond.ML:
+    """labels: optional dimension label per unknown (dimension-aware aggregation)."""
     opts = opts or SolveOptions()
-    return precond.FORMS[opts.form](sp.csr_matrix(A), part, opts.cycles, opts.amg)
+    return precond.FORMS[opts.form](sp.csr_matrix(A), part, opts.cycles, opts.amg, labels)
 
 
 def solve(A, b, part, opts: Optional[SolveOptions] = None, M: Optional[precond.ML] = None,

@@ -91,6 +91,7 @@ _sig = {
     "mdp_options_default": (C.c_int, [C.POINTER(mdp_options)]),
     "mdp_setup": (C.c_int, [C.POINTER(mdp_csr), _ip, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
     "mdp_setup_like": (C.c_int, [_vp, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
+    "mdp_setup_labeled": (C.c_int, [C.POINTER(mdp_csr), _ip, _ip, C.POINTER(mdp_options), _vp, C.POINTER(_vp)]),
     "mdp_destroy": (C.c_int, [_vp]),
     "mdp_solve": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int64, _vp, C.POINTER(mdp_stats)]),
     "mdp_solve_batch": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _ip, _vp,
@@ -182,9 +183,11 @@ class _CsrHold:
                          self.val.ctypes.data_as(C.POINTER(C.c_double)))
 
 
-def mdp_setup(A, part, opts: Optional[mdp_options] = None, stream=None) -> int:
-    """A: scipy CSR (or (row_ptr, col, val)); part: int array (0 host, 1 fracture).
-    Returns the handle (an integer address)."""
+def mdp_setup(A, part, opts: Optional[mdp_options] = None, stream=None, labels=None) -> int:
+    """A: scipy CSR (or (row_ptr, col, val)); part: int array (0 Omega, 1
+    Gamma); labels: optional int array (dimension of each unknown's
+    subdomain), which calls mdp_setup_labeled.  Returns the handle (an
+    integer address)."""
     if hasattr(A, "indptr"):
         hold = _CsrHold(A.indptr, A.indices, A.data)
     else:
@@ -194,7 +197,14 @@ def mdp_setup(A, part, opts: Optional[mdp_options] = None, stream=None) -> int:
     host_only = bool(opts.flags & MDP_HOST_ONLY)
     sp = None if host_only else _stream_ptr(stream)
     h = _vp()
-    _check(lib.mdp_setup(C.byref(hold.s), part.ctypes.data_as(_ip), C.byref(opts), sp, C.byref(h)), "mdp_setup")
+    if labels is None:
+        _check(lib.mdp_setup(C.byref(hold.s), part.ctypes.data_as(_ip), C.byref(opts), sp, C.byref(h)), "mdp_setup")
+    else:
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        if lab.shape != part.shape:
+            raise ValueError("labels must have one entry per unknown")
+        _check(lib.mdp_setup_labeled(C.byref(hold.s), part.ctypes.data_as(_ip), lab.ctypes.data_as(_ip),
+                                     C.byref(opts), sp, C.byref(h)), "mdp_setup_labeled")
     return h.value
 
 

@@ -217,6 +217,11 @@ int mdp_options_default(mdp_options *o) {
 }
 
 int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt, void *hip_stream, mdp_handle **out) {
+  return mdp_setup_labeled(A, part, nullptr, opt, hip_stream, out);
+}
+
+int mdp_setup_labeled(const mdp_csr *A, const int32_t *part, const int32_t *label, const mdp_options *opt,
+                      void *hip_stream, mdp_handle **out) {
   API_BEGIN
   if (!out) {
     set_last_error("NULL output handle");
@@ -233,7 +238,7 @@ int mdp_setup(const mdp_csr *A, const int32_t *part, const mdp_options *opt, voi
   const auto t0 = std::chrono::steady_clock::now();
   auto h = std::make_unique<mdp_handle>();
   h->s.opt = o;
-  build_host_system(A, part, o, h->s.host);
+  build_host_system(A, part, o, h->s.host, label);
   h->s.n = h->s.host.n;
   h->s.n_o = h->s.host.n_o;
   h->s.n_g = h->s.host.n_g;

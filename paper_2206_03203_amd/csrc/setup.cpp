@@ -68,15 +68,17 @@ void check_diag(const HCsr &a, const char *what) {
                                  std::to_string(i));
 }
 
-// Strong neighbours of every row as a CSR pattern (ascending columns).
-void strength(const HCsr &a, double theta, std::vector<int32_t> &sp, std::vector<int32_t> &sc) {
+// Strong neighbours of every row as a CSR pattern (ascending columns); with
+// labels (dimension-aware aggregation), only neighbours of the same label.
+void strength(const HCsr &a, double theta, const int32_t *labels, std::vector<int32_t> &sp,
+              std::vector<int32_t> &sc) {
   const std::vector<double> d = diagonal(a);
   sp.assign(static_cast<size_t>(a.nr) + 1, 0);
   sc.clear();
   for (int32_t i = 0; i < a.nr; ++i) {
     for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
       const int32_t j = a.col[p];
-      if (j == i) continue;
+      if (j == i || (labels && labels[j] != labels[i])) continue;
       if (std::fabs(a.val[p]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) sc.push_back(j);
     }
     sp[i + 1] = static_cast<int32_t>(sc.size());
@@ -255,7 +257,7 @@ HCsr fused_restriction(const HLevel &L, const HCsr &ra) {
   return one <= two ? f : HCsr::empty(0, 0);
 }
 
-HHier amg_setup(const HCsr &A, const AmgParams &prm) {
+HHier amg_setup(const HCsr &A, const AmgParams &prm, const int32_t *labels) {
   PhaseClock clk;
   HHier h;
   HCsr cur = A;
@@ -268,7 +270,9 @@ HHier amg_setup(const HCsr &A, const AmgParams &prm) {
     h.lv.push_back(std::move(lv));
     HLevel &L = h.lv.back();
     if (n <= prm.max_coarse || static_cast<int32_t>(h.lv.size()) >= prm.max_levels) break;
-    strength(L.A, prm.theta, sp, sc);
+    // dimension-aware aggregation (Section 3.3): aggregates of the finest
+    // level stay inside one label; coarser levels may cross labels
+    strength(L.A, prm.theta, h.lv.size() == 1 ? labels : nullptr, sp, sc);
     clk.lap("strength");
     std::vector<int32_t> agg;
     const int32_t na = aggregate(n, sp, sc, agg);
@@ -296,7 +300,7 @@ HHier amg_setup(const HCsr &A, const AmgParams &prm) {
 }
 
 void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_options &opt,
-                       HostSystem &s) {
+                       HostSystem &s, const int32_t *label) {
   PhaseClock clk;
   validate(Ain, part);
   clk.lap("validate");
@@ -371,8 +375,13 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
   prm.max_coarse = opt.max_coarse;
   prm.max_dense = opt.max_dense;
   prm.max_levels = opt.max_levels;
-  s.Ho = amg_setup(s.S, prm);
-  if (s.n_g > 0) s.Hg = amg_setup(s.Agg, prm);
+  std::vector<int32_t> lo, lg;
+  if (label) {  // labels in [Omega; Gamma] order
+    for (int32_t r = 0; r < s.n_o; ++r) lo.push_back(label[s.perm[r]]);
+    for (int32_t r = s.n_o; r < n; ++r) lg.push_back(label[s.perm[r]]);
+  }
+  s.Ho = amg_setup(s.S, prm, label ? lo.data() : nullptr);
+  if (s.n_g > 0) s.Hg = amg_setup(s.Agg, prm, label ? lg.data() : nullptr);
   s.A = std::move(A);
 }
 

@@ -50,9 +50,11 @@ struct SetupError {
   std::string msg;
 };
 
-// Build everything on the host.  Throws SetupError.
+// Build everything on the host.  label (may be NULL): one label per unknown
+// (the dimension of its subdomain) for dimension-aware aggregation on the
+// finest level of each hierarchy.  Throws SetupError.
 void build_host_system(const mdp_csr *A, const int32_t *part, const mdp_options &opt,
-                       HostSystem &out);
+                       HostSystem &out, const int32_t *label = nullptr);
 
 // Write / read the complete host setup (hierarchy file).  `amg` receives the
 // AMG options the file was built with.  Both throw SetupError (MDP_EINVAL).
@@ -60,6 +62,6 @@ void save_host_system(const HostSystem &s, const mdp_options &o, const char *pat
 void load_host_system(const char *path, HostSystem &out, mdp_options &amg);
 
 // SA-AMG setup on one block (exposed for testing through the C ABI).
-HHier amg_setup(const HCsr &A, const AmgParams &prm);
+HHier amg_setup(const HCsr &A, const AmgParams &prm, const int32_t *labels = nullptr);
 
 }  // namespace mdp

@@ -15,10 +15,10 @@ class Solver:
     ``precision`` is "fp64" or "mixed" (FP32 preconditioner, FP64 outer).
     Extra keyword arguments set fields of mdp_options."""
 
-    def __init__(self, A, part, precision: str = "fp64", stream=None, **opts):
+    def __init__(self, A, part, precision: str = "fp64", stream=None, labels=None, **opts):
         prec = {"fp64": L.MDP_FP64, "mixed": L.MDP_MIXED}[precision]
         self.options = L.mdp_options_default(precision=prec, **opts)
-        self.handle = L.mdp_setup(A, part, self.options, stream)
+        self.handle = L.mdp_setup(A, part, self.options, stream, labels=labels)
         self.info = L.mdp_info(self.handle)
         self.n = self.info["n"]
         self.precision = precision

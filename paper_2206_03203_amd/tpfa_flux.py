@@ -257,7 +257,16 @@ def assemble_flux(sc, sources: Optional[List[np.ndarray]] = None):
     part[n_cells:] = 1
     rhs_dir = np.bincount(np.concatenate(r_idx), weights=np.concatenate(r_val), minlength=ntot) \
         if r_idx else np.zeros(ntot)
-    info = {"host": nh, "fracture": nf, "intersection": ni, "point": npt, "interface": n_if, "cells": n_cells}
+    # dimension of each unknown's subdomain (an interface: its lower side's),
+    # for dimension-aware aggregation
+    labels = np.empty(ntot, dtype=np.int32)
+    labels[:nh] = dim
+    labels[nh:nh + nf] = dim - 1
+    labels[nh + nf:nh + nf + ni] = dim - 2
+    labels[nh + nf + ni:n_cells] = dim - 3
+    labels[n_cells:] = labels[lo]
+    info = {"host": nh, "fracture": nf, "intersection": ni, "point": npt, "interface": n_if, "cells": n_cells,
+            "labels": labels}
     vol = h ** dim
     if sources is None:
         b = rhs_dir.copy()

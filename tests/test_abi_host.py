@@ -69,27 +69,36 @@ def _flux(assemble):
     return f
 
 
-@pytest.mark.parametrize("form", ["pressure", "flux"])
+@pytest.mark.parametrize("form", ["pressure", "flux", "flux-labeled"])
 @pytest.mark.parametrize("make", SCEN)
 def test_host_hierarchy_matches_oracle(make, form):
     """Both block readings: the primal pressure system, and the paper's
-    own with interface fluxes as Gamma (oracle/mixed_dim.py)."""
+    own with interface fluxes as Gamma (oracle/mixed_dim.py), the latter also
+    with dimension-aware aggregation (mdp_setup_labeled)."""
     from oracle import mixed_dim as md
     from paper_2206_03203_amd import tpfa_flux
     sc = make()
-    lib_asm, ora_asm = (tpfa.assemble, oa.assemble) if form == "pressure" else \
-        (_flux(tpfa_flux.assemble_flux), _flux(md.assemble_flux))
-    A, b, part = lib_asm(sc)
+    labels = None
+    if form == "pressure":
+        A, b, part = tpfa.assemble(sc)
+    else:
+        A, b, part, finfo = tpfa_flux.assemble_flux(sc)
+        if form == "flux-labeled":
+            labels = finfo["labels"]
     opts = amg.AMGOptions(max_coarse=40)
-    h = _host_handle(A, part, max_coarse=40)
+    h = L.mdp_setup(A, part, L.mdp_options_default(flags=L.MDP_HOST_ONLY, max_coarse=40), labels=labels)
     try:
-        Ao, bo, po = ora_asm(sc)
-        _, _, Aoo, Aog, Ago, Agg = ob.split(Ao, po)
+        if form == "pressure":
+            Ao, bo, po = oa.assemble(sc)
+        else:
+            Ao, bo, po, oinfo = md.assemble_flux(sc)
+            assert labels is None or np.array_equal(labels, oinfo["labels"])
+        omega, gamma, Aoo, Aog, Ago, Agg = ob.split(Ao, po)
         S = ob.approx_schur(Aoo, Aog, Ago, Agg)
         info = L.mdp_info(h)
         assert info["n_omega"] == Aoo.shape[0] and info["n_gamma"] == Agg.shape[0]
-        for block, M in ((L.MDP_BLOCK_OMEGA, S), (L.MDP_BLOCK_GAMMA, Agg)):
-            H = amg.setup(M, opts)
+        for block, M, idx in ((L.MDP_BLOCK_OMEGA, S, omega), (L.MDP_BLOCK_GAMMA, Agg, gamma)):
+            H = amg.setup(M, opts, None if labels is None else labels[idx])
             nl = info["levels_omega" if block == L.MDP_BLOCK_OMEGA else "levels_gamma"]
             assert nl == len(H.levels)
             for lvl, lv in enumerate(H.levels):

@@ -90,3 +90,30 @@ def test_flux_reading_at_cube_60(prec):
         assert err8 <= 1e-6
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("name", ["2d-four-lines-32", "3d-regular-12", "3d-random-s4"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dimension_aware_aggregation_matches_oracle(name, prec):
+    """mdp_setup_labeled with each unknown's subdomain dimension (Section
+    3.3, last paragraph): M_L and the whole solve against the oracle built
+    with the same labels."""
+    sc = CASES[name]()
+    A, b, part, info = tpfa_flux.assemble_flux(sc)
+    Ao, bo, po, io = md.assemble_flux(sc)
+    M = precond.ML(Ao, po, cycles=1, labels=io["labels"])
+    ref8, _, _ = osv.solve(Ao, bo, po, osv.SolveOptions(tol=1e-8), M=M)
+    s = Solver(A, part, precision=prec, labels=info["labels"])
+    try:
+        assert s.info["levels_omega"] == len(M.H_omega.levels)
+        x = synth.random_vector(A.shape[0], 43)
+        z = host(s.apply(L.MDP_OP_ML, dev(x)))
+        assert relerr(z, M.apply(x)) <= TOL[prec]
+        xt, st = s.solve(dev(b))
+        xh = host(xt)
+        res = np.linalg.norm(bo - Ao @ xh) / np.linalg.norm(bo)
+        say(f"[flux] labelled {name} {prec}: iters {st[0]['iters']} (oracle {ref8.iters}) residual {res:.2e}")
+        assert st[0]["converged"] == 1 and res <= 1e-8 and abs(st[0]["iters"] - ref8.iters) <= 2
+        assert relerr(xh, ref8.x) <= 1e-6
+    finally:
+        s.close()

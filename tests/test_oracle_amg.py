@@ -353,3 +353,36 @@ def test_gauss_seidel_vcycle_equals_recursion_and_is_symmetric(pre, post):
     assert np.allclose(V, B, rtol=0, atol=1e-10 * np.abs(B).max())
     if pre == post:
         assert np.allclose(V, V.T, rtol=0, atol=1e-10 * np.abs(V).max())
+
+
+def test_dimension_aware_aggregation_by_hand():
+    """Chain of 7 whose first three nodes carry one label and last four
+    another (two subdomains of different dimension): the strength graph
+    loses the edge 2-3, pass 1 makes {0,1}, {3,4}, {6,5}, pass 2 attaches 2
+    to {0,1}: [0,0,0,1,1,2,2] (unlabelled: the golden chain aggregation)."""
+    labels = np.array([0, 0, 0, 1, 1, 1, 1])
+    agg, n_agg = amg.aggregate(amg.strong_neighbours(_chain(7), 0.08, labels))
+    assert np.array_equal(agg, [0, 0, 0, 1, 1, 2, 2]) and n_agg == 3
+    plain, _ = amg.aggregate(amg.strong_neighbours(_chain(7), 0.08))
+    assert np.array_equal(plain, _golden("aggregation_chain7.txt"))
+
+
+@pytest.mark.parametrize("make", [lambda: synth.grid_2d_four_lines(16), lambda: synth.tiny_3d(7, seed=1)])
+def test_dimension_aware_aggregation_properties(make):
+    """On the interface-flux system's S~ (host, fracture, line and point
+    unknowns): no finest-level aggregate mixes dimensions, coarser levels may;
+    with one label for all unknowns the hierarchy is the unlabelled one."""
+    from oracle import mixed_dim as md, precond
+    A, b, part, info = md.assemble_flux(make())
+    lab = info["labels"]
+    M = precond.ML(A, part, amg_opts=amg.AMGOptions(max_coarse=20), labels=lab)
+    lo = lab[M.omega]
+    agg = M.H_omega.levels[0].agg
+    assert len(np.unique(lo)) >= 3
+    for a in np.unique(agg[agg >= 0]):
+        assert len(np.unique(lo[agg == a])) == 1
+    M1 = precond.ML(A, part, amg_opts=amg.AMGOptions(max_coarse=20), labels=np.zeros_like(lab))
+    M0 = precond.ML(A, part, amg_opts=amg.AMGOptions(max_coarse=20))
+    assert M1.H_omega.sizes() == M0.H_omega.sizes()
+    for l1, l0 in zip(M1.H_omega.levels, M0.H_omega.levels):
+        assert (l1.A != l0.A).nnz == 0
