@@ -38,6 +38,9 @@ extern "C" {
 #define MDP_OK 0
 #define MDP_NOT_CONVERGED 1 /* iteration budget spent; x holds the last iterate */
 #define MDP_PENDING 2       /* mdp_poll: request not finished yet              */
+#define MDP_STAGNATED 3     /* no progress: a full restart cycle, or two shorter
+                               ones in a row, lowered the true residual by less
+                               than 0.1%; x holds the last iterate              */
 #define MDP_EINVAL (-1)     /* bad argument, malformed CSR, part not in {0,1}   */
 #define MDP_ENONPOS_DIAG (-2) /* a diagonal entry of A_GG or S~ <= 0 (eq. (7) and
                                  the smoothers divide by them)                  */
@@ -67,6 +70,17 @@ extern "C" {
                               launch-bound systems (4k-70k unknowns): 5-20%
                               less time per iteration; on 100^3 systems: about
                               2% more. */
+#define MDP_FALLBACK_FP64 16u /* mdp_solve in MDP_MIXED: a column whose
+                              iteration produced a NaN/Inf from finite input
+                              (e.g. matrix values beyond FP32's range) or that
+                              ended MDP_STAGNATED is solved again from zero with
+                              the FP64 preconditioner, built on first need and
+                              kept with the handle (its Krylov directions
+                              widen to FP64 too); stats report fallback = 1,
+                              the iterations and cycles of both attempts and
+                              the status of the second.  Columns solved one at
+                              a time only: batches and four-column groups
+                              report the mixed result. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,
@@ -134,7 +148,8 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length m (64, at most 64)                  */
   int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
   double rtol;            /* stop when ||b - A x|| <= rtol ||b|| (1e-8)                */
-  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS */
+  uint32_t flags;         /* MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS |
+                             MDP_FALLBACK_FP64                                       */
   int32_t block_form;     /* MDP_BLOCK_LOWER (default), MDP_BLOCK_DIAG, MDP_BLOCK_UPPER */
   int32_t smoother;       /* MDP_SMOOTH_L1JACOBI (default) or MDP_SMOOTH_GS             */
 } mdp_options;
@@ -143,11 +158,12 @@ typedef struct {
   int32_t iters;          /* preconditioner applications                       */
   int32_t restarts;       /* FGMRES cycles after the first                     */
   int32_t converged;      /* 1 if ||b - A x|| <= rtol ||b||                    */
-  int32_t status;         /* MDP_OK, MDP_NOT_CONVERGED or a negative error     */
+  int32_t status;         /* MDP_OK, MDP_NOT_CONVERGED, MDP_STAGNATED or < 0  */
   double rel_res_true;    /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
   double rel_res_est;     /* the Arnoldi estimate |g_{k+1}| / ||b||            */
   double setup_ms;        /* host + upload time of mdp_setup for this handle  */
   double solve_ms;        /* wall time of this solve                            */
+  int32_t fallback;       /* 1 if MDP_FALLBACK_FP64 re-solved the column in FP64 */
 } mdp_stats;
 
 /* Fill *opt with the defaults listed above.  Returns MDP_OK or MDP_EINVAL
@@ -220,8 +236,9 @@ int mdp_destroy(mdp_handle *h);
  * leading dimension ld (>= n) in device memory.  Zero initial guess unless
  * the handle's options carry MDP_USE_X0.  stats (nrhs entries, may be NULL)
  * receives the per-column result.  Returns MDP_OK when every column
- * converged, MDP_NOT_CONVERGED when any did not (x holds the last iterate),
- * or a negative error (ENAN for NaN/Inf in b or a breakdown producing one).
+ * converged, otherwise the most severe column status: a negative error (ENAN
+ * for NaN/Inf in b or a breakdown producing one) before MDP_STAGNATED before
+ * MDP_NOT_CONVERGED (x holds the last iterate of those columns).
  * With nrhs >= 4, columns are solved four at a time as one batch of this
  * system whose sparse products read each matrix once for all four (each
  * column keeps its own Krylov process; results equal one-column solves up to

@@ -41,17 +41,17 @@ if len(_hip_runtimes()) > 1:
     raise ImportError("two HIP runtimes are mapped in this process (%s); import torch before "
                       "loading libmdp" % ", ".join(_hip_runtimes()))
 
-MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING = 0, 1, 2
+MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING, MDP_STAGNATED = 0, 1, 2, 3
 MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP_EBUSY = -1, -2, -3, -4, -5, -6, -7
 MDP_FP64, MDP_MIXED = 0, 1
-MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS = 1, 2, 4, 8
+MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS, MDP_FALLBACK_FP64 = 1, 2, 4, 8, 16
 MDP_BLOCK_LOWER, MDP_BLOCK_DIAG, MDP_BLOCK_UPPER = 0, 1, 2
 MDP_SMOOTH_L1JACOBI, MDP_SMOOTH_GS = 0, 1
 MDP_OP_A, MDP_OP_ML, MDP_OP_QOO, MDP_OP_QGG = 0, 1, 2, 3
 MDP_BLOCK_OMEGA, MDP_BLOCK_GAMMA = 0, 1
 MDP_MAT_A, MDP_MAT_P, MDP_MAT_R = 0, 1, 2
 
-ERROR_NAMES = {0: "MDP_OK", 1: "MDP_NOT_CONVERGED", 2: "MDP_PENDING", -1: "MDP_EINVAL",
+ERROR_NAMES = {0: "MDP_OK", 1: "MDP_NOT_CONVERGED", 2: "MDP_PENDING", 3: "MDP_STAGNATED", -1: "MDP_EINVAL",
                -2: "MDP_ENONPOS_DIAG", -3: "MDP_ESINGULAR", -4: "MDP_ENAN", -5: "MDP_ENOMEM",
                -6: "MDP_EHIP", -7: "MDP_EBUSY"}
 
@@ -72,7 +72,7 @@ class mdp_options(C.Structure):
 class mdp_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("status", C.c_int32), ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("fallback", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -220,7 +220,7 @@ def mdp_destroy(h: int) -> None:
     _check(lib.mdp_destroy(h), "mdp_destroy")
 
 
-def mdp_solve(h: int, b, x, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
+def mdp_solve(h: int, b, x, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED, MDP_STAGNATED)):
     """b, x: CUDA float64 tensors of shape (n,) or (nrhs, n) (each row one
     right-hand side, contiguous).  Returns (code, [stats dicts])."""
     nrhs = _rhs_pair(h, b, x)
@@ -231,7 +231,7 @@ def mdp_solve(h: int, b, x, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
     return rc, [s.as_dict() for s in st]
 
 
-def mdp_solve_batch(hs: Sequence[int], bs, xs, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED)):
+def mdp_solve_batch(hs: Sequence[int], bs, xs, stream=None, ok=(MDP_OK, MDP_NOT_CONVERGED, MDP_STAGNATED)):
     """hs: handles; bs/xs: per-system CUDA float64 tensors (n,) or (nrhs, n)."""
     ns = len(hs)
     if len(bs) != ns or len(xs) != ns:
@@ -330,7 +330,7 @@ def mdp_poll(srv: int, ticket: int):
     if rc == MDP_PENDING:
         return rc, None
     del _inflight[key]
-    _check(rc, "mdp_poll", ok=(MDP_OK, MDP_NOT_CONVERGED))
+    _check(rc, "mdp_poll", ok=(MDP_OK, MDP_NOT_CONVERGED, MDP_STAGNATED))
     return rc, [s.as_dict() for s in st]
 
 

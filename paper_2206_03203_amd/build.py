@@ -25,6 +25,9 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CXX = shutil.which("g++") or "g++"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-result"]
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+# ROCTx ranges for rocprofv3 --marker-trace
+LINK = ["-L", ROCM_LIB, "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics"]
 
@@ -61,7 +64,7 @@ def build(verbose: bool = False) -> str:
             if verbose and log.strip():
                 print(log)
     tmp = OUT + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LINK])
     os.replace(tmp, OUT)
     return OUT
 

@@ -111,7 +111,8 @@ int check_options(const mdp_options &o) {
   if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
   if (o.max_iter < 0) return bad("max_iter must be >= 0");
   if (!(o.rtol > 0.0)) return bad("rtol must be > 0");
-  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS)) return bad("unknown bits in flags");
+  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS | MDP_FALLBACK_FP64))
+    return bad("unknown bits in flags");
   if (o.block_form != MDP_BLOCK_LOWER && o.block_form != MDP_BLOCK_DIAG && o.block_form != MDP_BLOCK_UPPER)
     return bad("block_form must be MDP_BLOCK_LOWER, MDP_BLOCK_DIAG or MDP_BLOCK_UPPER");
   if (o.smoother != MDP_SMOOTH_L1JACOBI && o.smoother != MDP_SMOOTH_GS)
@@ -238,11 +239,17 @@ int mdp_setup_labeled(const mdp_csr *A, const int32_t *part, const int32_t *labe
   const auto t0 = std::chrono::steady_clock::now();
   auto h = std::make_unique<mdp_handle>();
   h->s.opt = o;
-  build_host_system(A, part, o, h->s.host, label);
+  {
+    const Range r("mdp_setup host");
+    build_host_system(A, part, o, h->s.host, label);
+  }
   h->s.n = h->s.host.n;
   h->s.n_o = h->s.host.n_o;
   h->s.n_g = h->s.host.n_g;
-  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  if (!(o.flags & MDP_HOST_ONLY)) {
+    const Range r("mdp_setup upload");
+    h->s.upload(static_cast<hipStream_t>(hip_stream));
+  }
   h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return MDP_OK;
@@ -272,7 +279,10 @@ int mdp_setup_like(const mdp_handle *src, const mdp_options *opt, void *hip_stre
   h->s.n = h->s.host.n;
   h->s.n_o = h->s.host.n_o;
   h->s.n_g = h->s.host.n_g;
-  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  if (!(o.flags & MDP_HOST_ONLY)) {
+    const Range r("mdp_setup upload");
+    h->s.upload(static_cast<hipStream_t>(hip_stream));
+  }
   h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return MDP_OK;
@@ -317,7 +327,10 @@ int mdp_load(const char *path, const mdp_options *opt, void *hip_stream, mdp_han
   h->s.n = h->s.host.n;
   h->s.n_o = h->s.host.n_o;
   h->s.n_g = h->s.host.n_g;
-  if (!(o.flags & MDP_HOST_ONLY)) h->s.upload(static_cast<hipStream_t>(hip_stream));
+  if (!(o.flags & MDP_HOST_ONLY)) {
+    const Range r("mdp_setup upload");
+    h->s.upload(static_cast<hipStream_t>(hip_stream));
+  }
   h->s.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return MDP_OK;

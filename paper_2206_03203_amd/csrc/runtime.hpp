@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <cstring>
@@ -29,6 +30,16 @@ struct Error {
   } while (0)
 
 void set_last_error(const std::string &msg);
+
+// A named host-side range (setup, solve, restart cycle, preconditioner and
+// Arnoldi enqueue) for tools that record ROCTx markers; next to nothing
+// when none is attached.
+struct Range {
+  explicit Range(const char *name) { roctxRangePush(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 // Allocation goes through a process-wide hook (hipMalloc unless the caller
 // installed its own allocator).  Each allocation remembers the hook that

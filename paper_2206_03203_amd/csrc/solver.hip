@@ -896,7 +896,10 @@ void vcycle(DHier<T> &H, size_t l, const T *b, T *x, Gate gate, hipStream_t s) {
 // Q = `cycles` V-cycles as a stationary iteration from zero (lv[0].t = D^-1 r on entry).
 template <typename T>
 void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s) {
-  vcycle(H, 0, r, z, gate, s);
+  {
+    const Range range("V-cycle");
+    vcycle(H, 0, r, z, gate, s);
+  }
   const int64_t n = H.nfull();
   DLevel<T> &L0 = H.lv[0];
   for (int c = 1; c < cycles; ++c) {
@@ -915,7 +918,10 @@ void apply_q(DHier<T> &H, int cycles, const T *r, T *z, Gate gate, hipStream_t s
         hipLaunchKernelGGL(zero_kernel<T>, dim3(grid_for(nz)), dim3(kThreads), 0, s, nz,
                            dptr<T>(H.tmp_res) + static_cast<int64_t>(r) * L0.n + L0.ncont, gate.all);
     }
-    vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
+    {
+      const Range range("V-cycle");
+      vcycle(H, 0, dptr<const T>(H.tmp_res), dptr<T>(H.tmp_dz), gate, s);
+    }
     hipLaunchKernelGGL(add_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, static_cast<int>(n),
                        dptr<const T>(H.tmp_dz), z, gate.all);
   }
@@ -1064,10 +1070,20 @@ void pair_norms(Workspace &ws, const Layout &L, const double *v, hipStream_t s) 
   MDP_HIP(hipStreamSynchronize(s));
 }
 
+// A restart cycle that lowers the true residual by less than this fraction
+// makes no progress.  Stagnation is declared after a full cycle (m steps) of
+// no progress, or two shorter ones in a row (cycles that the recurrence's
+// estimate ended early while the true residual stayed put).
+constexpr double kStallFraction = 1e-3;
+
 // Solve A x = b for every pair; bg / xg are in the global layout.  st has one
 // entry per pair.  Returns the most severe code (errors before non-convergence).
+// retry (optional, one entry per pair) is set to 1 for a pair whose iteration
+// produced a NaN/Inf from finite inputs or stagnated: the cases a solve in a
+// higher precision may cure.
 template <typename T>
-int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_t s, mdp_stats *st) {
+int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_t s, mdp_stats *st,
+           int *retry = nullptr) {
   Workspace &ws = *pb.ws;
   const Layout &L = *pb.L;
   const DCsr<double> &A = *pb.A;
@@ -1086,7 +1102,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   const Tile *tiles = dptr<const Tile>(L.tiles);
 
   std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0), scale0(np, 1.0);
-  std::vector<int> iters(np, 0), cycles(np, 0), code(np, MDP_OK), active(np, 0), kmax_h(np, 0);
+  std::vector<int> iters(np, 0), cycles(np, 0), code(np, MDP_OK), active(np, 0), kmax_h(np, 0), stall(np, 0);
+  if (retry) std::fill(retry, retry + np, 0);
   pair_norms(ws, L, bg, s);
   for (int p = 0; p < np; ++p) {
     bnorm[p] = ws.host_norms[p];
@@ -1125,6 +1142,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
       }
     }
     if (nactive == 0) break;
+    const Range cycle_range("fgmres cycle");
     MDP_HIP(hipMemcpyAsync(ws.active.get(), active.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     MDP_HIP(hipMemcpyAsync(ws.kmaxp.get(), kmax_h.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
     MDP_HIP(hipMemcpyAsync(ws.tolp.get(), tol.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
@@ -1166,7 +1184,11 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
           });
         }
       }
-      apply_ml(P, pin, zj, g_apply, s);
+      {
+        const Range r("M_L apply");
+        apply_ml(P, pin, zj, g_apply, s);
+      }
+      const Range r("Arnoldi step");
       spmv<kPlain>(A, static_cast<const T *>(zj), cnull<double>(), cnull<double>(), w, mnull<double>(), g_apply,
                    s, kKcOuterSpmv);
       const int nv = 2 * j + 3;
@@ -1272,11 +1294,25 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     for (int p = 0; p < np; ++p) {
       if (!active[p]) continue;
       const GmresState &gs = ws.host_state[p];
-      if (gs.nan) code[p] = MDP_ENAN;
+      if (gs.nan) {
+        code[p] = MDP_ENAN;
+        if (retry) retry[p] = 1;
+      }
       iters[p] += gs.k;
       est[p] = gs.est;
       ++cycles[p];
-      beta[p] = ws.host_norms[p];
+      const double b_new = ws.host_norms[p];
+      if (code[p] == MDP_OK && b_new > tol[p] && iters[p] < opt.max_iter) {
+        if (b_new > (1.0 - kStallFraction) * beta[p])
+          stall[p] += gs.k >= m ? 2 : 1;
+        else
+          stall[p] = 0;
+        if (stall[p] >= 2) {
+          code[p] = MDP_STAGNATED;
+          if (retry) retry[p] = 1;
+        }
+      }
+      beta[p] = b_new;
     }
   }
   MDP_HIP(hipGetLastError());
@@ -1323,8 +1359,9 @@ void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &
   MDP_HIP(hipStreamSynchronize(s));
 }
 
-void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz, hipStream_t s) {
+void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz_, hipStream_t s) {
   m = m_;
+  tsz = tsz_;
   npairs = np;
   ntiles = std::max(nt, 1);
   ld = padded_ld(n);
@@ -1382,6 +1419,8 @@ hipStream_t Workspace::own_stream() {
 
 void Workspace::release() {
   graphs.clear();
+  graphs64.clear();
+  tsz = 0;
   if (handoff) (void)hipEventDestroy(handoff);
   if (own) (void)hipStreamDestroy(own);
   handoff = nullptr;
@@ -1455,6 +1494,7 @@ void Solver::upload(hipStream_t s) {
 }
 
 int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
+  const Range range("mdp_solve");
   const auto t0 = std::chrono::steady_clock::now();
   ensure_workspace(s);
   // The legacy stream cannot be captured: a solve handed it runs on the
@@ -1481,7 +1521,19 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   int rc;
   if (opt.precision == MDP_MIXED) {
     Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt, &ws.graphs};
-    rc = fgmres<float>(pb, bp, xp, use_x0, s, &out);
+    int retry = 0;
+    rc = fgmres<float>(pb, bp, xp, use_x0, s, &out, &retry);
+    if (retry && (opt.flags & MDP_FALLBACK_FP64)) {
+      // the FP32 preconditioner failed this column: solve it again from zero
+      // with the FP64 one (the graphs of the FP32 steps do not apply to it)
+      const int32_t it_mixed = out.iters, cyc_mixed = out.restarts + 1;
+      ensure_fp64(s);
+      Problem<double> p64{&A, pc64.get(), &layout, &ws, &opt, &ws.graphs64};
+      rc = fgmres<double>(p64, bp, xp, false, s, &out);
+      out.iters += it_mixed;
+      out.restarts += cyc_mixed;
+      out.fallback = 1;
+    }
   } else {
     Problem<double> pb{&A, pc64.get(), &layout, &ws, &opt, &ws.graphs};
     rc = fgmres<double>(pb, bp, xp, use_x0, s, &out);
@@ -1497,7 +1549,30 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   return rc;
 }
 
+void Solver::ensure_fp64(hipStream_t s) {
+  if (!pc64) {
+    const AutotuneScope tune((opt.flags & MDP_NO_AUTOTUNE) == 0);
+    const std::vector<const HostSystem *> sys{&host};
+    const LevelPlan po = plan_levels({&host.Ho});
+    const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
+    const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt, s);
+  }
+  if (ws.tsz < sizeof(double)) {
+    // Z holds FP64 directions from now on (FP32 solves use the wider array as
+    // it is).  Only Z moves: the solve's permuted b and x, its stream and its
+    // events stay; graphs captured with the old Z are dropped.
+    MDP_HIP(hipStreamSynchronize(s));
+    ws.graphs.clear();
+    ws.graphs64.clear();
+    ws.Z.alloc(static_cast<size_t>(ws.ld) * sizeof(double) * ws.m);
+    MDP_HIP(hipMemsetAsync(ws.Z.get(), 0, ws.Z.bytes(), s));
+    ws.tsz = sizeof(double);
+  }
+}
+
 void Solver::apply(int op, const double *x, double *y, hipStream_t s) {
+  const Range range("mdp_apply");
   ensure_workspace(s);
   enqueue_apply(op, x, y, s, dptr<float>(ws.rin), dptr<float>(ws.Z));
   MDP_HIP(hipStreamSynchronize(s));
@@ -1664,6 +1739,7 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
 }
 
 int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
+  const Range range("mdp_solve_batch");
   const auto t0 = std::chrono::steady_clock::now();
   const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
   Workspace &W = wsp ? *wsp : ws;

@@ -144,6 +144,7 @@ struct Workspace {
   int ntiles = 0;   // tiles the per-tile partial sums hold
   int ldv = 0;     // per-pair stride of length-(m+1) arrays
   int sstride = 0; // per-pair stride of the step sums
+  size_t tsz = 0;   // bytes per entry of Z and rin (4: FP32 preconditioner, 8: FP64)
   DevMem V, Z, w, rin, bp, xp;
   DevMem Hr, cs, sn, g, y, hist, hprev, coef, sums;
   DevMem partial, npart;
@@ -154,6 +155,7 @@ struct Workspace {
   double *host_norms = nullptr;      // pinned, npairs
   std::vector<hipEvent_t> ev;
   StepGraphs graphs;               // single-system solves on this workspace (MDP_GRAPHS)
+  StepGraphs graphs64;             // the FP64 re-solves of MDP_FALLBACK_FP64 on it
   hipStream_t own = nullptr;       // non-blocking stream for solves handed the legacy stream
   hipEvent_t handoff = nullptr;
   hipStream_t own_stream();        // created on first use
@@ -186,6 +188,9 @@ struct Solver {
   void ensure_workspace(hipStream_t s);  // (re)allocate the Krylov workspace if released
   size_t workspace_bytes_needed() const;
   int solve(const double *b, double *x, hipStream_t s, mdp_stats *st);
+  // MDP_FALLBACK_FP64: the FP64 preconditioner (built from the kept host
+  // hierarchy) and a workspace wide enough for FP64 directions
+  void ensure_fp64(hipStream_t s);
   void apply(int op, const double *x, double *y, hipStream_t s);
   // The launches of apply, without allocation or synchronisation; in mixed
   // precision `in` and `out` stage the FP32 copies of x and y (n entries each)

@@ -428,3 +428,32 @@ def test_tune_file_errors(tmp_path):
     p.write_text("8 10 10 3 28 64  1 0 0 0 8 4\ngarbage\n8 10 10 3 28 64  1 1 0 0 8 4\n")
     L.mdp_tune_file(str(p))
     L.mdp_tune_file(None)
+
+
+def test_binding_constants_match_the_header():
+    """Every integer constant the C header defines has the same value in the
+    Python binding (status codes, flags, forms, operators, blocks)."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "mdp.h")).read()
+    seen = 0
+    for name, val in re.findall(r"^#define (MDP_[A-Z0-9_]+) \(?(-?\d+)u?\)?", hdr, re.M):
+        if hasattr(L, name):
+            assert getattr(L, name) == int(val), name
+            seen += 1
+    for name in ("MDP_STAGNATED", "MDP_FALLBACK_FP64", "MDP_GRAPHS", "MDP_ENAN", "MDP_SMOOTH_GS"):
+        assert hasattr(L, name), name
+    assert seen >= 30
+
+
+def test_fallback_flag_accepted_and_stats_field_present():
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    o = L.mdp_options_default(precision=L.MDP_MIXED, flags=L.MDP_HOST_ONLY | L.MDP_FALLBACK_FP64)
+    h = L.mdp_setup(A, part, o)
+    L.mdp_destroy(h)
+    assert "fallback" in L.mdp_stats().as_dict()
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | 32)
+    with pytest.raises(L.MdpError) as e:
+        L.mdp_setup(A, part, o)
+    assert e.value.code == L.MDP_EINVAL
