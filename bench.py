@@ -315,10 +315,16 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
             torch.cuda.synchronize()
             dt1 = time.perf_counter() - t0
             ns = nr * sum(s["B4"].shape[0] for s in systems)
+            mem = [L.mdp_multi_rhs_memory(s["h"][prec]) for s in systems]
             multi_rhs[prec] = {"value": round(ns / dt4, 3), "unit": "solves/s",
                                "one_column_at_a_time": round(ns / dt1, 3),
                                "speedup": round(dt1 / dt4, 3), "solves": ns,
-                               "iters": sorted(set(its)), "iters_one_at_a_time": sorted(set(its1))}
+                               "iters": sorted(set(its)), "iters_one_at_a_time": sorted(set(its1)),
+                               "handles_with_plan": sum(m["plan_bytes"] > 0 for m in mem),
+                               "plan_gb": [round(m["plan_bytes"] / 1e9, 3) for m in mem],
+                               "shared_workspace_gb": round(max(m["shared_bytes"] for m in mem) / 1e9, 3),
+                               "held_gb": round(mem[-1]["held"] / 1e9, 3),
+                               "budget_gb": round(mem[-1]["budget"] / 1e9, 3)}
             log(f"[bench] four right-hand sides {prec}: {ns} solves in {dt4:.3f}s "
                 f"(one column at a time {dt1:.3f}s)")
         multi_rhs["what"] = ("each system with four right-hand sides (Dirichlet data alone and with three "

@@ -242,15 +242,18 @@ int mdp_destroy(mdp_handle *h);
  * With nrhs >= 4, columns are solved four at a time as one batch of this
  * system whose sparse products read each matrix once for all four (each
  * column keeps its own Krylov process; results equal one-column solves up to
- * rounding).  That batch (a four-column Krylov workspace, a four-fold copy
- * of the system matrix and one copy of the preconditioner) is built on first
- * use and kept with the handle until mdp_destroy.  All handles' batches
- * together hold at most MDP_MULTI_RHS_BYTES bytes of device memory (an
- * environment variable, read at each build; default a quarter of the
- * device's memory): a handle whose batch does not fit solves its columns one
- * by one, and tries again once others have been destroyed; one whose build
- * ran out of device memory stays with one column at a time.  Remaining
- * columns are solved one by one.  Synchronises hip_stream before returning. */
+ * rounding).  That batch (a four-fold copy of the system matrix and one copy
+ * of the preconditioner) is built on first use and kept with the handle
+ * until mdp_destroy; its four-column Krylov workspace is one per device,
+ * shared by every handle's batch there (sized to the largest, released with
+ * the last batch), so four-column solves on one device take turns.  The
+ * batches and the shared workspaces together hold at most
+ * MDP_MULTI_RHS_BYTES bytes of device memory (an environment variable, read
+ * at each build; default a quarter of the device's memory): a handle whose
+ * batch does not fit solves its columns one by one, and tries again once
+ * others have been destroyed; one whose build ran out of device memory stays
+ * with one column at a time.  Remaining columns are solved one by one.
+ * Synchronises hip_stream before returning. */
 int mdp_solve(mdp_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
               int64_t ld, void *hip_stream, mdp_stats *stats);
 
@@ -300,6 +303,15 @@ int mdp_apply_noalloc(mdp_handle *h, int32_t op, const double *x_dev, double *y_
 /* Sizes: n, n_Omega, n_Gamma and the number of levels of each hierarchy. */
 int mdp_info(const mdp_handle *h, int32_t *n, int32_t *n_omega, int32_t *n_gamma,
              int32_t *levels_omega, int32_t *levels_gamma);
+
+/* Device memory of mdp_solve's four-column batches (any pointer may be
+ * NULL): the bytes h's batch holds (0 before its first four-column solve or
+ * when it did not fit), the bytes of the shared four-column Krylov workspace
+ * of the device h's batch runs on (0 without a batch), and the bytes all
+ * batches and shared workspaces hold together against the budget
+ * MDP_MULTI_RHS_BYTES (its current value in *budget). */
+int mdp_multi_rhs_memory(const mdp_handle *h, int64_t *plan_bytes, int64_t *shared_bytes, int64_t *held,
+                         int64_t *budget);
 
 /* Shape of one hierarchy matrix (block = MDP_BLOCK_*, mat = MDP_MAT_*, level
  * 0 = finest; P and R do not exist on the coarsest level). */

@@ -99,6 +99,7 @@ _sig = {
     "mdp_apply": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "mdp_apply_noalloc": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "mdp_info": (C.c_int, [_vp, _ip, _ip, _ip, _ip, _ip]),
+    "mdp_multi_rhs_memory": (C.c_int, [_vp] + [C.POINTER(C.c_int64)] * 4),
     "mdp_level_shape": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_int64)]),
     "mdp_level_export": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_double)]),
     "mdp_level_aggregates": (C.c_int, [_vp, C.c_int32, C.c_int32, _ip]),
@@ -260,6 +261,12 @@ def mdp_info(h: int) -> dict:
     v = [C.c_int32() for _ in range(5)]
     _check(lib.mdp_info(h, *[C.byref(x) for x in v]), "mdp_info")
     return dict(zip(["n", "n_omega", "n_gamma", "levels_omega", "levels_gamma"], [x.value for x in v]))
+
+
+def mdp_multi_rhs_memory(h: int) -> dict:
+    v = [C.c_int64() for _ in range(4)]
+    _check(lib.mdp_multi_rhs_memory(h, *[C.byref(x) for x in v]), "mdp_multi_rhs_memory")
+    return dict(zip(["plan_bytes", "shared_bytes", "held", "budget"], [x.value for x in v]))
 
 
 def mdp_level_export(h: int, block: int, level: int, mat: int):

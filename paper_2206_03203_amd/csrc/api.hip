@@ -141,16 +141,38 @@ int64_t multi_rhs_cap() {
   return quarter;
 }
 
+// One four-column Krylov workspace per device, shared by every handle's
+// plan there: a plan keeps only its matrices.  The workspace grows to the
+// largest plan's sizes; four-column solves on a device take turns on it.
+struct SharedRhs4 {
+  std::mutex use;     // held through a four-column solve and while the workspace changes
+  Workspace ws;
+  int64_t bytes = 0;  // device bytes of ws (counted in g_mrhs_held)
+  int plans = 0;      // plans on this device (under g_mrhs_mu)
+};
+// never destroyed: the arrays stay until the process ends, as the runtime
+// may be gone by the time static destructors run
+SharedRhs4 &rhs4_of(int dev) {
+  static SharedRhs4 *const all = new SharedRhs4[kMaxDevices];
+  return all[dev];
+}
+
+size_t rhs4_tsz(const mdp_options &o) { return o.precision == MDP_MIXED ? sizeof(float) : sizeof(double); }
+
 // Build h's four-column plan if the budget has room (see mdp_solve).
 void build_multi_rhs(mdp_handle *h, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mrhs_mu);
   const int64_t cap = multi_rhs_cap();
   if (g_mrhs_held >= cap || g_mrhs_held + h->rhs4_need > cap) return;
+  int dev = 0;
+  MDP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) raise(MDP_EINVAL, "device index out of range");
+  SharedRhs4 &sh = rhs4_of(dev);
   const int64_t before = t_dev_net_bytes;
+  std::unique_ptr<Batch> bt;
   try {
-    auto bt = std::make_unique<Batch>();
-    bt->build(std::vector<const Solver *>(kMultiRhs, &h->s), s, true);
-    h->rhs4 = std::move(bt);
+    bt = std::make_unique<Batch>();
+    bt->build(std::vector<const Solver *>(kMultiRhs, &h->s), s, false);
   } catch (const Error &e) {
     if (e.code != MDP_ENOMEM) throw;
     (void)hipGetLastError();  // clear the failed allocation's error state
@@ -158,13 +180,69 @@ void build_multi_rhs(mdp_handle *h, hipStream_t s) {
     return;
   }
   const int64_t bytes = std::max<int64_t>(0, t_dev_net_bytes - before);
-  if (g_mrhs_held + bytes > cap) {
-    h->rhs4.reset();
-    h->rhs4_need = bytes;
+  // the shared workspace this plan needs, grown from what the device holds
+  const int m = bt->opt.restart;
+  const size_t tsz = rhs4_tsz(bt->opt);
+  std::lock_guard<std::mutex> use(sh.use);
+  const bool grow = !sh.ws.fits(bt->n, m, bt->npairs, bt->layout.ntiles, tsz);
+  int64_t n_ws = bt->n;
+  int np_ws = bt->npairs, nt_ws = bt->layout.ntiles;
+  size_t tsz_ws = tsz;
+  if (grow && sh.ws.allocated() && sh.ws.m == m) {
+    n_ws = std::max<int64_t>(n_ws, sh.ws.ld);
+    np_ws = std::max(np_ws, sh.ws.npairs);
+    nt_ws = std::max(nt_ws, sh.ws.ntiles);
+    tsz_ws = std::max(tsz_ws, sh.ws.tsz);
+  }
+  const int64_t ws_bytes =
+      grow ? static_cast<int64_t>(Workspace::bytes_for(n_ws, m, np_ws, nt_ws, tsz_ws, true)) : sh.bytes;
+  if (g_mrhs_held + bytes + (ws_bytes - sh.bytes) > cap) {
+    h->rhs4_need = bytes + (ws_bytes - sh.bytes);
     return;
   }
+  if (grow) {
+    try {
+      MDP_HIP(hipDeviceSynchronize());  // no plan's work may still use the old arrays
+      sh.ws.release();
+      sh.ws.alloc(n_ws, m, np_ws, nt_ws, tsz_ws, s);
+      sh.ws.bp.alloc(static_cast<size_t>(sh.ws.ld) * sizeof(double));
+      sh.ws.xp.alloc(static_cast<size_t>(sh.ws.ld) * sizeof(double));
+    } catch (const Error &e) {
+      sh.ws.release();
+      g_mrhs_held -= sh.bytes;
+      sh.bytes = 0;
+      if (e.code != MDP_ENOMEM) throw;
+      (void)hipGetLastError();
+      h->rhs4_failed = true;
+      return;
+    }
+    g_mrhs_held += ws_bytes - sh.bytes;
+    sh.bytes = ws_bytes;
+  }
+  bt->wsp = &sh.ws;
+  h->rhs4 = std::move(bt);
+  h->rhs4_dev = dev;
+  ++sh.plans;
   g_mrhs_held += bytes;
   h->rhs4_bytes = bytes;
+}
+
+// h's plan is going: its bytes leave the budget, and the device's shared
+// workspace goes with the last plan there.
+void drop_multi_rhs(mdp_handle *h) {
+  if (!h->rhs4) return;
+  std::lock_guard<std::mutex> lk(g_mrhs_mu);
+  SharedRhs4 &sh = rhs4_of(h->rhs4_dev);
+  g_mrhs_held -= h->rhs4_bytes;
+  h->rhs4_bytes = 0;
+  h->rhs4.reset();
+  if (--sh.plans == 0) {
+    std::lock_guard<std::mutex> use(sh.use);
+    (void)hipDeviceSynchronize();
+    sh.ws.release();
+    g_mrhs_held -= sh.bytes;
+    sh.bytes = 0;
+  }
 }
 
 }  // namespace
@@ -344,11 +422,24 @@ int mdp_destroy(mdp_handle *h) {
     if (g_batch && std::find(g_batch->handles.begin(), g_batch->handles.end(), h) != g_batch->handles.end())
       g_batch.reset();
   }
-  if (h && h->rhs4_bytes > 0) {
-    std::lock_guard<std::mutex> lk(g_mrhs_mu);
-    g_mrhs_held -= h->rhs4_bytes;
-  }
+  if (h) drop_multi_rhs(h);
   delete h;
+  return MDP_OK;
+  API_END
+}
+
+int mdp_multi_rhs_memory(const mdp_handle *h, int64_t *plan_bytes, int64_t *shared_bytes, int64_t *held,
+                         int64_t *budget) {
+  API_BEGIN
+  if (!h) {
+    set_last_error("null handle");
+    return MDP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_mrhs_mu);
+  if (plan_bytes) *plan_bytes = h->rhs4 ? h->rhs4_bytes : 0;
+  if (shared_bytes) *shared_bytes = h->rhs4 ? rhs4_of(h->rhs4_dev).bytes : 0;
+  if (held) *held = g_mrhs_held;
+  if (budget) *budget = multi_rhs_cap();
   return MDP_OK;
   API_END
 }
@@ -373,6 +464,7 @@ int mdp_solve(mdp_handle *h, const double *b, double *x, int32_t nrhs, int64_t l
   // or without device memory for it, the columns are solved one by one.
   if (nrhs >= kMultiRhs && !h->rhs4 && !h->rhs4_failed) build_multi_rhs(h, s);
   if (h->rhs4) {
+    std::lock_guard<std::mutex> use(rhs4_of(h->rhs4_dev).use);
     for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
       std::vector<PairIO> io;
       for (int r = 0; r < kMultiRhs; ++r) io.push_back(PairIO{b + (k + r) * ld, x + (k + r) * ld});

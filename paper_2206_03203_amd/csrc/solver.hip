@@ -17,6 +17,7 @@
 // with its own convergence test; whole-batch kernels (preconditioner, system
 // matrix) stop once no pair needs them in the current cycle.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1125,10 +1126,11 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   // timers run).  Graphs captured with another workspace are dropped.
   StepGraphs *sg = pb.graphs;
   bool use_graphs = sg && (opt.flags & MDP_GRAPHS) && !ktimer_any_on() && !sg->failed && s != nullptr;
-  if (use_graphs && (sg->ws != &ws || sg->exec.size() != static_cast<size_t>(2 * (m + 1)))) {
+  if (use_graphs && (sg->ws != &ws || sg->ws_gen != ws.gen || sg->exec.size() != static_cast<size_t>(2 * (m + 1)))) {
     sg->clear();
     sg->exec.assign(2 * (m + 1), nullptr);
     sg->ws = &ws;
+    sg->ws_gen = ws.gen;
   }
   while (true) {
     int nactive = 0, kmax_all = 0;
@@ -1359,7 +1361,25 @@ void Layout::build(const std::vector<std::vector<std::pair<int64_t, int64_t>>> &
   MDP_HIP(hipStreamSynchronize(s));
 }
 
+size_t Workspace::bytes_for(int64_t n, int m_, int np, int nt, size_t tsz_, bool perm) {
+  const size_t ld_ = static_cast<size_t>(padded_ld(n));
+  const size_t ldv_ = static_cast<size_t>(m_) + 2, ss = 2 * (static_cast<size_t>(m_) + 1) + 4;
+  const size_t npz = static_cast<size_t>(np), ntz = static_cast<size_t>(std::max(nt, 1));
+  size_t b = ld_ * 8 * (m_ + 1) + ld_ * tsz_ * m_ + ld_ * 8 + ld_ * tsz_;  // V, Z, w, rin
+  if (perm) b += 2 * ld_ * 8;                                             // bp, xp
+  b += 6 * npz * ldv_ * 8 + npz * (m_ + 1) * m_ * 8 + npz * sizeof(DcgsCoef) + npz * ss * 8;
+  b += (2 * (m_ + 1) + 3) * ntz * 8 + ntz * 8 + npz * sizeof(GmresState) + sizeof(BatchCtl);
+  b += npz * (4 + 8 + 8 + 4 + 8);  // kmaxp, tolp, scale0, active, norms
+  return b;
+}
+
+bool Workspace::fits(int64_t n, int m_, int np, int nt, size_t tsz_) const {
+  return allocated() && ld >= n && m == m_ && npairs >= np && ntiles >= nt && tsz >= tsz_ && bp.get() && xp.get();
+}
+
 void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz_, hipStream_t s) {
+  static std::atomic<uint64_t> generations{0};
+  gen = ++generations;
   m = m_;
   tsz = tsz_;
   npairs = np;
@@ -1568,6 +1588,7 @@ void Solver::ensure_fp64(hipStream_t s) {
     ws.Z.alloc(static_cast<size_t>(ws.ld) * sizeof(double) * ws.m);
     MDP_HIP(hipMemsetAsync(ws.Z.get(), 0, ws.Z.bytes(), s));
     ws.tsz = sizeof(double);
+    ++ws.gen;
   }
 }
 
@@ -1743,8 +1764,7 @@ int Batch::solve(const std::vector<PairIO> &io, hipStream_t s, mdp_stats *st) {
   const auto t0 = std::chrono::steady_clock::now();
   const bool use_x0 = (opt.flags & MDP_USE_X0) != 0;
   Workspace &W = wsp ? *wsp : ws;
-  if (!W.allocated() || W.ld < n || W.npairs < npairs || W.ntiles < layout.ntiles || W.m != opt.restart ||
-      !W.bp.get())
+  if (!W.fits(n, opt.restart, npairs, layout.ntiles, opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double)))
     raise(MDP_EINVAL, "batch workspace missing or too small");
   // As for single solves: graph replay cannot capture the legacy stream, so
   // the batch then runs on the workspace's own stream after the caller's work.

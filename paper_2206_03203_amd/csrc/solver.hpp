@@ -132,6 +132,7 @@ struct Layout {
 struct StepGraphs {
   std::vector<hipGraphExec_t> exec;
   const void *ws = nullptr;
+  uint64_t ws_gen = 0;  // the workspace's generation at capture
   bool failed = false;  // capture or instantiation failed once: launch directly
   void clear();
   ~StepGraphs() { clear(); }
@@ -145,6 +146,7 @@ struct Workspace {
   int ldv = 0;     // per-pair stride of length-(m+1) arrays
   int sstride = 0; // per-pair stride of the step sums
   size_t tsz = 0;   // bytes per entry of Z and rin (4: FP32 preconditioner, 8: FP64)
+  uint64_t gen = 0; // changes whenever the device arrays move (graphs hold their addresses)
   DevMem V, Z, w, rin, bp, xp;
   DevMem Hr, cs, sn, g, y, hist, hprev, coef, sums;
   DevMem partial, npart;
@@ -160,6 +162,10 @@ struct Workspace {
   hipEvent_t handoff = nullptr;
   hipStream_t own_stream();        // created on first use
   void alloc(int64_t n, int m, int npairs, int ntiles, size_t tsz, hipStream_t s);
+  // device bytes alloc() takes for these sizes (with bp / xp when `perm`)
+  static size_t bytes_for(int64_t n, int m, int npairs, int ntiles, size_t tsz, bool perm);
+  // holds at least these sizes (and bp / xp)
+  bool fits(int64_t n, int m, int npairs, int ntiles, size_t tsz) const;
   void release();           // free everything (alloc may be called again)
   size_t device_bytes() const;
   bool allocated() const { return V.get() != nullptr; }
@@ -235,7 +241,8 @@ struct mdp_handle {
   // kMultiRhs pairs sharing the preconditioner's matrix reads (built on first
   // use when the process-wide budget for such plans has room, kept until
   // mdp_destroy)
-  std::unique_ptr<mdp::Batch> rhs4;
+  std::unique_ptr<mdp::Batch> rhs4;  // its Krylov workspace is the device's shared one
+  int rhs4_dev = 0;        // the device the plan was built on
   int64_t rhs4_bytes = 0;  // device bytes the plan holds (counted in the budget)
   int64_t rhs4_need = 0;   // a plan that did not fit: its size (retried when the budget has room)
   bool rhs4_failed = false;  // the device ran out of memory building it: one column at a time

@@ -457,3 +457,17 @@ def test_fallback_flag_accepted_and_stats_field_present():
     with pytest.raises(L.MdpError) as e:
         L.mdp_setup(A, part, o)
     assert e.value.code == L.MDP_EINVAL
+
+
+def test_multi_rhs_memory_of_a_handle_without_a_batch(monkeypatch):
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    h = L.mdp_setup(A, part, L.mdp_options_default(flags=L.MDP_HOST_ONLY))
+    try:
+        monkeypatch.setenv("MDP_MULTI_RHS_BYTES", "12345")
+        m = L.mdp_multi_rhs_memory(h)
+        assert m["plan_bytes"] == 0 and m["shared_bytes"] == 0 and m["budget"] == 12345
+    finally:
+        L.mdp_destroy(h)
+    with pytest.raises(L.MdpError):
+        L.mdp_multi_rhs_memory(None)
