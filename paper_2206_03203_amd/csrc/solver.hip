@@ -163,11 +163,27 @@ void tune_record(const TuneKey &k, const FormatChoice &f) {
   }
 }
 
+// A restriction choice: "-vsize nr nc ncont nnz(Rf) nnz(R)  fused 0 0 0 4 4".
+void tune_record_restriction(const TuneKey &k, bool fused) {
+  if (g_tune_path.empty()) return;
+  if (FILE *fp = std::fopen(g_tune_path.c_str(), "a")) {
+    std::fprintf(fp, "%d %d %d %d %lld %lld  %d 0 0 0 4 %d\n", k.vsize, k.nr, k.nc, k.maxlen,
+                 static_cast<long long>(k.nnz), static_cast<long long>(k.padded), fused ? 1 : 0, kCsrBatch);
+    std::fclose(fp);
+  }
+}
+
 bool valid_lpr(int l) { return l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64 || l == kThreads; }
 
 template <typename T>
 FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
                              const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep);
+
+// Restriction of a level: true to keep the fused product R (I - A D^-1) b,
+// false for the residual b - A D^-1 b and then R (see choose_fused).
+std::map<TuneKey, int> g_rtune;  // under g_tune_mu
+template <typename T>
+bool choose_fused(const HCsr &rf, const DCsr<T> &Rf, const DCsr<T> &A, const DCsr<T> &R, hipStream_t s);
 
 // Upload a host CSR in the device format that suits it.  With autotuning
 // on, matrices of at least kTuneMinNnz entries are timed on the device in
@@ -308,7 +324,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     dl.ncont = pl.ncont[l];
     dl.sw_off = pl.sw_off[l];
     const size_t nfull = static_cast<size_t>(kb) * dl.n;
-    std::vector<Piece> pa, pp, pr, psw;
+    std::vector<Piece> pa, pp, pr, pr_plain, psw;
     std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
     // the level restricts b with R (I - A D^-1) when every continuing system
@@ -326,6 +342,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
         pa.emplace_back(&hl.A, o, o);
         pp.emplace_back(&hl.P, o, oc);
         pr.emplace_back(dl.fused ? &hl.Rf : &hl.R, oc, o);
+        pr_plain.emplace_back(&hl.R, oc, o);
       } else if (h.dense) {
         for (int r = 0; r < kb; ++r)
           desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
@@ -377,7 +394,18 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     }
     if (l + 1 < L) {
       upload_csr(concat_blocks(dl.ncont, pl.n[l + 1], pp), dl.P, s, keep);
-      upload_csr(concat_blocks(pl.n[l + 1], dl.ncont, pr), dl.R, s, keep);
+      const HCsr Rcat = concat_blocks(pl.n[l + 1], dl.ncont, pr);
+      upload_csr(Rcat, dl.R, s, keep);
+      if (dl.fused && t_autotune && Rcat.nnz() >= kTuneMinNnz) {
+        // the fused product moves fewer bytes, but the residual's own format
+        // (diagonals, say) can make the two products faster: time both
+        DCsr<T> Rp;
+        upload_csr(concat_blocks(pl.n[l + 1], dl.ncont, pr_plain), Rp, s, keep);
+        if (!choose_fused<T>(Rcat, dl.R, dl.A, Rp, s)) {
+          dl.R = std::move(Rp);
+          dl.fused = false;
+        }
+      }
     }
     upload_csr(concat_blocks(dl.n - dl.sw_off, dl.n - dl.sw_off, psw), dl.Asw, s, keep);
     dl.ndense = static_cast<int32_t>(desc.size());
@@ -723,6 +751,68 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
   return best;
 }
 
+// Time the two ways of restricting b on one level, each from cold caches as
+// in autotune_format: the fused product Rf b, and the residual b - A D^-1 b
+// followed by R of it.  A recorded choice is used without timing.
+template <typename T>
+bool choose_fused(const HCsr &rf, const DCsr<T> &Rf, const DCsr<T> &A, const DCsr<T> &R, hipStream_t s) {
+  const TuneKey key{-static_cast<int>(sizeof(T)), rf.nr, rf.nc, A.nr, rf.nnz(), R.nnz};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_rtune.find(key);
+    if (it != g_rtune.end()) return it->second != 0;
+  }
+  const int64_t nf = std::max<int32_t>(A.nr, 1), nc = std::max<int32_t>(Rf.nr, 1);
+  DevMem bv(sizeof(T) * nf), tv(sizeof(T) * nf), rv(sizeof(T) * nf), dv(sizeof(T) * nf);
+  DevMem yc(sizeof(T) * nc), y2c(sizeof(T) * nc), dc(sizeof(T) * nc);
+  for (DevMem *d : {&bv, &tv, &rv, &dv, &yc, &y2c, &dc}) MDP_HIP(hipMemsetAsync(d->get(), 0, d->bytes(), s));
+  DevMem *flush = t_flush;
+  if (flush && !flush->get()) {
+    try {
+      flush->alloc(kFlushBytes);
+      MDP_HIP(hipMemsetAsync(flush->get(), 0, kFlushBytes, s));
+    } catch (const Error &e) {
+      if (e.code != MDP_ENOMEM) throw;
+      (void)hipGetLastError();
+    }
+  }
+  const bool cold = flush && flush->get();
+  const int reps = cold ? kTuneColdReps : kTuneReps;
+  Events ev(2);
+  auto fused = [&] {
+    spmv<kPlainScale>(Rf, dptr<const T>(bv), cnull<T>(), dptr<const T>(dc), dptr<T>(yc), dptr<T>(y2c), Gate{}, s);
+  };
+  auto unfused = [&] {
+    spmv<kResid>(A, dptr<const T>(tv), dptr<const T>(bv), dptr<const T>(dv), dptr<T>(rv), mnull<T>(), Gate{}, s);
+    spmv<kPlainScale>(R, dptr<const T>(rv), cnull<T>(), dptr<const T>(dc), dptr<T>(yc), dptr<T>(y2c), Gate{}, s);
+  };
+  auto time_route = [&](auto &&route) {
+    route();
+    route();
+    float total = 0.f;
+    for (int i = 0; i < reps; ++i) {
+      if (cold) flush_caches(*flush, s);
+      MDP_HIP(hipEventRecord(ev[0], s));
+      route();
+      MDP_HIP(hipEventRecord(ev[1], s));
+      MDP_HIP(hipEventSynchronize(ev[1]));
+      float ms = 0.f;
+      MDP_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      total += ms;
+    }
+    return total / reps;
+  };
+  const float tf = time_route(fused), tu = time_route(unfused);
+  const bool keep_fused = tf <= tu;
+  MDP_HIP(hipStreamSynchronize(s));
+  if (std::getenv("MDP_SETUP_VERBOSE"))
+    std::fprintf(stderr, "[mdp] restriction %s rows=%d: fused %.2f us, residual + R %.2f us -> %s\n",
+                 sizeof(T) == 8 ? "f64" : "f32", rf.nr, 1e3 * tf, 1e3 * tu, keep_fused ? "fused" : "residual + R");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_rtune.emplace(key, keep_fused ? 1 : 0).second) tune_record_restriction(key, keep_fused);
+  return keep_fused;
+}
+
 }  // namespace
 
 void set_tune_file(const char *path) {
@@ -739,6 +829,12 @@ void set_tune_file(const char *path) {
       if (std::sscanf(line, "%d %d %d %d %lld %lld %d %d %d %d %d %d", &k.vsize, &k.nr, &k.nc, &k.maxlen, &nnz,
                       &padded, &dia, &hyb, &sell, &scalar, &lpr, &batch) != 12)
         continue;
+      if ((k.vsize == -4 || k.vsize == -8) && (dia == 0 || dia == 1) && hyb + sell + scalar == 0) {
+        k.nnz = nnz;
+        k.padded = padded;
+        g_rtune[k] = dia;
+        continue;
+      }
       if ((k.vsize != 4 && k.vsize != 8) || dia + hyb + sell + scalar > 1 || !valid_lpr(lpr) ||
           (batch != kCsrBatch && batch != 8))
         continue;
