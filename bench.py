@@ -18,6 +18,10 @@ the library on the launch stream), and the CPU oracle timed on this host.
 Further sections, each with its own set-up outside its clock:
 
 * ``config1``: the 2D 32x32 grid with four full fracture lines, FP64;
+* ``flux``: the headline's four systems in the paper's own block reading
+  (subdomain pressures with explicit intersection lines and points on
+  Omega, interface fluxes on Gamma), FP64 and mixed, with its own roofline
+  pass;
 * ``cube160``: the same cube at 160^3 (4.33M unknowns), FP64 and mixed,
   with its own roofline pass;
 * ``batch``: 256 uneven 2D systems (side uniform in 64..512, 1..20 random
