@@ -63,7 +63,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--n", type=int, default=100, help="host cells per side")
-    p.add_argument("--seeds", type=int, default=1, help="log-normal seeds per (K_par, kappa) pair")
+    p.add_argument("--seeds", type=int, default=3, help="log-normal seeds per (K_par, kappa) pair (headline)")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
     p.add_argument("--restart", type=int, default=64, help="FGMRES restart length (at most 64)")
     p.add_argument("--max-coarse", type=int, default=400,
