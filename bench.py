@@ -93,6 +93,8 @@ def parse():
     p.add_argument("--requests", type=int, default=2000, help="serve mode: requests per arrival rate")
     p.add_argument("--slots", type=int, default=4, help="serve mode: server slots")
     p.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: workspace memory budget")
+    p.add_argument("--serve-grouping", action="store_true",
+                   help="serve mode: solve queued requests of one system together (mdp_server_set_grouping)")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="solve time after which the CPU oracle sample stops taking further systems")
     p.add_argument("--sections", default="config1,flux,cube160,batch,serve",
@@ -671,6 +673,7 @@ def mode_serve(args):
                                      L.MDP_NO_AUTOTUNE if args.no_autotune else 0, args.restart)
     budget = int(args.budget_gb * (1 << 30))
     srv = L.mdp_server_create(budget, args.slots)
+    L.mdp_server_set_grouping(srv, args.serve_grouping)
     for p in pool:
         L.mdp_server_register(srv, p["h"]["mixed"])
     rng = np.random.default_rng(12345)
@@ -755,6 +758,7 @@ def mode_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 preconditioner / f64 outer", "data": "synthetic",
         "config": {"workload": f"serving-pool-{len(pool)}-2d64-512-3d40-160", "slots": args.slots,
+                   "grouping": bool(args.serve_grouping),
                    "budget_gb": args.budget_gb, "requests_per_rate": args.requests,
                    "unknowns_range": [min(p["n"] for p in pool), max(p["n"] for p in pool)]},
         "saturated": {"solves_per_s": round(sat, 2), "p50_ms": _pct(lat_sat, 50), "p99_ms": _pct(lat_sat, 99),

@@ -337,10 +337,30 @@ int mdp_level_aggregates(const mdp_handle *h, int32_t block, int32_t level, int3
  * within mem_budget_bytes together with the workspaces of all registered
  * handles (0 = no bound).  To admit a request the server frees workspaces of
  * idle handles, least recently used first; a request whose workspace alone
- * exceeds the budget runs when no other request is running.  Results do not
- * depend on what else runs: every request executes the kernels of mdp_solve,
- * whose reductions have a fixed order.  Returns EINVAL for bad arguments. */
+ * exceeds the budget runs when no other request is running.  Grouping (off
+ * by default, see mdp_server_set_grouping): the slot that admits a request
+ * also takes every other queued request of the same handle, and solves all
+ * their columns as mdp_solve solves the columns of one call (four at a time
+ * through the handle's four-column batch within its memory budget, the rest
+ * one by one).  Every kernel's reductions have a fixed order, so a column's
+ * result depends only on the columns grouped with it (equal to its solve
+ * alone up to rounding, as for mdp_solve), and without grouping it is bit
+ * for bit the one-column mdp_solve result, whatever else runs.  Returns
+ * EINVAL for bad arguments. */
 int mdp_server_create(size_t mem_budget_bytes, int32_t max_slots, mdp_server **out);
+
+/* Grouping of queued requests of one handle: 1, or 0 (the default: each
+ * request alone, column by column).  Grouping pays once the handles' four-
+ * column batches exist (hot systems of a long-running server): the first
+ * grouped solve of a handle builds its batch inside the serving loop, and
+ * grouped solves on one device take turns on the shared four-column
+ * workspace.  Applies to requests admitted from now on.  EINVAL for NULL or
+ * another value. */
+int mdp_server_set_grouping(mdp_server *srv, int32_t on);
+
+/* Columns solved so far, and how many of them four at a time (either may
+ * be NULL).  EINVAL for NULL. */
+int mdp_server_counts(mdp_server *srv, int64_t *columns, int64_t *grouped);
 
 /* Make a handle servable.  Its hierarchy stays resident in device memory.
  * The handle must outlive the server (destroy the server first). */

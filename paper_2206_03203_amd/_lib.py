@@ -110,6 +110,8 @@ _sig = {
     "mdp_submit": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32, C.POINTER(C.c_uint64)]),
     "mdp_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(mdp_stats)]),
     "mdp_server_destroy": (C.c_int, [_vp]),
+    "mdp_server_set_grouping": (C.c_int, [_vp, C.c_int32]),
+    "mdp_server_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mdp_set_allocator": (C.c_int, [_vp, _vp, _vp]),
     "mdp_tune_file": (C.c_int, [C.c_char_p]),
     "mdp_ktimer_begin": (C.c_int, [C.c_int32]),
@@ -339,6 +341,16 @@ def mdp_poll(srv: int, ticket: int):
     del _inflight[key]
     _check(rc, "mdp_poll", ok=(MDP_OK, MDP_NOT_CONVERGED, MDP_STAGNATED))
     return rc, [s.as_dict() for s in st]
+
+
+def mdp_server_set_grouping(srv: int, on: bool) -> None:
+    _check(lib.mdp_server_set_grouping(srv, 1 if on else 0), "mdp_server_set_grouping")
+
+
+def mdp_server_counts(srv: int) -> dict:
+    c, g = C.c_int64(), C.c_int64()
+    _check(lib.mdp_server_counts(srv, C.byref(c), C.byref(g)), "mdp_server_counts")
+    return {"columns": c.value, "grouped": g.value}
 
 
 def mdp_server_destroy(srv: int) -> None:

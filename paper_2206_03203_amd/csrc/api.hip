@@ -227,6 +227,42 @@ void build_multi_rhs(mdp_handle *h, hipStream_t s) {
   h->rhs4_bytes = bytes;
 }
 
+}  // namespace
+
+int solve_columns(mdp_handle *h, const std::vector<PairIO> &cols, hipStream_t s, mdp_stats *st, bool group,
+                  int64_t *grouped) {
+  const int32_t nrhs = static_cast<int32_t>(cols.size());
+  int worst = MDP_OK;
+  int32_t k = 0;
+  auto fail_rest = [&](int32_t from, int rc) {
+    for (int32_t r = from; r < nrhs; ++r) st[r].status = rc;
+    return rc;
+  };
+  // Four columns at a time run as one batch of the same system, whose
+  // sparse products read each matrix once for all four (the plan is built on
+  // first use and kept with the handle); without room in the plans' budget,
+  // or without device memory for it, the columns are solved one by one.
+  if (group && nrhs >= kMultiRhs && !h->rhs4 && !h->rhs4_failed) build_multi_rhs(h, s);
+  if (group && h->rhs4 && nrhs >= kMultiRhs) {
+    std::lock_guard<std::mutex> use(rhs4_of(h->rhs4_dev).use);
+    for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
+      const std::vector<PairIO> io(cols.begin() + k, cols.begin() + k + kMultiRhs);
+      const int rc = h->rhs4->solve(io, s, st + k);
+      if (grouped) *grouped += kMultiRhs;
+      if (rc < 0) return fail_rest(k + kMultiRhs, rc);
+      if (rc > worst) worst = rc;
+    }
+  }
+  for (; k < nrhs; ++k) {
+    const int rc = h->s.solve(cols[k].b, cols[k].x, s, st + k);
+    if (rc < 0) return fail_rest(k + 1, rc);
+    if (rc > worst) worst = rc;
+  }
+  return worst;
+}
+
+namespace {
+
 // h's plan is going: its bytes leave the budget, and the device's shared
 // workspace goes with the last plan there.
 void drop_multi_rhs(mdp_handle *h) {
@@ -455,35 +491,13 @@ int mdp_solve(mdp_handle *h, const double *b, double *x, int32_t nrhs, int64_t l
     set_last_error("handle was set up host-only");
     return MDP_EINVAL;
   }
-  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int worst = MDP_OK;
-  int32_t k = 0;
-  // Four columns at a time run as one batch of the same system, whose
-  // sparse products read each matrix once for all four (the plan is built on
-  // first use and kept with the handle); without room in the plans' budget,
-  // or without device memory for it, the columns are solved one by one.
-  if (nrhs >= kMultiRhs && !h->rhs4 && !h->rhs4_failed) build_multi_rhs(h, s);
-  if (h->rhs4) {
-    std::lock_guard<std::mutex> use(rhs4_of(h->rhs4_dev).use);
-    for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
-      std::vector<PairIO> io;
-      for (int r = 0; r < kMultiRhs; ++r) io.push_back(PairIO{b + (k + r) * ld, x + (k + r) * ld});
-      mdp_stats st[kMultiRhs] = {};
-      const int rc = h->rhs4->solve(io, s, st);
-      if (stats)
-        for (int r = 0; r < kMultiRhs; ++r) stats[k + r] = st[r];
-      if (rc < 0) return rc;
-      if (rc > worst) worst = rc;
-    }
-  }
-  for (; k < nrhs; ++k) {
-    mdp_stats st{};
-    const int rc = h->s.solve(b + k * ld, x + k * ld, s, &st);
-    if (stats) stats[k] = st;
-    if (rc < 0) return rc;
-    if (rc > worst) worst = rc;
-  }
-  return worst;
+  std::vector<PairIO> cols;
+  for (int32_t k = 0; k < nrhs; ++k) cols.push_back(PairIO{b + k * ld, x + k * ld});
+  std::vector<mdp_stats> st(static_cast<size_t>(nrhs));
+  const int rc = solve_columns(h, cols, static_cast<hipStream_t>(hip_stream), st.data(), true);
+  if (stats)
+    for (int32_t k = 0; k < nrhs; ++k) stats[k] = st[k];
+  return rc;
   API_END
 }
 

@@ -4,9 +4,13 @@
 // slot is free, its system is not already being solved by another slot, and
 // the Krylov workspace it needs fits the memory budget (workspaces of idle
 // systems are released, least recently used first, to make room).  Work of
-// different slots runs concurrently on the device.  Every request runs the
-// same kernels as mdp_solve, whose reductions have a fixed order, so a result
-// does not depend on what else is in flight.
+// different slots runs concurrently on the device.  With grouping on (off by
+// default), the slot that takes a request also takes every other queued
+// request of the same system, and their columns run four at a time through
+// the system's four-column batch (shared matrix reads), the rest one by one.
+// Every kernel's reductions have a fixed order, so a column's result depends
+// only on the columns it was grouped with: without grouping it does not
+// depend on what else is in flight at all.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -52,6 +56,9 @@ constexpr size_t kMaxQueue = 1 << 20;
 struct mdp_server {
   size_t budget = 0;  // bytes of Krylov workspace allowed at once (0 = no bound)
   int slots = 1;
+  bool group = false;       // gather queued requests of one system (under mu)
+  int64_t columns = 0;      // columns solved (under mu)
+  int64_t grouped = 0;      // of which four at a time
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
@@ -104,38 +111,65 @@ struct mdp_server {
         continue;
       }
       mdp_handle *h = r->h;
+      // the requests solved together: r, and with grouping every other
+      // queued request of the same system, in arrival order
+      std::vector<Request *> group_reqs{r};
+      if (group)
+        for (auto it = queue.begin(); it != queue.end();)
+          if ((*it)->h == h) {
+            group_reqs.push_back(*it);
+            it = queue.erase(it);
+          } else {
+            ++it;
+          }
+      const bool grouping = group;
       busy.insert(h);
       lru.remove(h);
       const size_t before = ws_of(h);
       ++running;
       lk.unlock();
-      int worst = MDP_OK;
+      std::vector<PairIO> cols;
+      for (Request *q : group_reqs)
+        for (int32_t k = 0; k < q->nrhs; ++k)
+          cols.push_back(PairIO{q->b + static_cast<int64_t>(k) * h->s.n, q->x + static_cast<int64_t>(k) * h->s.n});
+      std::vector<mdp_stats> st(cols.size());
+      int64_t n_grouped = 0;
+      int fail = MDP_OK;
+      std::string msg;
       try {
         if (!s) MDP_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         h->s.ensure_workspace(s);
-        for (int32_t k = 0; k < r->nrhs; ++k) {
-          const int rc = h->s.solve(r->b + static_cast<int64_t>(k) * h->s.n, r->x + static_cast<int64_t>(k) * h->s.n,
-                                    s, &r->stats[k]);
-          if (rc < 0) {
-            worst = rc;
-            break;
-          }
-          if (rc > worst) worst = rc;
-        }
+        solve_columns(h, cols, s, st.data(), grouping, &n_grouped);
       } catch (const Error &e) {
-        worst = e.code;
-        r->msg = e.msg;
+        fail = e.code;
+        msg = e.msg;
       } catch (...) {
-        worst = MDP_EHIP;
-        r->msg = "unexpected failure in a server slot";
+        fail = MDP_EHIP;
+        msg = "unexpected failure in a server slot";
       }
       lk.lock();
       ws_bytes += ws_of(h) - before;
       --running;
       busy.erase(h);
       lru.push_back(h);
-      r->rc = worst;
-      r->done = true;
+      columns += static_cast<int64_t>(cols.size());
+      grouped += n_grouped;
+      size_t c = 0;
+      for (Request *q : group_reqs) {
+        int worst = MDP_OK;
+        for (int32_t k = 0; k < q->nrhs; ++k, ++c) {
+          q->stats[k] = st[c];
+          const int rc = fail != MDP_OK ? fail : st[c].status;
+          if (rc < 0) {
+            if (worst >= 0 || rc < worst) worst = rc;
+          } else if (worst >= 0 && rc > worst) {
+            worst = rc;
+          }
+        }
+        q->rc = worst;
+        if (worst < 0) q->msg = fail != MDP_OK ? msg : "a column of this request failed";
+        q->done = true;
+      }
       cv_done.notify_all();
       cv_work.notify_all();
     }
@@ -167,6 +201,27 @@ int mdp_server_create(size_t mem_budget_bytes, int32_t max_slots, mdp_server **o
     return MDP_EINVAL;
   }
   *out = srv.release();
+  return MDP_OK;
+}
+
+int mdp_server_set_grouping(mdp_server *srv, int32_t on) {
+  if (!srv || (on != 0 && on != 1)) {
+    set_last_error("NULL server or grouping not 0 / 1");
+    return MDP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->group = on != 0;
+  return MDP_OK;
+}
+
+int mdp_server_counts(mdp_server *srv, int64_t *columns, int64_t *grouped) {
+  if (!srv) {
+    set_last_error("NULL server");
+    return MDP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (columns) *columns = srv->columns;
+  if (grouped) *grouped = srv->grouped;
   return MDP_OK;
 }
 

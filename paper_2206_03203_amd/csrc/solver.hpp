@@ -237,6 +237,20 @@ void set_tune_file(const char *path);
 
 }  // namespace mdp
 
+struct mdp_handle;
+
+namespace mdp {
+
+// Solve the columns of one system (st: one entry per column), four at a
+// time through the handle's four-column batch when `group` is set and the
+// batch fits its budget, the rest one by one; returns the most severe code.
+// After an error the columns not solved carry that code.  *grouped (may be
+// NULL) counts the columns solved four at a time.
+int solve_columns(mdp_handle *h, const std::vector<PairIO> &cols, hipStream_t s, mdp_stats *st, bool group,
+                  int64_t *grouped = nullptr);
+
+}  // namespace mdp
+
 struct mdp_handle {
   mdp::Solver s;
   // mdp_solve with four or more columns: the same system as a batch of

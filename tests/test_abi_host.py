@@ -262,6 +262,12 @@ def test_server_lifecycle_without_device_work():
         t = ctypes.c_uint64()
         assert L.lib.mdp_submit(srv, h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, ctypes.byref(t)) == L.MDP_EINVAL
         assert L.lib.mdp_poll(srv, 1, None) == L.MDP_EINVAL
+        L.mdp_server_set_grouping(srv, False)
+        L.mdp_server_set_grouping(srv, True)
+        assert L.lib.mdp_server_set_grouping(srv, 2) == L.MDP_EINVAL
+        assert L.lib.mdp_server_set_grouping(None, 1) == L.MDP_EINVAL
+        assert L.mdp_server_counts(srv) == {"columns": 0, "grouped": 0}
+        assert L.lib.mdp_server_counts(None, None, None) == L.MDP_EINVAL
     finally:
         L.mdp_destroy(h)
         L.mdp_server_destroy(srv)
