@@ -78,9 +78,10 @@ extern "C" {
                               kept with the handle (its Krylov directions
                               widen to FP64 too); stats report fallback = 1,
                               the iterations and cycles of both attempts and
-                              the status of the second.  Columns solved one at
-                              a time only: batches and four-column groups
-                              report the mixed result. */
+                              the status of the second.  mdp_solve's four-
+                              column groups re-solve their failed columns one
+                              by one; mdp_solve_batch reports the mixed
+                              result. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,

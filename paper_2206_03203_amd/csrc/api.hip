@@ -247,8 +247,28 @@ int solve_columns(mdp_handle *h, const std::vector<PairIO> &cols, hipStream_t s,
     std::lock_guard<std::mutex> use(rhs4_of(h->rhs4_dev).use);
     for (; k + kMultiRhs <= nrhs; k += kMultiRhs) {
       const std::vector<PairIO> io(cols.begin() + k, cols.begin() + k + kMultiRhs);
-      const int rc = h->rhs4->solve(io, s, st + k);
+      int rc = h->rhs4->solve(io, s, st + k);
       if (grouped) *grouped += kMultiRhs;
+      if ((h->s.opt.flags & MDP_FALLBACK_FP64) && h->s.opt.precision == MDP_MIXED) {
+        // MDP_FALLBACK_FP64: columns of the group that produced a NaN/Inf or
+        // stagnated are solved again, one by one, in FP64
+        rc = MDP_OK;
+        for (int r = 0; r < kMultiRhs; ++r) {
+          mdp_stats &c = st[k + r];
+          if (c.status == MDP_ENAN || c.status == MDP_STAGNATED) {
+            mdp_stats again{};
+            h->s.solve(cols[k + r].b, cols[k + r].x, s, &again, true);
+            again.iters += c.iters;
+            again.restarts += c.restarts + 1;
+            c = again;
+          }
+          if (c.status < 0) {
+            if (rc >= 0 || c.status < rc) rc = c.status;
+          } else if (rc >= 0 && c.status > rc) {
+            rc = c.status;
+          }
+        }
+      }
       if (rc < 0) return fail_rest(k + kMultiRhs, rc);
       if (rc > worst) worst = rc;
     }

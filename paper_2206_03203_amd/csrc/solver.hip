@@ -1621,7 +1621,7 @@ void Solver::upload(hipStream_t s) {
   on_device = true;
 }
 
-int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
+int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st, bool fp64_only) {
   const Range range("mdp_solve");
   const auto t0 = std::chrono::steady_clock::now();
   ensure_workspace(s);
@@ -1647,7 +1647,13 @@ int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st) {
   }
   mdp_stats out{};
   int rc;
-  if (opt.precision == MDP_MIXED) {
+  if (opt.precision == MDP_MIXED && fp64_only) {
+    // a column whose mixed solve failed elsewhere (a four-column group)
+    ensure_fp64(s);
+    Problem<double> p64{&A, pc64.get(), &layout, &ws, &opt, &ws.graphs64};
+    rc = fgmres<double>(p64, bp, xp, false, s, &out);
+    out.fallback = 1;
+  } else if (opt.precision == MDP_MIXED) {
     Problem<float> pb{&A, pc32.get(), &layout, &ws, &opt, &ws.graphs};
     int retry = 0;
     rc = fgmres<float>(pb, bp, xp, use_x0, s, &out, &retry);

@@ -195,7 +195,9 @@ struct Solver {
   void upload(hipStream_t s);
   void ensure_workspace(hipStream_t s);  // (re)allocate the Krylov workspace if released
   size_t workspace_bytes_needed() const;
-  int solve(const double *b, double *x, hipStream_t s, mdp_stats *st);
+  // fp64_only: solve from zero with the FP64 preconditioner at once (the
+  // fallback of a mixed column whose four-column solve failed)
+  int solve(const double *b, double *x, hipStream_t s, mdp_stats *st, bool fp64_only = false);
   // MDP_FALLBACK_FP64: the FP64 preconditioner (built from the kept host
   // hierarchy) and a workspace wide enough for FP64 directions
   void ensure_fp64(hipStream_t s);

@@ -144,3 +144,25 @@ def test_fallback_flag_is_inert_when_nothing_fails(system):
         finally:
             s0.close()
             s1.close()
+
+
+def test_four_column_group_falls_back_column_by_column(system):
+    """mdp_solve with four columns runs them as one group; with matrix values
+    beyond FP32's range every column fails in mixed precision and is solved
+    again in FP64: converged, fallback = 1, the oracle's solution (scaled
+    right-hand sides give scaled solutions)."""
+    A, b = system["A"] * BEYOND_FP32, system["b"] * BEYOND_FP32
+    say("[failure] four-column group with fallback")
+    s = Solver(A, system["part"], precision="mixed", flags=L.MDP_FALLBACK_FP64)
+    try:
+        B = dev(np.stack([b * (k + 1) for k in range(4)]))
+        X = torch.zeros_like(B)
+        rc, st = L.mdp_solve(s.handle, B, X, None, ok=ANY)
+        say(f"[failure] group stats {[(c['status'], c['iters'], c['fallback']) for c in st]}")
+        assert rc == L.MDP_OK
+        assert L.mdp_multi_rhs_memory(s.handle)["plan_bytes"] > 0  # the four columns ran as one group
+        for k in range(4):
+            assert st[k]["converged"] == 1 and st[k]["fallback"] == 1
+            assert relerr(host(X[k]), (k + 1) * system["x"]) <= 1e-6
+    finally:
+        s.close()
