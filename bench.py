@@ -51,6 +51,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PAIRS = [(1e-4, 1e-4), (1e-4, 1e4), (1e4, 1e-4), (1e4, 1e4)]
+DEFAULT_SEEDS = 3  # log-normal host permeability seeds 0, 1, 2 per pair: twelve headline systems
 
 
 def log(*a):
@@ -63,7 +64,8 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--n", type=int, default=100, help="host cells per side")
-    p.add_argument("--seeds", type=int, default=3, help="log-normal seeds per (K_par, kappa) pair (headline)")
+    p.add_argument("--seeds", type=int, default=DEFAULT_SEEDS,
+                   help="log-normal seeds per (K_par, kappa) pair (headline)")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
     p.add_argument("--restart", type=int, default=64, help="FGMRES restart length (at most 64)")
     p.add_argument("--max-coarse", type=int, default=400,
@@ -290,21 +292,22 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
     # the columns four at a time with each matrix read once for all four,
     # against the same columns solved one at a time.
     multi_rhs = {}
+    mr_systems = systems[:len(PAIRS)]  # the first seed's four systems
     if headline and args.block == "lower" and args.multi_rhs and formulation == "pressure":
-        for s in systems:
+        for s in mr_systems:
             fs = [None] + [synth.host_sources(s["sc"], 100 + k) for k in range(3)]
             _, B, _ = tpfa.assemble(s["sc"], sources=fs)
             s["B4"] = torch.tensor(np.ascontiguousarray(B.T), dtype=torch.float64, device=dev)
         nr = args.multi_rhs
         for prec in ("fp64", "mixed"):
-            xs = [torch.zeros_like(s["B4"]) for s in systems]
-            for s, x in zip(systems, xs):
+            xs = [torch.zeros_like(s["B4"]) for s in mr_systems]
+            for s, x in zip(mr_systems, xs):
                 L.mdp_solve(s["h"][prec], s["B4"], x, stream)  # builds the four-column plan (untimed)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             its = []
             for _ in range(nr):
-                for s, x in zip(systems, xs):
+                for s, x in zip(mr_systems, xs):
                     rc, st = L.mdp_solve(s["h"][prec], s["B4"], x, stream)
                     if rc != L.MDP_OK:
                         raise RuntimeError(f"{s['name']} {prec} four-column solve did not converge")
@@ -314,14 +317,14 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
             t0 = time.perf_counter()
             its1 = []
             for _ in range(nr):
-                for s, x in zip(systems, xs):
+                for s, x in zip(mr_systems, xs):
                     for k in range(s["B4"].shape[0]):
                         rc, st = L.mdp_solve(s["h"][prec], s["B4"][k], x[k], stream)
                         its1.append(st[0]["iters"])
             torch.cuda.synchronize()
             dt1 = time.perf_counter() - t0
-            ns = nr * sum(s["B4"].shape[0] for s in systems)
-            mem = [L.mdp_multi_rhs_memory(s["h"][prec]) for s in systems]
+            ns = nr * sum(s["B4"].shape[0] for s in mr_systems)
+            mem = [L.mdp_multi_rhs_memory(s["h"][prec]) for s in mr_systems]
             multi_rhs[prec] = {"value": round(ns / dt4, 3), "unit": "solves/s",
                                "one_column_at_a_time": round(ns / dt1, 3),
                                "speedup": round(dt1 / dt4, 3), "solves": ns,
@@ -333,8 +336,8 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
                                "budget_gb": round(mem[-1]["budget"] / 1e9, 3)}
             log(f"[bench] four right-hand sides {prec}: {ns} solves in {dt4:.3f}s "
                 f"(one column at a time {dt1:.3f}s)")
-        multi_rhs["what"] = ("each system with four right-hand sides (Dirichlet data alone and with three "
-                             "uniform host source fields) in one mdp_solve call")
+        multi_rhs["what"] = ("the four systems of seed 0, each with four right-hand sides (Dirichlet data "
+                             "alone and with three uniform host source fields) in one mdp_solve call")
 
     # Roofline: the same FP64 steps again, with HIP events recorded by the
     # library around every launch of each kernel class on its launch stream
@@ -342,7 +345,7 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
     # between kernels, not the kernels).
     roofline, classes = roofline_pass(lambda: run("fp64", steps), args.kernel_class,
                                       f"the {steps} FP64 steps repeated", fp["seconds"])
-    if roofline["kernel_symbol"] and args.seeds == 1 and args.vcycles == 1 and args.block == "lower" and \
+    if roofline["kernel_symbol"] and args.seeds == DEFAULT_SEEDS and args.vcycles == 1 and args.block == "lower" and \
             args.max_coarse == 400 and args.restart == 64 and formulation == "pressure" and args.smoother == "l1jacobi":
         roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}")
 

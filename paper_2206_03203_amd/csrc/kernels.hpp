@@ -555,53 +555,6 @@ __global__ __launch_bounds__(kThreads) void dense_gemv_batched_kernel(const Dens
   if (lane == 0) x[d.row + row] = static_cast<T>(s);
 }
 
-// The same coarsest solve for kMultiRhs right-hand-side blocks at once, as
-// the small dense product X = A_c^-1 B (n x n times n x 4) on the FP64
-// matrix cores: one wavefront per 16 output rows of one system, 16x16x4
-// FP64 MFMA steps over k, with the four blocks as the first four of the 16
-// product columns.  Lane l feeds row l % 16 of the tile and the four
-// consecutive k of its row that group l / 16 covers (a 32-byte load of the
-// row-major inverse); the k order inside a step only has to agree between
-// the two operands.  Output: component q of lane l holds row l / 16 + 4 q of
-// the tile in column l % 16 (the layout measured on gfx950).  Block r of x
-// and b starts r * bstride further on.
-typedef double MfmaF64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-__global__ __launch_bounds__(64) void dense_gemm4_mfma_kernel(const DenseDesc *__restrict__ desc,
-                                                              const double *__restrict__ ainv,
-                                                              const T *__restrict__ b, T *__restrict__ x,
-                                                              int64_t bstride, const int *__restrict__ gate) {
-  if (gate && *gate) return;
-  const DenseDesc d = desc[blockIdx.y];
-  const int r0 = static_cast<int>(blockIdx.x) * 16;
-  if (r0 >= d.n) return;  // the whole wavefront leaves together
-  const int lane = static_cast<int>(threadIdx.x);
-  const int i = lane % 16, g = lane / 16;
-  const int row = r0 + i;
-  const double *arow = ainv + d.inv_off + static_cast<int64_t>(row < d.n ? row : d.n - 1) * d.n;
-  const T *bj = b + static_cast<int64_t>(i < kMultiRhs ? i : 0) * bstride + d.row;
-  MfmaF64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < d.n; k0 += 16) {
-    double av[4], bv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = k0 + 4 * g + t;
-      const bool in = k < d.n;
-      av[t] = in && row < d.n ? arow[k] : 0.0;
-      bv[t] = in && i < kMultiRhs ? static_cast<double>(bj[k]) : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
-  }
-  if (i < kMultiRhs)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int orow = r0 + g + 4 * q;
-      if (orow < d.n) x[static_cast<int64_t>(i) * bstride + d.row + orow] = static_cast<T>(acc[q]);
-    }
-}
-
 // Batched gather / scatter between the callers' vectors (one device pointer
 // per pair, caller order) and the global layout.
 __global__ __launch_bounds__(kThreads) void gather_pairs_kernel(int64_t n, const int *__restrict__ gpair,

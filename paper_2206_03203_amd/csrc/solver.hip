@@ -326,7 +326,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     const size_t nfull = static_cast<size_t>(kb) * dl.n;
     std::vector<Piece> pa, pp, pr, pr_plain, psw;
     std::vector<T> dinv(nfull);
-    std::vector<DenseDesc> desc, desc4;  // per block; per system (kMultiRhs blocks)
+    std::vector<DenseDesc> desc;
     // the level restricts b with R (I - A D^-1) when every continuing system
     // has it and the pre-smoothing is the single l1-Jacobi sweep from zero D^-1 b
     dl.fused = dl.ncont > 0 && pre == 1 && !gs;
@@ -346,7 +346,6 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
       } else if (h.dense) {
         for (int r = 0; r < kb; ++r)
           desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
-        desc4.push_back(DenseDesc{o, hl.A.nr, static_cast<int64_t>(cinv.size())});
         cinv.insert(cinv.end(), h.coarse_inv.begin(), h.coarse_inv.end());
         dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
       } else {
@@ -411,10 +410,6 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     upload_csr(concat_blocks(dl.n - dl.sw_off, dl.n - dl.sw_off, psw), dl.Asw, s, keep);
     dl.ndense = static_cast<int32_t>(desc.size());
     upload_vec(dl.dense, keep.put(std::move(desc)), s);
-    if (kb == kMultiRhs && !desc4.empty()) {
-      dl.ndense4 = static_cast<int32_t>(desc4.size());
-      upload_vec(dl.dense4, keep.put(std::move(desc4)), s);
-    }
     upload_vec(dl.dinv, keep.put(std::move(dinv)), s);
     const size_t nb = std::max<size_t>(nfull, 1) * sizeof(T);
     dl.x.alloc(nb);
@@ -881,14 +876,7 @@ void start_smoother(DHier<T> &H, const T *b, Gate gate, hipStream_t s) {
 // from zero (the first, D^-1 b, is already in t).
 template <typename T>
 void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, Gate gate, hipStream_t s) {
-  if (H.kb == kMultiRhs && L.ndense4 > 0) {
-    // the kMultiRhs blocks of each system as one small matrix product
-    const dim3 grid((L.max_dense_n + 15) / 16, L.ndense4);
-    timed_launch(kKcVcycleOther, s, 0.0, [&] {
-      hipLaunchKernelGGL(dense_gemm4_mfma_kernel<T>, grid, dim3(64), 0, s, dptr<const DenseDesc>(L.dense4),
-                         dptr<const double>(H.cinv), b, x, static_cast<int64_t>(L.n), gate.all);
-    });
-  } else if (L.ndense > 0) {
+  if (L.ndense > 0) {
     const dim3 grid((L.max_dense_n + (kThreads / 64) - 1) / (kThreads / 64), L.ndense);
     timed_launch(kKcVcycleOther, s, 0.0, [&] {
       hipLaunchKernelGGL(dense_gemv_batched_kernel<T>, grid, dim3(kThreads), 0, s, dptr<const DenseDesc>(L.dense),

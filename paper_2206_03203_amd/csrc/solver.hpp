@@ -66,8 +66,6 @@ struct DLevel {
   DevMem dinv;      // n entries: 1 / sum_j |a_ij|
   int32_t ndense = 0, max_dense_n = 0;
   DevMem dense;     // DenseDesc[ndense]
-  int32_t ndense4 = 0;
-  DevMem dense4;    // kMultiRhs blocks: one DenseDesc per system (block 0's rows)
   int32_t sw_off = 0;
   DCsr<T> Asw;      // swept coarsest systems, indices relative to sw_off
   DevMem x, b, t, r;  // unknown, right-hand side, smoothing iterate, residual (and sweep ping-pong)
