@@ -79,9 +79,9 @@ extern "C" {
                               widen to FP64 too); stats report fallback = 1,
                               the iterations and cycles of both attempts and
                               the status of the second.  mdp_solve's four-
-                              column groups re-solve their failed columns one
-                              by one; mdp_solve_batch reports the mixed
-                              result. */
+                              column groups and mdp_solve_batch re-solve their
+                              failed columns one by one, each with its own
+                              handle's flag. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,

@@ -529,6 +529,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     return MDP_EINVAL;
   }
   std::vector<const Solver *> pairs;
+  std::vector<mdp_handle *> pair_h;  // the handle of every pair (for the FP64 fallback)
   std::vector<PairIO> io;
   for (int32_t i = 0; i < nsys; ++i) {
     if (!hs[i] || nrhs[i] < 0 || (nrhs[i] > 0 && (!b[i] || !x[i]))) {  // no vectors needed for nrhs 0
@@ -551,6 +552,7 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     }
     for (int32_t k = 0; k < nrhs[i]; ++k) {
       pairs.push_back(&si);
+      pair_h.push_back(hs[i]);
       io.push_back(PairIO{b[i] + static_cast<int64_t>(k) * si.n, x[i] + static_cast<int64_t>(k) * si.n});
     }
   }
@@ -615,17 +617,42 @@ int mdp_solve_batch(mdp_handle *const *hs, int32_t nsys, const double *const *b,
     g_batch = std::move(bc);
   }
   int worst = MDP_OK;
-  for (size_t c = 0; c < g_batch->chunks.size(); ++c) {
-    Batch &bt = *g_batch->chunks[c];
-    const int p0 = g_batch->first_pair[c];
-    const std::vector<PairIO> sub(io.begin() + p0, io.begin() + p0 + bt.npairs);
-    const int rc = bt.solve(sub, s, stats ? stats + p0 : nullptr);
+  auto fold = [&](int rc) {
     if (rc < 0) {
       if (worst >= 0 || rc < worst) worst = rc;
     } else if (worst >= 0 && rc > worst) {
       worst = rc;
     }
+  };
+  std::vector<mdp_stats> st(pairs.size());
+  for (size_t c = 0; c < g_batch->chunks.size(); ++c) {
+    Batch &bt = *g_batch->chunks[c];
+    const int p0 = g_batch->first_pair[c];
+    const std::vector<PairIO> sub(io.begin() + p0, io.begin() + p0 + bt.npairs);
+    const int rc = bt.solve(sub, s, st.data() + p0);
+    if (rc >= 0 || rc == MDP_ENAN) {
+      // MDP_FALLBACK_FP64 (mixed): pairs that produced a NaN/Inf or
+      // stagnated are solved again, one by one, with their handle's FP64
+      // preconditioner
+      for (int q = p0; q < p0 + bt.npairs; ++q) {
+        mdp_stats &cs = st[q];
+        Solver &sv = pair_h[q]->s;
+        if ((cs.status == MDP_ENAN || cs.status == MDP_STAGNATED) && sv.opt.precision == MDP_MIXED &&
+            (sv.opt.flags & MDP_FALLBACK_FP64)) {
+          mdp_stats again{};
+          sv.solve(io[q].b, io[q].x, s, &again, true);
+          again.iters += cs.iters;
+          again.restarts += cs.restarts + 1;
+          cs = again;
+        }
+        fold(cs.status);
+      }
+    } else {
+      fold(rc);
+    }
   }
+  if (stats)
+    for (size_t q = 0; q < st.size(); ++q) stats[q] = st[q];
   return worst;
   API_END
 }

@@ -166,3 +166,26 @@ def test_four_column_group_falls_back_column_by_column(system):
             assert relerr(host(X[k]), (k + 1) * system["x"]) <= 1e-6
     finally:
         s.close()
+
+
+def test_batch_pairs_fall_back_one_by_one(system):
+    """mdp_solve_batch in mixed precision on matrices beyond FP32's range:
+    every pair fails in the batch and, with MDP_FALLBACK_FP64 on its handle,
+    is solved again in FP64; a handle without the flag keeps MDP_ENAN."""
+    A, b = system["A"] * BEYOND_FP32, system["b"] * BEYOND_FP32
+    say("[failure] batch pairs with fallback")
+    ss = [Solver(A, system["part"], precision="mixed", flags=L.MDP_FALLBACK_FP64) for _ in range(2)]
+    plain = Solver(A, system["part"], precision="mixed")
+    try:
+        bs = [dev(b), dev(2.0 * b), dev(b)]
+        xs = [torch.zeros_like(t) for t in bs]
+        rc, st = L.mdp_solve_batch([ss[0].handle, ss[1].handle, plain.handle], bs, xs, None, ok=ANY)
+        say(f"[failure] batch stats {[(c['status'], c['iters'], c['fallback']) for c in st]}")
+        assert rc == L.MDP_ENAN
+        for k in range(2):
+            assert st[k]["converged"] == 1 and st[k]["fallback"] == 1 and st[k]["status"] == L.MDP_OK
+            assert relerr(host(xs[k]), (k + 1) * system["x"]) <= 1e-6
+        assert st[2]["status"] == L.MDP_ENAN and st[2]["fallback"] == 0
+    finally:
+        for s in ss + [plain]:
+            s.close()
