@@ -305,6 +305,15 @@ int mdp_apply_noalloc(mdp_handle *h, int32_t op, const double *x_dev, double *y_
 int mdp_info(const mdp_handle *h, int32_t *n, int32_t *n_omega, int32_t *n_gamma,
              int32_t *levels_omega, int32_t *levels_gamma);
 
+/* Residual history of the handle's last one-column solve (an mdp_solve
+ * column solved alone or a served request; not four-column groups or
+ * batches): the Arnoldi estimate |g_{k+1}| / ||b|| after each iteration, in
+ * order across restarts (after a MDP_FALLBACK_FP64 re-solve, of the FP64
+ * attempt).  *count (may be NULL) receives the number of iterations; the
+ * first min(cap, count) values are copied to out (host memory).  EINVAL for
+ * NULL h, cap < 0, or cap > 0 with NULL out. */
+int mdp_residual_history(const mdp_handle *h, double *out, int32_t cap, int32_t *count);
+
 /* Device memory of mdp_solve's four-column batches (any pointer may be
  * NULL): the bytes h's batch holds (0 before its first four-column solve or
  * when it did not fit), the bytes of the shared four-column Krylov workspace

@@ -100,6 +100,7 @@ _sig = {
     "mdp_apply_noalloc": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp]),
     "mdp_info": (C.c_int, [_vp, _ip, _ip, _ip, _ip, _ip]),
     "mdp_multi_rhs_memory": (C.c_int, [_vp] + [C.POINTER(C.c_int64)] * 4),
+    "mdp_residual_history": (C.c_int, [_vp, C.POINTER(C.c_double), C.c_int32, _ip]),
     "mdp_level_shape": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_int64)]),
     "mdp_level_export": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, C.POINTER(C.c_double)]),
     "mdp_level_aggregates": (C.c_int, [_vp, C.c_int32, C.c_int32, _ip]),
@@ -263,6 +264,16 @@ def mdp_info(h: int) -> dict:
     v = [C.c_int32() for _ in range(5)]
     _check(lib.mdp_info(h, *[C.byref(x) for x in v]), "mdp_info")
     return dict(zip(["n", "n_omega", "n_gamma", "levels_omega", "levels_gamma"], [x.value for x in v]))
+
+
+def mdp_residual_history(h: int) -> np.ndarray:
+    """|g_{k+1}| / ||b|| after each iteration of the handle's last one-column solve."""
+    n = C.c_int32()
+    _check(lib.mdp_residual_history(h, None, 0, C.byref(n)), "mdp_residual_history")
+    out = np.zeros(max(n.value, 1), dtype=np.float64)
+    _check(lib.mdp_residual_history(h, out.ctypes.data_as(C.POINTER(C.c_double)), n.value, None),
+           "mdp_residual_history")
+    return out[: n.value]
 
 
 def mdp_multi_rhs_memory(h: int) -> dict:

@@ -484,6 +484,20 @@ int mdp_destroy(mdp_handle *h) {
   API_END
 }
 
+int mdp_residual_history(const mdp_handle *h, double *out, int32_t cap, int32_t *count) {
+  API_BEGIN
+  if (!h || cap < 0 || (cap > 0 && !out)) {
+    set_last_error("bad history arguments");
+    return MDP_EINVAL;
+  }
+  const std::vector<double> &hist = h->s.ws.history;
+  if (count) *count = static_cast<int32_t>(hist.size());
+  const size_t n = std::min(hist.size(), static_cast<size_t>(cap));
+  std::copy(hist.begin(), hist.begin() + static_cast<std::ptrdiff_t>(n), out);
+  return MDP_OK;
+  API_END
+}
+
 int mdp_multi_rhs_memory(const mdp_handle *h, int64_t *plan_bytes, int64_t *shared_bytes, int64_t *held,
                          int64_t *budget) {
   API_BEGIN

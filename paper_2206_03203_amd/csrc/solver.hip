@@ -1199,6 +1199,7 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
   const Tile *tiles = dptr<const Tile>(L.tiles);
 
   std::vector<double> bnorm(np), tol(np), beta(np), est(np, 0.0), scale0(np, 1.0);
+  if (np == 1) ws.history.clear();
   std::vector<int> iters(np, 0), cycles(np, 0), code(np, MDP_OK), active(np, 0), kmax_h(np, 0), stall(np, 0);
   if (retry) std::fill(retry, retry + np, 0);
   pair_norms(ws, L, bg, s);
@@ -1361,6 +1362,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
     }
     MDP_HIP(hipGetLastError());
     MDP_HIP(hipMemcpyAsync(ws.host_state, dst, sizeof(GmresState) * np, hipMemcpyDeviceToHost, s));
+    if (np == 1)  // this cycle's residual estimates, read after the synchronisation below
+      MDP_HIP(hipMemcpyAsync(ws.host_hist, ws.hist.get(), sizeof(double) * m, hipMemcpyDeviceToHost, s));
     hipLaunchKernelGGL(backsolve_kernel, dim3(np), dim3(64), 0, s, static_cast<const GmresState *>(dst),
                        dptr<const double>(ws.Hr), m + 1, m, dptr<const double>(ws.g), dptr<double>(ws.y), ws.ldv);
     timed_launch(kKcOther, s, 16.0 * n, [&] {
@@ -1399,6 +1402,8 @@ int fgmres(Problem<T> &pb, const double *bg, double *xg, bool use_x0, hipStream_
       iters[p] += gs.k;
       est[p] = gs.est;
       ++cycles[p];
+      if (np == 1 && bnorm[p] > 0.0)
+        for (int i = 0; i < gs.k && i < m; ++i) ws.history.push_back(ws.host_hist[i] / bnorm[p]);
       const double b_new = ws.host_norms[p];
       if (code[p] == MDP_OK && b_new > tol[p] && iters[p] < opt.max_iter) {
         if (b_new > (1.0 - kStallFraction) * beta[p])
@@ -1512,6 +1517,7 @@ void Workspace::alloc(int64_t n, int m_, int np, int nt, size_t tsz_, hipStream_
   MDP_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&host_ctl_dev), host_ctl, 0));
   MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_state), np * sizeof(GmresState), hipHostMallocDefault));
   MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_norms), np * sizeof(double), hipHostMallocDefault));
+  MDP_HIP(hipHostMalloc(reinterpret_cast<void **>(&host_hist), (m + 2) * sizeof(double), hipHostMallocDefault));
   ev.resize(static_cast<size_t>(m) + 2);
   for (auto &e : ev) MDP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   MDP_HIP(hipStreamSynchronize(s));
@@ -1546,6 +1552,8 @@ void Workspace::release() {
   if (host_ctl) (void)hipHostFree(host_ctl);
   if (host_state) (void)hipHostFree(host_state);
   if (host_norms) (void)hipHostFree(host_norms);
+  if (host_hist) (void)hipHostFree(host_hist);
+  host_hist = nullptr;
   host_ctl = nullptr;
   host_ctl_dev = nullptr;
   host_state = nullptr;

@@ -155,6 +155,8 @@ struct Workspace {
   BatchCtl *host_ctl_dev = nullptr;  // its device address
   GmresState *host_state = nullptr;  // pinned, npairs
   double *host_norms = nullptr;      // pinned, npairs
+  double *host_hist = nullptr;       // pinned, m: a cycle's residual estimates (single-pair solves)
+  std::vector<double> history;       // |g_{k+1}| / ||b|| per iteration of the last single-pair solve
   std::vector<hipEvent_t> ev;
   StepGraphs graphs;               // single-system solves on this workspace (MDP_GRAPHS)
   StepGraphs graphs64;             // the FP64 re-solves of MDP_FALLBACK_FP64 on it

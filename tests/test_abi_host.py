@@ -465,6 +465,20 @@ def test_fallback_flag_accepted_and_stats_field_present():
     assert e.value.code == L.MDP_EINVAL
 
 
+def test_residual_history_of_a_handle_without_solves():
+    import ctypes
+    sc = synth.tiny_2d(6)
+    A, b, part = tpfa.assemble(sc)
+    h = L.mdp_setup(A, part, L.mdp_options_default(flags=L.MDP_HOST_ONLY))
+    try:
+        assert len(L.mdp_residual_history(h)) == 0
+        assert L.lib.mdp_residual_history(h, None, -1, None) == L.MDP_EINVAL
+        assert L.lib.mdp_residual_history(h, None, 3, None) == L.MDP_EINVAL
+        assert L.lib.mdp_residual_history(None, None, 0, None) == L.MDP_EINVAL
+    finally:
+        L.mdp_destroy(h)
+
+
 def test_multi_rhs_memory_of_a_handle_without_a_batch(monkeypatch):
     sc = synth.tiny_2d(6)
     A, b, part = tpfa.assemble(sc)

@@ -61,6 +61,20 @@ def test_solve_matches_oracle(name, prec):
         assert abs(st[0]["rel_res_true"] - res) <= 1e-3 * res + 1e-15
         assert err <= 1e-6
         assert abs(st[0]["iters"] - ref8.iters) <= 2
+        # residual history: one estimate per iteration, the last one the
+        # reported estimate; non-increasing inside a restart cycle (the
+        # GMRES least-squares residual); in FP64 the oracle's own history
+        hist = L.mdp_residual_history(s.handle)
+        assert len(hist) == st[0]["iters"]
+        assert abs(hist[-1] - st[0]["rel_res_est"]) <= 1e-12 * max(st[0]["rel_res_est"], 1e-300)
+        m = L.mdp_options_default().restart
+        for c0 in range(0, len(hist), m):
+            cyc = hist[c0:c0 + m]
+            assert np.all(np.diff(cyc) <= 1e-12 * cyc[:-1]), name
+        if prec == "fp64" and len(hist) == len(ref8.history):
+            d = np.abs(hist - np.asarray(ref8.history)) / np.asarray(ref8.history)
+            say(f"    history vs oracle: max relative difference {d.max():.2e}")
+            assert d.max() <= 1e-9  # measured at most 1.2e-12: CGS2 and MGS agree to rounding
     finally:
         s.close()
 
