@@ -327,6 +327,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     std::vector<Piece> pa, pp, pr, pr_plain, psw;
     std::vector<T> dinv(nfull);
     std::vector<DenseDesc> desc;
+    bool sw_all_diag = true;  // every swept system of this level has a diagonal matrix
     // the level restricts b with R (I - A D^-1) when every continuing system
     // has it and the pre-smoothing is the single l1-Jacobi sweep from zero D^-1 b
     dl.fused = dl.ncont > 0 && pre == 1 && !gs;
@@ -350,6 +351,10 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
         dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
       } else {
         psw.emplace_back(&hl.A, o - dl.sw_off, o - dl.sw_off);
+        bool diag = true;
+        for (int32_t i = 0; i < hl.A.nr && diag; ++i)
+          diag = hl.A.ptr[i + 1] - hl.A.ptr[i] == 1 && hl.A.col[hl.A.ptr[i]] == i;
+        sw_all_diag = sw_all_diag && diag;
       }
     }
     for (int r = 1; r < kb; ++r) std::copy(dinv.begin(), dinv.begin() + dl.n, dinv.begin() + r * dl.n);
@@ -408,6 +413,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
       }
     }
     upload_csr(concat_blocks(dl.n - dl.sw_off, dl.n - dl.sw_off, psw), dl.Asw, s, keep);
+    dl.sw_diag = dl.n > dl.sw_off && sw_all_diag;
     dl.ndense = static_cast<int32_t>(desc.size());
     upload_vec(dl.dense, keep.put(std::move(desc)), s);
     upload_vec(dl.dinv, keep.put(std::move(dinv)), s);
@@ -884,7 +890,20 @@ void coarse_solve(DHier<T> &H, DLevel<T> &L, const T *b, T *x, Gate gate, hipStr
     });
   }
   const int nsw = L.n - L.sw_off;
-  if (nsw > 0) {
+  if (nsw > 0 && L.sw_diag) {
+    // diagonal systems (A_GG of the interface-flux reading): the first
+    // l1-Jacobi iterate D^-1 b, already in t, is their solution, and further
+    // sweeps would only add rounding
+    const int o = L.sw_off;
+    for (int r = 0; r < H.kb; ++r) {
+      const int64_t off = static_cast<int64_t>(r) * L.n + o;
+      timed_launch(kKcVcycleOther, s, 2.0 * sizeof(T) * nsw, [&] {
+        hipLaunchKernelGGL((scale_copy_kernel<T, T>), dim3(grid_for(nsw)), dim3(kThreads), 0, s,
+                           static_cast<int64_t>(nsw), dptr<const T>(L.t) + off, static_cast<const double *>(nullptr),
+                           x + off, gate.all);
+      });
+    }
+  } else if (nsw > 0) {
     const int o = L.sw_off;
     T *pa = dptr<T>(L.pp), *pb = pa + sweep_stride(L, H.kb);
     const T *t = dptr<const T>(L.t) + o;

@@ -68,6 +68,7 @@ struct DLevel {
   DevMem dense;     // DenseDesc[ndense]
   int32_t sw_off = 0;
   DCsr<T> Asw;      // swept coarsest systems, indices relative to sw_off
+  bool sw_diag = false;  // every swept system is diagonal: D^-1 b solves it
   DevMem x, b, t, r;  // unknown, right-hand side, smoothing iterate, residual (and sweep ping-pong)
   DevMem pp;          // ping-pong for the swept coarsest systems
   // multicolour Gauss-Seidel (MDP_SMOOTH_GS): the continuing systems'
