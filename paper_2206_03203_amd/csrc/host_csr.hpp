@@ -88,14 +88,21 @@ HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn) {
   }
   out.col.resize(static_cast<size_t>(acc));
   out.val.resize(static_cast<size_t>(acc));
-  parallel_chunks(T, [&](int64_t b, int64_t e, int) {
-    for (int64_t t = b; t < e; ++t) {
-      if (first[t] < 0) continue;
-      const int64_t off = out.ptr[first[t]];
-      std::copy(lc[t].begin(), lc[t].end(), out.col.begin() + off);
-      std::copy(lv[t].begin(), lv[t].end(), out.val.begin() + off);
-    }
-  });
+  // each chunk's rows go to their place; the chunks are copied by threads
+  // of their own when there is enough to copy
+  auto place = [&](int t) {
+    if (first[t] < 0) return;
+    const int64_t off = out.ptr[first[t]];
+    std::copy(lc[t].begin(), lc[t].end(), out.col.begin() + off);
+    std::copy(lv[t].begin(), lv[t].end(), out.val.begin() + off);
+  };
+  if (T > 1 && acc >= (int64_t{1} << 16)) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back(place, t);
+    for (auto &x : th) x.join();
+  } else {
+    for (int t = 0; t < T; ++t) place(t);
+  }
   return out;
 }
 

@@ -248,9 +248,33 @@ void check_grounded(const HCsr &a) {
 // rounding differs).  It is kept only when that product moves no more bytes
 // than the two it replaces (8-byte values, 4-byte indices).
 HCsr fused_restriction(const HLevel &L, const HCsr &ra) {
-  HCsr sc = ra;
-  for (size_t k = 0; k < sc.col.size(); ++k) sc.val[k] /= L.dl1[static_cast<size_t>(sc.col[k])];
-  HCsr f = subtract(L.R, sc);
+  // R - (R A) D^-1, row by row in parallel: a merge of the two sorted rows,
+  // the (R A) entries divided by the l1 diagonal of their column
+  const HCsr &r = L.R;
+  const std::vector<double> &d = L.dl1;
+  if (r.nr != ra.nr || r.nc != ra.nc) throw std::invalid_argument("fused restriction shape mismatch");
+  HCsr f = build_rows(r.nr, r.nc, [&](int32_t i, int, std::vector<int32_t> &C, std::vector<double> &V) {
+    int32_t p = r.ptr[i], pe = r.ptr[i + 1], q = ra.ptr[i], qe = ra.ptr[i + 1];
+    while (p < pe || q < qe) {
+      if (q >= qe || (p < pe && r.col[p] < ra.col[q])) {
+        C.push_back(r.col[p]);
+        V.push_back(r.val[p]);
+        ++p;
+      } else if (p >= pe || ra.col[q] < r.col[p]) {
+        C.push_back(ra.col[q]);
+        V.push_back(-(ra.val[q] / d[static_cast<size_t>(ra.col[q])]));
+        ++q;
+      } else {
+        const double v = r.val[p] - ra.val[q] / d[static_cast<size_t>(ra.col[q])];
+        if (v != 0.0) {
+          C.push_back(r.col[p]);
+          V.push_back(v);
+        }
+        ++p;
+        ++q;
+      }
+    }
+  });
   const double n = L.A.nr, nc = L.R.nr;
   const double two = 12.0 * static_cast<double>(L.A.nnz() + L.R.nnz()) + 8.0 * (4.0 * n + 2.0 * nc);
   const double one = 12.0 * static_cast<double>(f.nnz()) + 8.0 * (n + 2.0 * nc);
