@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <iterator>
 #include <limits>
 #include <unordered_map>
 #include <utility>
@@ -60,15 +61,33 @@ inline bool sell_possible(const SliceStats &st, int64_t nnz, double max_padding)
 // there are at most kMaxDiag of them and the diagonal layout pads the
 // entries by at most 20%; empty otherwise.
 inline std::vector<int32_t> dia_offsets(const HCsr &h) {
+  // each chunk of rows collects its offsets (giving up past kMaxDiag), then
+  // the chunks' sets are merged
+  const int T = setup_workers();
+  std::vector<std::vector<int32_t>> part(static_cast<size_t>(T));
+  std::vector<char> over(static_cast<size_t>(T), 0);
+  parallel_chunks(h.nr, [&](int64_t b, int64_t e, int t) {
+    std::vector<int32_t> &offs = part[t];
+    for (int64_t i = b; i < e && !over[t]; ++i)
+      for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+        const int32_t d = h.col[k] - static_cast<int32_t>(i);
+        const auto it = std::lower_bound(offs.begin(), offs.end(), d);
+        if (it != offs.end() && *it == d) continue;
+        if (static_cast<int>(offs.size()) == kMaxDiag) {
+          over[t] = 1;
+          break;
+        }
+        offs.insert(it, d);
+      }
+  });
   std::vector<int32_t> offs;
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const int32_t d = h.col[k] - i;
-      const auto it = std::lower_bound(offs.begin(), offs.end(), d);
-      if (it != offs.end() && *it == d) continue;
-      if (static_cast<int>(offs.size()) == kMaxDiag) return {};
-      offs.insert(it, d);
-    }
+  for (int t = 0; t < T; ++t) {
+    if (over[t]) return {};
+    std::vector<int32_t> m;
+    std::set_union(offs.begin(), offs.end(), part[t].begin(), part[t].end(), std::back_inserter(m));
+    if (static_cast<int>(m.size()) > kMaxDiag) return {};
+    offs.swap(m);
+  }
   if (static_cast<double>(offs.size()) * h.nr > 1.2 * static_cast<double>(std::max<int64_t>(h.nnz(), 1))) return {};
   return offs;
 }
@@ -80,10 +99,17 @@ inline std::vector<int32_t> dia_offsets(const HCsr &h) {
 // not looked at.
 inline std::vector<int32_t> hyb_offsets(const HCsr &h) {
   if (h.nr == 0 || h.nnz() > static_cast<int64_t>(kMaxDiag + 4) * h.nr) return {};
+  const int T = setup_workers();
+  std::vector<std::unordered_map<int32_t, int64_t>> part(static_cast<size_t>(T));
+  parallel_chunks(h.nr, [&](int64_t b, int64_t e, int t) {
+    auto &c = part[t];
+    c.reserve(64);
+    for (int64_t i = b; i < e; ++i)
+      for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) ++c[h.col[k] - static_cast<int32_t>(i)];
+  });
   std::unordered_map<int32_t, int64_t> count;
-  count.reserve(64);
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) ++count[h.col[k] - i];
+  for (const auto &c : part)
+    for (const auto &kv : c) count[kv.first] += kv.second;
   std::vector<std::pair<int64_t, int32_t>> full;
   for (const auto &c : count)
     if (2 * c.second >= h.nr) full.emplace_back(c.second, c.first);
@@ -140,33 +166,36 @@ inline SellLayout sell_layout(const HCsr &h, const SliceStats &st) {
   const int32_t ns = (h.nr + 63) / 64;
   L.nslices = ns;
   L.soff.assign(static_cast<size_t>(ns) + 1, 0);
+  for (int32_t sl = 0; sl < ns; ++sl) {
+    int32_t w = 0;
+    for (int32_t r = sl * 64; r < std::min(h.nr, sl * 64 + 64); ++r) w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
+    L.soff[sl + 1] = L.soff[sl] + w * 64;
+  }
   L.col.assign(static_cast<size_t>(st.padded), 0);
   L.val.assign(static_cast<size_t>(st.padded), 0.0);
-  int64_t o = 0;
-  for (int32_t sl = 0; sl < ns; ++sl) {
-    const int32_t r0 = sl * 64, r1 = std::min(h.nr, r0 + 64);
-    int32_t w = 0, first = 0;
-    for (int32_t r = r1 - 1; r >= r0; --r) {
-      w = std::max(w, h.ptr[r + 1] - h.ptr[r]);
-      if (h.ptr[r + 1] > h.ptr[r]) first = h.col[h.ptr[r]];
-    }
-    L.soff[sl] = static_cast<int32_t>(o);
-    for (int32_t lane = 0; lane < 64; ++lane) {
-      const int32_t r = r0 + lane;
-      const int32_t len = r < r1 ? h.ptr[r + 1] - h.ptr[r] : 0;
-      int32_t lastc = first;
-      for (int32_t k = 0; k < w; ++k) {
-        const int64_t dst = o + static_cast<int64_t>(k) * 64 + lane;
-        if (k < len) {
-          lastc = h.col[h.ptr[r] + k];
-          L.val[dst] = h.val[h.ptr[r] + k];
+  parallel_chunks(ns, [&](int64_t sb, int64_t se, int) {
+    for (int64_t sl = sb; sl < se; ++sl) {
+      const int32_t r0 = static_cast<int32_t>(sl) * 64, r1 = std::min(h.nr, r0 + 64);
+      const int64_t o = L.soff[sl];
+      const int32_t w = static_cast<int32_t>((L.soff[sl + 1] - o) / 64);
+      int32_t first = 0;
+      for (int32_t r = r1 - 1; r >= r0; --r)
+        if (h.ptr[r + 1] > h.ptr[r]) first = h.col[h.ptr[r]];
+      for (int32_t lane = 0; lane < 64; ++lane) {
+        const int32_t r = r0 + lane;
+        const int32_t len = r < r1 ? h.ptr[r + 1] - h.ptr[r] : 0;
+        int32_t lastc = first;
+        for (int32_t k = 0; k < w; ++k) {
+          const int64_t dst = o + static_cast<int64_t>(k) * 64 + lane;
+          if (k < len) {
+            lastc = h.col[h.ptr[r] + k];
+            L.val[dst] = h.val[h.ptr[r] + k];
+          }
+          L.col[dst] = lastc;
         }
-        L.col[dst] = lastc;
       }
     }
-    o += static_cast<int64_t>(w) * 64;
-  }
-  L.soff[ns] = static_cast<int32_t>(o);
+  });
   return L;
 }
 
@@ -181,11 +210,13 @@ inline DiaLayout dia_layout(const HCsr &h, const std::vector<int32_t> &offs) {
   DiaLayout L;
   L.offs = offs;
   L.val.assign(offs.size() * static_cast<size_t>(h.nr), 0.0);
-  for (int32_t i = 0; i < h.nr; ++i)
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const size_t di = std::lower_bound(offs.begin(), offs.end(), h.col[k] - i) - offs.begin();
-      L.val[di * h.nr + i] = h.val[k];
-    }
+  parallel_chunks(h.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i)
+      for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+        const size_t di = std::lower_bound(offs.begin(), offs.end(), h.col[k] - static_cast<int32_t>(i)) - offs.begin();
+        L.val[di * h.nr + i] = h.val[k];
+      }
+  });
   return L;
 }
 
@@ -207,19 +238,40 @@ inline HybLayout hyb_layout(const HCsr &h, const std::vector<int32_t> &offs) {
   L.offs = offs;
   L.dval.assign(offs.size() * static_cast<size_t>(h.nr), 0.0);
   L.ptr.assign(static_cast<size_t>(h.nr) + 1, 0);
-  for (int32_t i = 0; i < h.nr; ++i) {
-    for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
-      const int32_t off = h.col[k] - i;
-      const auto it = std::lower_bound(offs.begin(), offs.end(), off);
-      if (it != offs.end() && *it == off) {
-        L.dval[static_cast<size_t>(it - offs.begin()) * h.nr + i] = h.val[k];
-      } else {
-        L.col.push_back(h.col[k]);
-        L.val.push_back(h.val[k]);
+  // first pass: the diagonal entries and the remainder's row lengths; second
+  // pass: the remainder at its row offsets
+  auto on_diag = [&](int32_t i, int32_t k) {
+    const int32_t off = h.col[k] - i;
+    const auto it = std::lower_bound(offs.begin(), offs.end(), off);
+    return it != offs.end() && *it == off ? static_cast<int64_t>(it - offs.begin()) : int64_t{-1};
+  };
+  parallel_chunks(h.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t rem = 0;
+      for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k) {
+        const int64_t d = on_diag(static_cast<int32_t>(i), k);
+        if (d >= 0)
+          L.dval[static_cast<size_t>(d) * h.nr + i] = h.val[k];
+        else
+          ++rem;
       }
+      L.ptr[i + 1] = rem;
     }
-    L.ptr[i + 1] = static_cast<int32_t>(L.col.size());
-  }
+  });
+  for (int32_t i = 0; i < h.nr; ++i) L.ptr[i + 1] += L.ptr[i];
+  L.col.resize(static_cast<size_t>(L.ptr[h.nr]));
+  L.val.resize(static_cast<size_t>(L.ptr[h.nr]));
+  parallel_chunks(h.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t q = L.ptr[i];
+      for (int32_t k = h.ptr[i]; k < h.ptr[i + 1]; ++k)
+        if (on_diag(static_cast<int32_t>(i), k) < 0) {
+          L.col[q] = h.col[k];
+          L.val[q] = h.val[k];
+          ++q;
+        }
+    }
+  });
   L.split = h.nr;
   while (L.split > 0 && L.ptr[L.split] > L.ptr[L.split - 1]) --L.split;
   if (L.split == 0) L.split = h.nr;

@@ -24,20 +24,34 @@ inline int setup_workers() {
 }
 
 // Split [0, n) into at most setup_workers() contiguous chunks and run
-// f(begin, end, chunk) on each in its own thread.  The chunking depends only
-// on n, so two calls with the same n see the same chunks.  f must not throw.
+// f(begin, end, chunk) on each in its own thread.  With work (the prefix sums
+// of a per-row cost, size n + 1) the chunks carry equal shares of the cost,
+// else equal numbers of rows; below 8192 units of cost everything runs on the
+// calling thread.  The chunking depends only on n and work.  f must not
+// throw.
 template <class F>
-void parallel_chunks(int64_t n, F &&f) {
-  const int T = (n < 8192) ? 1 : setup_workers();
-  const int64_t chunk = (n + T - 1) / T;
+void parallel_chunks(int64_t n, F &&f, const std::vector<int64_t> *work = nullptr) {
+  const int64_t total = work ? (*work)[static_cast<size_t>(n)] : n;
+  const int T = static_cast<int>(std::min<int64_t>(total < 8192 ? 1 : setup_workers(), std::max<int64_t>(n, 1)));
   if (T == 1) {
     f(int64_t{0}, n, 0);
     return;
   }
+  std::vector<int64_t> bound(static_cast<size_t>(T) + 1, n);
+  bound[0] = 0;
+  for (int t = 1; t < T; ++t) {
+    if (work) {
+      const int64_t target = total / T * t + total % T * t / T;
+      bound[t] = std::lower_bound(work->begin(), work->begin() + n + 1, target) - work->begin();
+    } else {
+      bound[t] = std::min<int64_t>(n, t * ((n + T - 1) / T));
+    }
+    bound[t] = std::max(bound[t], bound[t - 1]);
+  }
   std::vector<std::thread> th;
   for (int t = 0; t < T; ++t) {
-    const int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
-    if (b >= e) break;
+    const int64_t b = bound[t], e = bound[t + 1];
+    if (b >= e) continue;
     th.emplace_back([&f, b, e, t] { f(b, e, t); });
   }
   for (auto &x : th) x.join();
@@ -63,7 +77,7 @@ struct HCsr {
 // entries of row i.  Rows are computed independently, so the result does not
 // depend on the number of threads.
 template <class RowFn>
-HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn) {
+HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn, const std::vector<int64_t> *work = nullptr) {
   const int T = setup_workers();
   std::vector<std::vector<int32_t>> lc(static_cast<size_t>(T));
   std::vector<std::vector<double>> lv(static_cast<size_t>(T));
@@ -78,7 +92,7 @@ HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn) {
       fn(static_cast<int32_t>(i), t, C, V);
       cnt[i] = static_cast<int32_t>(C.size() - before);
     }
-  });
+  }, work);
   HCsr out = HCsr::empty(nr, nc);
   int64_t acc = 0;
   for (int32_t i = 0; i < nr; ++i) {
@@ -145,9 +159,6 @@ inline HCsr transpose(const HCsr &a) {
   return t;  // rows of t come out sorted because i increases
 }
 
-// C = A * B (Gustavson row-by-row with a dense accumulator).  Each output
-// entry sums a_ik * b_kj over A's row in stored order, then B's row in stored
-// order.  Output columns sorted; entries that sum to exactly zero are dropped.
 // Greedy colouring for multicolour Gauss-Seidel: in natural order, node i
 // takes the smallest colour not used by an already coloured neighbour in the
 // pattern of a + a^T (diagonal and stored zeros excluded).  Returns the
@@ -171,9 +182,19 @@ inline std::vector<int32_t> greedy_colours(const HCsr &a) {
   return col;
 }
 
+// C = A * B (Gustavson row-by-row with a dense accumulator).  Each output
+// entry sums a_ik * b_kj over A's row in stored order, then B's row in stored
+// order.  Output columns sorted; entries that sum to exactly zero are dropped.
+// Rows are shared among the threads by their number of products.
 inline HCsr spgemm(const HCsr &a, const HCsr &b) {
   if (a.nc != b.nr) throw std::invalid_argument("spgemm shape mismatch");
   const int T = setup_workers();
+  std::vector<int64_t> work(static_cast<size_t>(a.nr) + 1, 0);
+  for (int32_t i = 0; i < a.nr; ++i) {
+    int64_t w = 1;
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) w += b.ptr[a.col[p] + 1] - b.ptr[a.col[p]];
+    work[i + 1] = work[i] + w;
+  }
   std::vector<std::vector<int32_t>> mark(static_cast<size_t>(T)), cols(static_cast<size_t>(T));
   std::vector<std::vector<double>> acc(static_cast<size_t>(T));
   return build_rows(a.nr, b.nc, [&](int32_t i, int t, std::vector<int32_t> &C, std::vector<double> &V) {
@@ -205,7 +226,7 @@ inline HCsr spgemm(const HCsr &a, const HCsr &b) {
       C.push_back(j);
       V.push_back(ac[j]);
     }
-  });
+  }, &work);
 }
 
 // C = A - B for matrices with sorted rows; entries present in only one operand
@@ -235,6 +256,29 @@ inline HCsr subtract(const HCsr &a, const HCsr &b) {
       }
     }
   });
+}
+
+// a == a^T exactly, values included, for a square matrix whose rows are
+// sorted without repeated columns: every entry (i, j, v) has its mirror
+// (j, i, v), found by binary search in row j.
+inline bool is_symmetric(const HCsr &a) {
+  if (a.nr != a.nc) return false;
+  std::vector<char> bad(static_cast<size_t>(setup_workers()), 0);
+  parallel_chunks(a.nr, [&](int64_t b, int64_t e, int t) {
+    for (int64_t i = b; i < e && !bad[t]; ++i)
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+        const int32_t j = a.col[p];
+        const auto lo = a.col.begin() + a.ptr[j], hi = a.col.begin() + a.ptr[j + 1];
+        const auto q = std::lower_bound(lo, hi, static_cast<int32_t>(i));
+        if (q == hi || *q != i || a.val[static_cast<size_t>(q - a.col.begin())] != a.val[p]) {
+          bad[t] = 1;
+          break;
+        }
+      }
+  });
+  for (char c : bad)
+    if (c) return false;
+  return true;
 }
 
 inline std::vector<double> diagonal(const HCsr &a) {

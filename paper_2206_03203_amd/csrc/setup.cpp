@@ -202,7 +202,7 @@ std::vector<double> dense_inverse(const HCsr &a) {
 // closed under that relation whose rows all sum to zero, so A[U, U] 1 = 0 and
 // the rows of U couple only to U: A is singular, nothing ties the level of
 // U.  Such input cannot be solved and is rejected up front.
-void check_grounded(const HCsr &a) {
+void check_grounded(const HCsr &a, bool symmetric) {
   const int32_t n = a.nr;
   std::vector<double> rs(static_cast<size_t>(n), 0.0), dg(static_cast<size_t>(n), 0.0);
   for (int32_t i = 0; i < n; ++i)
@@ -213,7 +213,8 @@ void check_grounded(const HCsr &a) {
     }
   // walk the transpose from the grounded rows: row j reaches ground when
   // a_ji != 0 for a row i that does
-  const HCsr t = transpose(a);
+  const HCsr tt = symmetric ? HCsr::empty(0, 0) : transpose(a);
+  const HCsr &t = symmetric ? a : tt;
   std::vector<char> reach(static_cast<size_t>(n), 0);
   std::vector<int32_t> stack;
   for (int32_t i = 0; i < n; ++i)
@@ -360,11 +361,8 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
   clk.lap("permute");
 
   // symmetry check (informational: the method does not need it)
-  {
-    HCsr t = transpose(A);
-    s.symmetric = (t.col == A.col && t.val == A.val);
-  }
-  check_grounded(A);
+  s.symmetric = is_symmetric(A);
+  check_grounded(A, s.symmetric);
   clk.lap("symmetry + grounding");
 
   std::vector<int32_t> rows_o(static_cast<size_t>(s.n_o)), rows_g(static_cast<size_t>(s.n_g));

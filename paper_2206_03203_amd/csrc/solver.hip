@@ -177,7 +177,23 @@ bool valid_lpr(int l) { return l == 2 || l == 4 || l == 8 || l == 16 || l == 32 
 
 template <typename T>
 FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
-                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep);
+                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep, DCsr<T> &won,
+                             bool &filled);
+
+// Move the device arrays of a matrix, and the fields that describe them, from
+// src into d (d's block and pair fields stay).
+template <typename T>
+void take_arrays(DCsr<T> &d, DCsr<T> &src) {
+  d.ptr = std::move(src.ptr);
+  d.col = std::move(src.col);
+  d.val = std::move(src.val);
+  d.doff = std::move(src.doff);
+  d.dval = std::move(src.dval);
+  d.ndiag = src.ndiag;
+  d.rem_nnz = src.rem_nnz;
+  d.split = src.split;
+  d.nslices = src.nslices;
+}
 
 // Restriction of a level: true to keep the fused product R (I - A D^-1) b,
 // false for the residual b - A D^-1 b and then R (see choose_fused).
@@ -199,14 +215,22 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
   const std::vector<int32_t> offs = h.nr > 0 ? dia_offsets(h) : std::vector<int32_t>{};
   const std::vector<int32_t> hoffs = offs.empty() ? hyb_offsets(h) : std::vector<int32_t>{};
   FormatChoice f = heuristic_format(h, st, !offs.empty(), !hoffs.empty());
-  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, offs, hoffs, s, keep);
+  const auto t0 = std::chrono::steady_clock::now();
+  // the autotuner hands over the arrays of the format it chose (filled), or
+  // returns a recorded choice whose arrays are built here
+  DCsr<T> won;
+  bool filled = false;
+  if (t_autotune && d.nnz >= kTuneMinNnz && h.nr > 0) f = autotune_format<T>(h, st, offs, hoffs, s, keep, won, filled);
+  const auto t1 = std::chrono::steady_clock::now();
   d.dia = f.dia;
   d.hyb = f.hyb;
   d.sell = f.sell;
   d.scalar = f.scalar;
   d.lpr = f.lpr;
   d.batch = f.batch;
-  if (f.dia)
+  if (filled)
+    take_arrays(d, won);
+  else if (f.dia)
     upload_dia_arrays(h, d, offs, s, keep);
   else if (f.hyb)
     upload_hyb_arrays(h, d, hoffs, s, keep);
@@ -214,6 +238,12 @@ void upload_csr(const HCsr &h, DCsr<T> &d, hipStream_t s, Keep &keep) {
     upload_sell_arrays(h, d, st, s, keep);
   else
     upload_csr_arrays(h, d, s, keep);
+  if (std::getenv("MDP_SETUP_VERBOSE")) {
+    const auto t2 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[mdp] upload n=%d nnz=%lld: tune %.3f s, upload %.3f s\n", h.nr,
+                 static_cast<long long>(h.nnz()), std::chrono::duration<double>(t1 - t0).count(),
+                 std::chrono::duration<double>(t2 - t1).count());
+  }
 }
 
 using Piece = std::tuple<const HCsr *, int32_t, int32_t>;  // matrix, row offset, column offset
@@ -634,7 +664,9 @@ void flush_caches(const DevMem &buf, hipStream_t s) {
 
 template <typename T>
 FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vector<int32_t> &offs,
-                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep) {
+                             const std::vector<int32_t> &hoffs, hipStream_t s, Keep &keep, DCsr<T> &won,
+                             bool &filled) {
+  filled = false;
   const TuneKey key{static_cast<int>(sizeof(T)), h.nr, h.nc, st.maxlen, h.nnz(), st.padded};
   {
     // a recorded choice is used when this matrix has that layout
@@ -752,9 +784,22 @@ FormatChoice autotune_format(const HCsr &h, const SliceStats &st, const std::vec
                  sizeof(T) == 8 ? "f64" : "f32", h.nr, static_cast<long long>(h.nnz()),
                  best.dia ? "dia" : best.hyb ? "dia+csr" : best.sell ? "sell" : best.scalar ? "scalar" : "csr-vector",
                  best.lpr, best.batch, 1e3 * tbest);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (g_tune.emplace(key, best).second) tune_record(key, best);
-  return best;
+  // a choice recorded meanwhile by another thread for the same signature
+  // wins, so that equal matrices get one format
+  FormatChoice chosen = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto ins = g_tune.emplace(key, best);
+    if (ins.second) {
+      tune_record(key, best);
+    } else {
+      const FormatChoice &f = ins.first->second;
+      if ((!f.dia || !offs.empty()) && (!f.hyb || !hoffs.empty()) && (!f.sell || has_sell)) chosen = f;
+    }
+  }
+  take_arrays(won, chosen.dia ? dia : chosen.hyb ? hyb : chosen.sell ? sell : csr);
+  filled = true;
+  return chosen;
 }
 
 // Time the two ways of restricting b on one level, each from cold caches as
@@ -1611,6 +1656,7 @@ void Solver::ensure_workspace(hipStream_t s) {
 
 void Solver::upload(hipStream_t s) {
   const AutotuneScope tune((opt.flags & MDP_NO_AUTOTUNE) == 0);
+  const auto t0 = std::chrono::steady_clock::now();
   n = host.n;
   n_o = host.n_o;
   n_g = host.n_g;
@@ -1634,6 +1680,9 @@ void Solver::upload(hipStream_t s) {
   }
   MDP_HIP(hipStreamSynchronize(s));
   on_device = true;
+  if (std::getenv("MDP_SETUP_VERBOSE"))
+    std::fprintf(stderr, "[mdp] device upload %.3f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
 }
 
 int Solver::solve(const double *b, double *x, hipStream_t s, mdp_stats *st, bool fp64_only) {
