@@ -82,6 +82,18 @@ extern "C" {
                               column groups and mdp_solve_batch re-solve their
                               failed columns one by one, each with its own
                               handle's flag. */
+#define MDP_HOST_PRODUCTS 32u /* mdp_setup: form every sparse product of the
+                              set-up (A P_t, R A, (R A) P of Section 3.3 and
+                              A_OG diag(A_GG)^-1 A_GO of eq. (7)) on the host
+                              threads.  By default, unless MDP_HOST_ONLY is
+                              set, products of at least 2^22 terms (or the
+                              count in the environment variable
+                              MDP_DEVICE_PRODUCT_TERMS) are formed on the
+                              device (expansion, stable radix sort by
+                              row and column, in-order sums): the same
+                              matrices bit for bit, so the same hierarchy; a
+                              product that does not fit in free device memory
+                              is formed on the host. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,

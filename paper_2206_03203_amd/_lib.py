@@ -44,7 +44,7 @@ if len(_hip_runtimes()) > 1:
 MDP_OK, MDP_NOT_CONVERGED, MDP_PENDING, MDP_STAGNATED = 0, 1, 2, 3
 MDP_EINVAL, MDP_ENONPOS_DIAG, MDP_ESINGULAR, MDP_ENAN, MDP_ENOMEM, MDP_EHIP, MDP_EBUSY = -1, -2, -3, -4, -5, -6, -7
 MDP_FP64, MDP_MIXED = 0, 1
-MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS, MDP_FALLBACK_FP64 = 1, 2, 4, 8, 16
+MDP_USE_X0, MDP_HOST_ONLY, MDP_NO_AUTOTUNE, MDP_GRAPHS, MDP_FALLBACK_FP64, MDP_HOST_PRODUCTS = 1, 2, 4, 8, 16, 32
 MDP_BLOCK_LOWER, MDP_BLOCK_DIAG, MDP_BLOCK_UPPER = 0, 1, 2
 MDP_SMOOTH_L1JACOBI, MDP_SMOOTH_GS = 0, 1
 MDP_OP_A, MDP_OP_ML, MDP_OP_QOO, MDP_OP_QGG = 0, 1, 2, 3

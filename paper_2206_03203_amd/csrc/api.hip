@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 
+#include "dev_spgemm.hpp"
 #include "ktimer.hpp"
 #include "mdp.h"
 #include "solver.hpp"
@@ -16,6 +17,22 @@
 namespace mdp {
 
 namespace {
+
+// The set-up's large sparse products on the device while alive (this
+// thread): those of at least MDP_DEVICE_PRODUCT_TERMS terms (default 2^22).
+constexpr int64_t kDeviceProductTerms = int64_t{1} << 22;
+struct DeviceProducts {
+  ProductHook saved;
+  DeviceProducts(bool on, void *stream) : saved(product_hook()) {
+    const char *e = std::getenv("MDP_DEVICE_PRODUCT_TERMS");
+    const int64_t min_terms = e ? std::max<int64_t>(1, std::atoll(e)) : kDeviceProductTerms;
+    if (on) product_hook() = ProductHook{&device_spgemm, stream, min_terms};
+  }
+  ~DeviceProducts() { product_hook() = saved; }
+  DeviceProducts(const DeviceProducts &) = delete;
+  DeviceProducts &operator=(const DeviceProducts &) = delete;
+};
+
 thread_local std::string g_last_error;
 std::mutex g_hook_mu;
 AllocHook g_hook;
@@ -111,7 +128,7 @@ int check_options(const mdp_options &o) {
   if (o.restart < 1 || o.restart > kMaxCols) return bad("restart must be in [1, 64]");
   if (o.max_iter < 0) return bad("max_iter must be >= 0");
   if (!(o.rtol > 0.0)) return bad("rtol must be > 0");
-  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS | MDP_FALLBACK_FP64))
+  if (o.flags & ~(MDP_USE_X0 | MDP_HOST_ONLY | MDP_NO_AUTOTUNE | MDP_GRAPHS | MDP_FALLBACK_FP64 | MDP_HOST_PRODUCTS))
     return bad("unknown bits in flags");
   if (o.block_form != MDP_BLOCK_LOWER && o.block_form != MDP_BLOCK_DIAG && o.block_form != MDP_BLOCK_UPPER)
     return bad("block_form must be MDP_BLOCK_LOWER, MDP_BLOCK_DIAG or MDP_BLOCK_UPPER");
@@ -375,6 +392,7 @@ int mdp_setup_labeled(const mdp_csr *A, const int32_t *part, const int32_t *labe
   h->s.opt = o;
   {
     const Range r("mdp_setup host");
+    const DeviceProducts dp(!(o.flags & (MDP_HOST_ONLY | MDP_HOST_PRODUCTS)), hip_stream);
     build_host_system(A, part, o, h->s.host, label);
   }
   h->s.n = h->s.host.n;

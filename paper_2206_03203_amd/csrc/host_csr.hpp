@@ -182,6 +182,20 @@ inline std::vector<int32_t> greedy_colours(const HCsr &a) {
   return col;
 }
 
+// A device implementation of spgemm that returns the same matrix bit for
+// bit, installed (per thread) by the library around a set-up that may use the
+// GPU; products of at least min_terms terms go to it, and to the host when it
+// returns false.
+struct ProductHook {
+  bool (*fn)(const HCsr &a, const HCsr &b, HCsr &c, void *ctx) = nullptr;
+  void *ctx = nullptr;
+  int64_t min_terms = 0;
+};
+inline ProductHook &product_hook() {
+  static thread_local ProductHook h;
+  return h;
+}
+
 // C = A * B (Gustavson row-by-row with a dense accumulator).  Each output
 // entry sums a_ik * b_kj over A's row in stored order, then B's row in stored
 // order.  Output columns sorted; entries that sum to exactly zero are dropped.
@@ -194,6 +208,11 @@ inline HCsr spgemm(const HCsr &a, const HCsr &b) {
     int64_t w = 1;
     for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) w += b.ptr[a.col[p] + 1] - b.ptr[a.col[p]];
     work[i + 1] = work[i] + w;
+  }
+  const ProductHook &hook = product_hook();
+  if (hook.fn && work[a.nr] - a.nr >= hook.min_terms) {
+    HCsr c;
+    if (hook.fn(a, b, c, hook.ctx)) return c;
   }
   std::vector<std::vector<int32_t>> mark(static_cast<size_t>(T)), cols(static_cast<size_t>(T));
   std::vector<std::vector<double>> acc(static_cast<size_t>(T));

@@ -447,7 +447,8 @@ def test_binding_constants_match_the_header():
         if hasattr(L, name):
             assert getattr(L, name) == int(val), name
             seen += 1
-    for name in ("MDP_STAGNATED", "MDP_FALLBACK_FP64", "MDP_GRAPHS", "MDP_ENAN", "MDP_SMOOTH_GS"):
+    for name in ("MDP_STAGNATED", "MDP_FALLBACK_FP64", "MDP_GRAPHS", "MDP_ENAN", "MDP_SMOOTH_GS",
+                 "MDP_HOST_PRODUCTS"):
         assert hasattr(L, name), name
     assert seen >= 30
 
@@ -459,7 +460,9 @@ def test_fallback_flag_accepted_and_stats_field_present():
     h = L.mdp_setup(A, part, o)
     L.mdp_destroy(h)
     assert "fallback" in L.mdp_stats().as_dict()
-    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | 32)
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | L.MDP_HOST_PRODUCTS)
+    L.mdp_destroy(L.mdp_setup(A, part, o))
+    o = L.mdp_options_default(flags=L.MDP_HOST_ONLY | 64)
     with pytest.raises(L.MdpError) as e:
         L.mdp_setup(A, part, o)
     assert e.value.code == L.MDP_EINVAL
