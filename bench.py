@@ -68,6 +68,8 @@ def parse():
                    help="log-normal seeds per (K_par, kappa) pair (headline)")
     p.add_argument("--vcycles", type=int, default=1, help="V-cycles per block solve (Section 3.3)")
     p.add_argument("--restart", type=int, default=64, help="FGMRES restart length (at most 64)")
+    p.add_argument("--theta", type=float, default=0.02,
+                   help="strength threshold of the SA aggregation (reading R8)")
     p.add_argument("--max-coarse", type=int, default=400,
                    help="AMG: stop coarsening at this many unknowns (the coarsest is dense up to 2000)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,9 +216,11 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
             bf = {"lower": L.MDP_BLOCK_LOWER, "diag": L.MDP_BLOCK_DIAG, "upper": L.MDP_BLOCK_UPPER}[args.block]
             sm = L.MDP_SMOOTH_GS if args.smoother == "gs" else L.MDP_SMOOTH_L1JACOBI
             o64 = L.mdp_options_default(precision=L.MDP_FP64, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
+                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm,
+                                        strength_theta=args.theta)
             o32 = L.mdp_options_default(precision=L.MDP_MIXED, vcycles=args.vcycles, flags=fl, block_form=bf,
-                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm)
+                                        max_coarse=args.max_coarse, restart=args.restart, smoother=sm,
+                                        strength_theta=args.theta)
             labels = info["labels"] if (formulation == "flux" and args.dim_aware) else None
             hs = {"fp64": L.mdp_setup(A, part, o64, stream, labels=labels)}
             hs["mixed"] = L.mdp_setup_like(hs["fp64"], o32, stream)
@@ -346,8 +350,9 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
     roofline, classes = roofline_pass(lambda: run("fp64", steps), args.kernel_class,
                                       f"the {steps} FP64 steps repeated", fp["seconds"])
     if roofline["kernel_symbol"] and args.seeds == DEFAULT_SEEDS and args.vcycles == 1 and args.block == "lower" and \
-            args.max_coarse == 400 and args.restart == 64 and formulation == "pressure" and args.smoother == "l1jacobi":
-        roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}")
+            args.max_coarse == 400 and args.restart == 64 and formulation == "pressure" and args.smoother == "l1jacobi" \
+            and args.theta == 0.02:
+        roofline["traffic"] = measured_traffic(roofline["kernel_symbol"].split("<")[0], f"cube{n}", args.theta)
 
     # Each system's solution in both precisions against the oracle's solution
     # of the same system (the oracle solves are the CPU baseline's).
@@ -392,7 +397,7 @@ def run_cube(args, n, steps, warmup, headline, formulation=None):
                    "unknown_kinds": {k: v for k, v in info.items() if k != "labels"} if info else None,
                    "systems": len(systems), "unknowns": systems[0]["n"], "nnz": systems[0]["nnz"],
                    "fracture_perm_pairs": PAIRS, "rtol": 1e-8, "vcycles": args.vcycles,
-                   "amg_max_coarse": args.max_coarse, "restart": args.restart,
+                   "amg_max_coarse": args.max_coarse, "amg_theta": args.theta, "restart": args.restart,
                    "autotune": not args.no_autotune, "graphs": args.graphs, "smoother": args.smoother,
                    "block_preconditioner": args.block},
         "p50_ms": pct(fp["lat"], 50),
@@ -505,11 +510,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(symbol: str, workload: str):
+def measured_traffic(symbol: str, workload: str, theta: float):
     """HBM bytes per launch of kernel `symbol` on `workload` from the
     committed hardware-counter summary (FETCH_SIZE and WRITE_SIZE passes,
-    scaled by a copy of known size), or None when there is none or the
-    kernel sources changed since the counters were taken."""
+    scaled by a copy of known size), or None when there is none, the kernel
+    sources changed since the counters were taken, or the counters were taken
+    with another strength threshold (another hierarchy, other iteration
+    counts, so another mix of Arnoldi steps)."""
     path = os.path.join(ROOT, "profiles", f"{symbol}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -520,6 +527,11 @@ def measured_traffic(symbol: str, workload: str):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        if float(kv.get("amg_theta", "nan")) != theta:
+            return None
+    except ValueError:
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])

@@ -154,7 +154,7 @@ typedef struct {
   int32_t vcycles;        /* V-cycles per Q application (default 1, Section 3.3)      */
   int32_t pre_sweeps;     /* l1-Jacobi sweeps before the coarse correction (1; 1..8)  */
   int32_t post_sweeps;    /* l1-Jacobi sweeps after it (1; 1..8)                       */
-  double strength_theta;  /* SA strength threshold (0.08)                              */
+  double strength_theta;  /* SA strength threshold (0.02)                              */
   int32_t max_coarse;     /* stop coarsening at or below this size (400)               */
   int32_t max_dense;      /* coarsest solved densely up to this size (2000)            */
   int32_t max_levels;     /* at most this many levels per hierarchy (10)               */

@@ -355,7 +355,7 @@ int mdp_options_default(mdp_options *o) {
   o->vcycles = 1;
   o->pre_sweeps = 1;
   o->post_sweeps = 1;
-  o->strength_theta = 0.08;
+  o->strength_theta = 0.02;
   o->max_coarse = 400;
   o->max_dense = 2000;
   o->max_levels = 10;

@@ -12,7 +12,7 @@
 namespace mdp {
 
 struct AmgParams {
-  double theta = 0.08;
+  double theta = 0.02;
   int32_t max_coarse = 400;
   int32_t max_dense = 2000;
   int32_t max_levels = 10;

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported():
 def test_options_default_values():
     o = L.mdp_options_default()
     assert (o.precision, o.vcycles, o.pre_sweeps, o.post_sweeps) == (L.MDP_FP64, 1, 1, 1)
-    assert (o.strength_theta, o.max_coarse, o.max_dense, o.max_levels) == (0.08, 400, 2000, 10)
+    assert (o.strength_theta, o.max_coarse, o.max_dense, o.max_levels) == (0.02, 400, 2000, 10)
     assert (o.restart, o.max_iter, o.rtol, o.flags) == (64, 1000, 1e-8, 0)
     assert o.block_form == L.MDP_BLOCK_LOWER
     assert L.mdp_version().startswith("mdp")
