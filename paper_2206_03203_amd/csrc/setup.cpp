@@ -282,6 +282,114 @@ HCsr fused_restriction(const HLevel &L, const HCsr &ra) {
   return one <= two ? f : HCsr::empty(0, 0);
 }
 
+namespace {
+
+void csr_mv(const HCsr &a, const double *x, double *y) {
+  for (int32_t i = 0; i < a.nr; ++i) {
+    double acc = 0.0;
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) acc += a.val[p] * x[a.col[p]];
+    y[i] = acc;
+  }
+}
+
+// Work vectors of one thread, per level.
+struct TailScratch {
+  std::vector<std::vector<double>> ax, bc, xc;
+};
+
+// x = one V-cycle from zero on levels l.. of h (Section 3.3), in FP64 and in
+// the steps the device takes with l1-Jacobi smoothing: the first iterate
+// D^-1 b and pre - 1 further sweeps, the residual restricted by R, the coarse
+// correction added through P, post sweeps; the coarsest level's dense inverse.
+void vcycle_from(const HHier &h, size_t l, const double *b, double *x, int pre, int post, TailScratch &s) {
+  const HLevel &L = h.lv[l];
+  const int32_t n = L.A.nr;
+  if (l + 1 == h.lv.size()) {
+    for (int32_t i = 0; i < n; ++i) {
+      double acc = 0.0;
+      const double *row = h.coarse_inv.data() + static_cast<size_t>(i) * n;
+      for (int32_t j = 0; j < n; ++j) acc += row[j] * b[j];
+      x[i] = acc;
+    }
+    return;
+  }
+  double *ax = s.ax[l].data(), *bc = s.bc[l].data(), *xc = s.xc[l].data();
+  for (int32_t i = 0; i < n; ++i) x[i] = b[i] / L.dl1[i];
+  for (int k = 1; k < pre; ++k) {
+    csr_mv(L.A, x, ax);
+    for (int32_t i = 0; i < n; ++i) x[i] += (b[i] - ax[i]) / L.dl1[i];
+  }
+  csr_mv(L.A, x, ax);
+  for (int32_t i = 0; i < n; ++i) ax[i] = b[i] - ax[i];
+  csr_mv(L.R, ax, bc);
+  vcycle_from(h, l + 1, bc, xc, pre, post, s);
+  csr_mv(L.P, xc, ax);
+  for (int32_t i = 0; i < n; ++i) x[i] += ax[i];
+  for (int k = 0; k < post; ++k) {
+    csr_mv(L.A, x, ax);
+    for (int32_t i = 0; i < n; ++i) x[i] += (b[i] - ax[i]) / L.dl1[i];
+  }
+}
+
+}  // namespace
+
+void clear_tail(HHier &h) {
+  h.tail = -1;
+  h.tail_pre = h.tail_post = h.tail_max = 0;
+  h.tail_op.clear();
+}
+
+// The V-cycle is linear in b (fixed sweeps from zero, a fixed coarse solve),
+// so its part from level `tail` down is a matrix: column j is the V-cycle of
+// the unit vector e_j.  Columns are formed independently on the set-up
+// threads, so the matrix does not depend on their number.
+void form_tail(HHier &h, int pre, int post, int32_t max_n) {
+  if (h.tail_max == max_n && h.tail_pre == pre && h.tail_post == post && (h.tail >= 0 || h.tail_max > 0)) return;
+  clear_tail(h);
+  h.tail_pre = pre;
+  h.tail_post = post;
+  h.tail_max = max_n;
+  if (!h.dense || h.lv.size() < 3) return;
+  size_t ls = 0;
+  for (size_t l = 1; l + 1 < h.lv.size(); ++l)
+    if (h.lv[l].A.nr <= max_n) {
+      ls = l;
+      break;
+    }
+  if (ls == 0) return;
+  const int32_t n = h.lv[ls].A.nr;
+  int64_t per_col = 1;
+  for (size_t l = ls; l < h.lv.size(); ++l)
+    per_col += h.lv[l].A.nnz() * (pre + post + 1) + h.lv[l].R.nnz() + h.lv[l].P.nnz();
+  per_col += static_cast<int64_t>(h.lv.back().A.nr) * h.lv.back().A.nr;
+  std::vector<int64_t> work(static_cast<size_t>(n) + 1);
+  for (int32_t j = 0; j <= n; ++j) work[j] = per_col * j;
+  std::vector<double> T(static_cast<size_t>(n) * n);
+  std::vector<TailScratch> scratch(static_cast<size_t>(setup_workers()));
+  parallel_chunks(n, [&](int64_t b, int64_t e, int t) {
+    TailScratch &sc = scratch[t];
+    sc.ax.resize(h.lv.size());
+    sc.bc.resize(h.lv.size());
+    sc.xc.resize(h.lv.size());
+    for (size_t l = ls; l + 1 < h.lv.size(); ++l) {
+      sc.ax[l].assign(static_cast<size_t>(h.lv[l].A.nr), 0.0);
+      sc.bc[l].assign(static_cast<size_t>(h.lv[l + 1].A.nr), 0.0);
+      sc.xc[l].assign(static_cast<size_t>(h.lv[l + 1].A.nr), 0.0);
+    }
+    std::vector<double> ej(static_cast<size_t>(n), 0.0), col(static_cast<size_t>(n));
+    for (int64_t j = b; j < e; ++j) {
+      ej[j] = 1.0;
+      vcycle_from(h, ls, ej.data(), col.data(), pre, post, sc);
+      ej[j] = 0.0;
+      for (int32_t i = 0; i < n; ++i) T[static_cast<size_t>(i) * n + j] = col[i];
+    }
+  }, &work);
+  for (double v : T)
+    if (!std::isfinite(v)) return;  // keep the levels themselves
+  h.tail = static_cast<int32_t>(ls);
+  h.tail_op = std::move(T);
+}
+
 HHier amg_setup(const HCsr &A, const AmgParams &prm, const int32_t *labels) {
   PhaseClock clk;
   HHier h;

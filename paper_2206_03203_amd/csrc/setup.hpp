@@ -30,7 +30,18 @@ struct HHier {
   std::vector<HLevel> lv;
   bool dense = false;               // coarsest solved with a dense inverse
   std::vector<double> coarse_inv;   // n_c x n_c row-major inverse when dense
+  // Dense tail (derived at upload, not part of the hierarchy itself): the
+  // V-cycle from level `tail` down is one linear operator of b, kept here as
+  // an n_tail x n_tail row-major matrix and applied in place of those levels
+  // (-1: none).  It was formed for the sweep counts and size bound below.
+  int32_t tail = -1;
+  int tail_pre = 0, tail_post = 0, tail_max = 0;
+  std::vector<double> tail_op;
   int32_t n() const { return lv.empty() ? 0 : lv[0].A.nr; }
+  // levels the device runs, whether the last is a dense product, and its matrix
+  size_t depth() const { return tail >= 0 ? static_cast<size_t>(tail) + 1 : lv.size(); }
+  bool ends_dense() const { return tail >= 0 || dense; }
+  const std::vector<double> &coarse_op() const { return tail >= 0 ? tail_op : coarse_inv; }
 };
 
 struct HostSystem {
@@ -63,5 +74,12 @@ void load_host_system(const char *path, HostSystem &out, mdp_options &amg);
 
 // SA-AMG setup on one block (exposed for testing through the C ABI).
 HHier amg_setup(const HCsr &A, const AmgParams &prm, const int32_t *labels = nullptr);
+
+// Form h's dense tail for l1-Jacobi V-cycles with `pre` / `post` sweeps: the
+// first level l >= 1 above the coarsest with at most max_n unknowns, when the
+// coarsest level is dense; else clear it.  Does nothing when the tail was
+// already formed for these arguments.
+void form_tail(HHier &h, int pre, int post, int32_t max_n);
+void clear_tail(HHier &h);
 
 }  // namespace mdp

@@ -287,7 +287,7 @@ struct LevelPlan {
 LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
   LevelPlan pl;
   size_t L = 0;
-  for (const HHier *h : hs) L = std::max(L, h->lv.size());
+  for (const HHier *h : hs) L = std::max(L, h->depth());
   pl.order.resize(L);
   pl.off.assign(L, std::vector<int64_t>(hs.size(), -1));
   pl.n.assign(L, 0);
@@ -297,10 +297,10 @@ LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
     std::vector<int> cont, dense, sweep;
     for (size_t p = 0; p < hs.size(); ++p) {
       const HHier &h = *hs[p];
-      if (h.lv.size() <= l) continue;
-      if (l + 1 < h.lv.size())
+      if (h.depth() <= l) continue;
+      if (l + 1 < h.depth())
         cont.push_back(static_cast<int>(p));
-      else if (h.dense)
+      else if (h.ends_dense())
         dense.push_back(static_cast<int>(p));
       else
         sweep.push_back(static_cast<int>(p));
@@ -362,22 +362,22 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     // has it and the pre-smoothing is the single l1-Jacobi sweep from zero D^-1 b
     dl.fused = dl.ncont > 0 && pre == 1 && !gs;
     for (int p : pl.order[l])
-      if (l + 1 < hs[p]->lv.size() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
+      if (l + 1 < hs[p]->depth() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
     for (int p : pl.order[l]) {
       const HHier &h = *hs[p];
       const HLevel &hl = h.lv[l];
       const int32_t o = static_cast<int32_t>(pl.off[l][p]);
       for (int32_t i = 0; i < hl.A.nr; ++i) dinv[o + i] = static_cast<T>(1.0 / hl.dl1[i]);
-      if (l + 1 < h.lv.size()) {
+      if (l + 1 < h.depth()) {
         const int32_t oc = static_cast<int32_t>(pl.off[l + 1][p]);
         pa.emplace_back(&hl.A, o, o);
         pp.emplace_back(&hl.P, o, oc);
         pr.emplace_back(dl.fused ? &hl.Rf : &hl.R, oc, o);
         pr_plain.emplace_back(&hl.R, oc, o);
-      } else if (h.dense) {
+      } else if (h.ends_dense()) {
         for (int r = 0; r < kb; ++r)
           desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
-        cinv.insert(cinv.end(), h.coarse_inv.begin(), h.coarse_inv.end());
+        cinv.insert(cinv.end(), h.coarse_op().begin(), h.coarse_op().end());
         dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
       } else {
         psw.emplace_back(&hl.A, o - dl.sw_off, o - dl.sw_off);
@@ -395,7 +395,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
       // that colour's rows of every system, ascending
       std::vector<std::vector<int32_t>> by_colour;
       for (int p : pl.order[l]) {
-        if (l + 1 >= hs[p]->lv.size()) continue;
+        if (l + 1 >= hs[p]->depth()) continue;
         const std::vector<int32_t> col = greedy_colours(hs[p]->lv[l].A);
         const int32_t o = static_cast<int32_t>(pl.off[l][p]);
         for (size_t i = 0; i < col.size(); ++i) {
@@ -1664,6 +1664,14 @@ void Solver::upload(hipStream_t s) {
   upload_csr(host.A, A, s, keep);
   if (!host.identity) upload_vec(perm, host.perm, s);
   const std::vector<const HostSystem *> sys{&host};
+  // each hierarchy's dense tail for this handle's smoothing (none with
+  // Gauss-Seidel, whose sweeps the tail does not model)
+  for (HHier *hh : {&host.Ho, &host.Hg}) {
+    if (opt.smoother == MDP_SMOOTH_GS)
+      clear_tail(*hh);
+    else
+      form_tail(*hh, opt.pre_sweeps, opt.post_sweeps, opt.max_dense);
+  }
   const LevelPlan po = plan_levels({&host.Ho});
   const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
   const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
