@@ -38,10 +38,13 @@ struct HHier {
   int tail_pre = 0, tail_post = 0, tail_max = 0;
   std::vector<double> tail_op;
   int32_t n() const { return lv.empty() ? 0 : lv[0].A.nr; }
-  // levels the device runs, whether the last is a dense product, and its matrix
-  size_t depth() const { return tail >= 0 ? static_cast<size_t>(tail) + 1 : lv.size(); }
-  bool ends_dense() const { return tail >= 0 || dense; }
-  const std::vector<double> &coarse_op() const { return tail >= 0 ? tail_op : coarse_inv; }
+  // levels the device runs, whether the last is a dense product, and its
+  // matrix, with the tail in use or not
+  size_t depth(bool with_tail) const { return with_tail && tail >= 0 ? static_cast<size_t>(tail) + 1 : lv.size(); }
+  bool ends_dense(bool with_tail) const { return (with_tail && tail >= 0) || dense; }
+  const std::vector<double> &coarse_op(bool with_tail) const {
+    return with_tail && tail >= 0 ? tail_op : coarse_inv;
+  }
 };
 
 struct HostSystem {

@@ -284,10 +284,10 @@ struct LevelPlan {
   std::vector<int32_t> n, ncont, sw_off;
 };
 
-LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
+LevelPlan plan_levels(const std::vector<const HHier *> &hs, bool tails) {
   LevelPlan pl;
   size_t L = 0;
-  for (const HHier *h : hs) L = std::max(L, h->depth());
+  for (const HHier *h : hs) L = std::max(L, h->depth(tails));
   pl.order.resize(L);
   pl.off.assign(L, std::vector<int64_t>(hs.size(), -1));
   pl.n.assign(L, 0);
@@ -297,10 +297,10 @@ LevelPlan plan_levels(const std::vector<const HHier *> &hs) {
     std::vector<int> cont, dense, sweep;
     for (size_t p = 0; p < hs.size(); ++p) {
       const HHier &h = *hs[p];
-      if (h.depth() <= l) continue;
-      if (l + 1 < h.depth())
+      if (h.depth(tails) <= l) continue;
+      if (l + 1 < h.depth(tails))
         cont.push_back(static_cast<int>(p));
-      else if (h.ends_dense())
+      else if (h.ends_dense(tails))
         dense.push_back(static_cast<int>(p));
       else
         sweep.push_back(static_cast<int>(p));
@@ -339,7 +339,8 @@ int64_t sweep_stride(const DLevel<T> &L, int kb) {
 // pairs' rows (pair of a row in block r = r * nsys + its system).
 template <typename T>
 void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHier<T> &d, hipStream_t s, Keep &keep,
-                 int pre, int post, bool gs, const std::vector<int> *pair_of = nullptr, int kb = 1, int nsys = 1) {
+                 int pre, int post, bool gs, bool tails, const std::vector<int> *pair_of = nullptr, int kb = 1,
+                 int nsys = 1) {
   const size_t L = pl.order.size();
   d.lv.clear();
   d.lv.resize(L);
@@ -362,22 +363,22 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
     // has it and the pre-smoothing is the single l1-Jacobi sweep from zero D^-1 b
     dl.fused = dl.ncont > 0 && pre == 1 && !gs;
     for (int p : pl.order[l])
-      if (l + 1 < hs[p]->depth() && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
+      if (l + 1 < hs[p]->depth(tails) && hs[p]->lv[l].Rf.nr == 0) dl.fused = false;
     for (int p : pl.order[l]) {
       const HHier &h = *hs[p];
       const HLevel &hl = h.lv[l];
       const int32_t o = static_cast<int32_t>(pl.off[l][p]);
       for (int32_t i = 0; i < hl.A.nr; ++i) dinv[o + i] = static_cast<T>(1.0 / hl.dl1[i]);
-      if (l + 1 < h.depth()) {
+      if (l + 1 < h.depth(tails)) {
         const int32_t oc = static_cast<int32_t>(pl.off[l + 1][p]);
         pa.emplace_back(&hl.A, o, o);
         pp.emplace_back(&hl.P, o, oc);
         pr.emplace_back(dl.fused ? &hl.Rf : &hl.R, oc, o);
         pr_plain.emplace_back(&hl.R, oc, o);
-      } else if (h.ends_dense()) {
+      } else if (h.ends_dense(tails)) {
         for (int r = 0; r < kb; ++r)
           desc.push_back(DenseDesc{static_cast<int32_t>(r * dl.n + o), hl.A.nr, static_cast<int64_t>(cinv.size())});
-        cinv.insert(cinv.end(), h.coarse_op().begin(), h.coarse_op().end());
+        cinv.insert(cinv.end(), h.coarse_op(tails).begin(), h.coarse_op(tails).end());
         dl.max_dense_n = std::max(dl.max_dense_n, hl.A.nr);
       } else {
         psw.emplace_back(&hl.A, o - dl.sw_off, o - dl.sw_off);
@@ -395,7 +396,7 @@ void upload_hier(const std::vector<const HHier *> &hs, const LevelPlan &pl, DHie
       // that colour's rows of every system, ascending
       std::vector<std::vector<int32_t>> by_colour;
       for (int p : pl.order[l]) {
-        if (l + 1 >= hs[p]->depth()) continue;
+        if (l + 1 >= hs[p]->depth(tails)) continue;
         const std::vector<int32_t> col = greedy_colours(hs[p]->lv[l].A);
         const int32_t o = static_cast<int32_t>(pl.off[l][p]);
         for (size_t i = 0; i < col.size(); ++i) {
@@ -1125,7 +1126,7 @@ void apply_ml(Precond<T> &P, const T *r, T *z, Gate gate, hipStream_t s) {
 template <typename T>
 std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *> &sys, const LevelPlan &plan_o,
                                            const LevelPlan &plan_g, const std::vector<int> &gsys,
-                                           const mdp_options &opt, hipStream_t s, int kb = 1) {
+                                           const mdp_options &opt, bool tails, hipStream_t s, int kb = 1) {
   auto p = std::make_unique<Precond<T>>();
   Keep keep;
   p->vcycles = opt.vcycles;
@@ -1140,12 +1141,13 @@ std::unique_ptr<Precond<T>> upload_precond(const std::vector<const HostSystem *>
   const int nsys = static_cast<int>(sys.size());
   const bool maps = nsys > 1;
   const bool gs = opt.smoother == MDP_SMOOTH_GS;
-  upload_hier(ho, plan_o, p->Ho, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, maps ? &sys_o : nullptr, kb, nsys);
+  upload_hier(ho, plan_o, p->Ho, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, tails, maps ? &sys_o : nullptr, kb,
+              nsys);
   p->Ho.is_omega = true;
   const int32_t no1 = p->Ho.n();
   p->n_o = static_cast<int32_t>(p->Ho.nfull());
   if (!gsys.empty()) {
-    upload_hier(hg, plan_g, p->Hg, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, maps ? &gsys : nullptr, kb,
+    upload_hier(hg, plan_g, p->Hg, s, keep, opt.pre_sweeps, opt.post_sweeps, gs, tails, maps ? &gsys : nullptr, kb,
                 nsys);
     const int32_t ng1 = p->Hg.n();
     p->n_g = static_cast<int32_t>(p->Hg.nfull());
@@ -1672,13 +1674,13 @@ void Solver::upload(hipStream_t s) {
     else
       form_tail(*hh, opt.pre_sweeps, opt.post_sweeps, opt.max_dense);
   }
-  const LevelPlan po = plan_levels({&host.Ho});
-  const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
+  const LevelPlan po = plan_levels({&host.Ho}, true);
+  const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}, true) : LevelPlan{};
   const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(sys, po, pg, gp, opt, s);
+    pc32 = upload_precond<float>(sys, po, pg, gp, opt, true, s);
   else
-    pc64 = upload_precond<double>(sys, po, pg, gp, opt, s);
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt, true, s);
   layout.build({{{0, n}}}, n, s);
   const size_t tsz = opt.precision == MDP_MIXED ? sizeof(float) : sizeof(double);
   ws.alloc(n, opt.restart, 1, layout.ntiles, tsz, s);
@@ -1759,10 +1761,10 @@ void Solver::ensure_fp64(hipStream_t s) {
   if (!pc64) {
     const AutotuneScope tune((opt.flags & MDP_NO_AUTOTUNE) == 0);
     const std::vector<const HostSystem *> sys{&host};
-    const LevelPlan po = plan_levels({&host.Ho});
-    const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}) : LevelPlan{};
+    const LevelPlan po = plan_levels({&host.Ho}, true);
+    const LevelPlan pg = n_g > 0 ? plan_levels({&host.Hg}, true) : LevelPlan{};
     const std::vector<int> gp = n_g > 0 ? std::vector<int>{0} : std::vector<int>{};
-    pc64 = upload_precond<double>(sys, po, pg, gp, opt, s);
+    pc64 = upload_precond<double>(sys, po, pg, gp, opt, true, s);
   }
   if (ws.tsz < sizeof(double)) {
     // Z holds FP64 directions from now on (FP32 solves use the wider array as
@@ -1876,8 +1878,12 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
       hg.push_back(&bsys[k]->host.Hg);
     }
   }
-  const LevelPlan po = plan_levels(ho);
-  const LevelPlan pg = gsys.empty() ? LevelPlan{} : plan_levels(hg);
+  // dense tails only for plans of one system (a four-column group): over many
+  // different systems the tails' dense matrices outweigh the shared launches
+  // they save
+  const bool tails = bsys.size() == 1;
+  const LevelPlan po = plan_levels(ho, tails);
+  const LevelPlan pg = gsys.empty() ? LevelPlan{} : plan_levels(hg, tails);
   const int64_t no1 = po.n[0], ng1 = gsys.empty() ? 0 : pg.n[0];
   if (kb * (no1 + ng1) > std::numeric_limits<int32_t>::max()) raise(MDP_EINVAL, "batch exceeds int32 indexing");
   n_o = static_cast<int32_t>(kb * no1);
@@ -1929,9 +1935,9 @@ void Batch::build(const std::vector<const Solver *> &pairs, hipStream_t s, bool 
   upload_vec(gpair, keep.put(std::move(gpair_h)), s);
   if (npairs > 1) A.rowpair = dptr<const int>(gpair);
   if (opt.precision == MDP_MIXED)
-    pc32 = upload_precond<float>(hsys, po, pg, gsys, opt, s, kb);
+    pc32 = upload_precond<float>(hsys, po, pg, gsys, opt, tails, s, kb);
   else
-    pc64 = upload_precond<double>(hsys, po, pg, gsys, opt, s, kb);
+    pc64 = upload_precond<double>(hsys, po, pg, gsys, opt, tails, s, kb);
   layout.build(ranges, n, s);
   if (std::getenv("MDP_SETUP_VERBOSE"))
     std::fprintf(stderr, "[mdp] batch: %d pairs, %d right-hand-side blocks of %d systems, n=%d\n", npairs, kb, nsys,
