@@ -549,8 +549,18 @@ __global__ __launch_bounds__(kThreads) void dense_gemv_batched_kernel(const Dens
   if (row >= d.n) return;
   const double *a = ainv + d.inv_off + static_cast<int64_t>(row) * d.n;
   const T *bb = b + d.row;
-  double s = 0.0;
-  for (int j = lane; j < d.n; j += 64) s += a[j] * static_cast<double>(bb[j]);
+  // four partial sums, so that four loads per lane are in flight (few rows
+  // per system: the wavefronts alone cannot hide the latency)
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = lane;
+  for (; j + 192 < d.n; j += 256) {
+    s0 += a[j] * static_cast<double>(bb[j]);
+    s1 += a[j + 64] * static_cast<double>(bb[j + 64]);
+    s2 += a[j + 128] * static_cast<double>(bb[j + 128]);
+    s3 += a[j + 192] * static_cast<double>(bb[j + 192]);
+  }
+  for (; j < d.n; j += 64) s0 += a[j] * static_cast<double>(bb[j]);
+  double s = (s0 + s1) + (s2 + s3);
   s = group_sum<64>(s);
   if (lane == 0) x[d.row + row] = static_cast<T>(s);
 }
