@@ -156,7 +156,11 @@ typedef struct {
   int32_t post_sweeps;    /* l1-Jacobi sweeps after it (1; 1..8)                       */
   double strength_theta;  /* SA strength threshold (0.02)                              */
   int32_t max_coarse;     /* stop coarsening at or below this size (400)               */
-  int32_t max_dense;      /* coarsest solved densely up to this size (2000)            */
+  int32_t max_dense;      /* coarsest solved densely up to this size (2000); with
+                             l1-Jacobi smoothing, a one-system solve also runs the
+                             V-cycle from its first level l >= 1 of at most this size
+                             down as one dense product (the same operator, formed at
+                             upload in FP64)                                         */
   int32_t max_levels;     /* at most this many levels per hierarchy (10)               */
   int32_t restart;        /* FGMRES restart length m (64, at most 64)                  */
   int32_t max_iter;       /* total preconditioner applications per solve (1000)       */
