@@ -120,6 +120,42 @@ HCsr build_rows(int32_t nr, int32_t nc, RowFn &&fn, const std::vector<int64_t> *
   return out;
 }
 
+// Build a matrix in two parallel passes over its rows, for rows that are
+// cheap to form twice (merges): emit(i, put) calls put(col, val) for each
+// entry of row i in order; the first pass only counts them, the second writes
+// them in place.  The result does not depend on the number of threads.
+template <class Emit>
+HCsr build_rows_twice(int32_t nr, int32_t nc, Emit &&emit) {
+  HCsr out = HCsr::empty(nr, nc);
+  std::vector<int32_t> cnt(static_cast<size_t>(nr), 0);
+  parallel_chunks(nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t c = 0;
+      emit(static_cast<int32_t>(i), [&c](int32_t, double) { ++c; });
+      cnt[i] = c;
+    }
+  });
+  int64_t acc = 0;
+  for (int32_t i = 0; i < nr; ++i) {
+    acc += cnt[i];
+    if (acc > INT32_MAX) throw std::length_error("matrix exceeds int32 indexing");
+    out.ptr[i + 1] = static_cast<int32_t>(acc);
+  }
+  out.col.resize(static_cast<size_t>(acc));
+  out.val.resize(static_cast<size_t>(acc));
+  parallel_chunks(nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t q = out.ptr[i];
+      emit(static_cast<int32_t>(i), [&](int32_t c, double v) {
+        out.col[q] = c;
+        out.val[q] = v;
+        ++q;
+      });
+    }
+  });
+  return out;
+}
+
 // Sort the column indices of every row (values follow); duplicate columns are
 // summed in their stored order.
 inline void sort_rows(HCsr &a) {
@@ -253,23 +289,18 @@ inline HCsr spgemm(const HCsr &a, const HCsr &b) {
 // that are exactly zero are dropped.
 inline HCsr subtract(const HCsr &a, const HCsr &b) {
   if (a.nr != b.nr || a.nc != b.nc) throw std::invalid_argument("subtract shape mismatch");
-  return build_rows(a.nr, a.nc, [&](int32_t i, int, std::vector<int32_t> &C, std::vector<double> &V) {
+  return build_rows_twice(a.nr, a.nc, [&](int32_t i, auto &&put) {
     int32_t p = a.ptr[i], pe = a.ptr[i + 1], q = b.ptr[i], qe = b.ptr[i + 1];
     while (p < pe || q < qe) {
       if (q >= qe || (p < pe && a.col[p] < b.col[q])) {
-        C.push_back(a.col[p]);
-        V.push_back(a.val[p]);
+        put(a.col[p], a.val[p]);
         ++p;
       } else if (p >= pe || b.col[q] < a.col[p]) {
-        C.push_back(b.col[q]);
-        V.push_back(-b.val[q]);
+        put(b.col[q], -b.val[q]);
         ++q;
       } else {
         const double v = a.val[p] - b.val[q];
-        if (v != 0.0) {
-          C.push_back(a.col[p]);
-          V.push_back(v);
-        }
+        if (v != 0.0) put(a.col[p], v);
         ++p;
         ++q;
       }

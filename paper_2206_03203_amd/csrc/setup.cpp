@@ -254,23 +254,18 @@ HCsr fused_restriction(const HLevel &L, const HCsr &ra) {
   const HCsr &r = L.R;
   const std::vector<double> &d = L.dl1;
   if (r.nr != ra.nr || r.nc != ra.nc) throw std::invalid_argument("fused restriction shape mismatch");
-  HCsr f = build_rows(r.nr, r.nc, [&](int32_t i, int, std::vector<int32_t> &C, std::vector<double> &V) {
+  HCsr f = build_rows_twice(r.nr, r.nc, [&](int32_t i, auto &&put) {
     int32_t p = r.ptr[i], pe = r.ptr[i + 1], q = ra.ptr[i], qe = ra.ptr[i + 1];
     while (p < pe || q < qe) {
       if (q >= qe || (p < pe && r.col[p] < ra.col[q])) {
-        C.push_back(r.col[p]);
-        V.push_back(r.val[p]);
+        put(r.col[p], r.val[p]);
         ++p;
       } else if (p >= pe || ra.col[q] < r.col[p]) {
-        C.push_back(ra.col[q]);
-        V.push_back(-(ra.val[q] / d[static_cast<size_t>(ra.col[q])]));
+        put(ra.col[q], -(ra.val[q] / d[static_cast<size_t>(ra.col[q])]));
         ++q;
       } else {
         const double v = r.val[p] - ra.val[q] / d[static_cast<size_t>(ra.col[q])];
-        if (v != 0.0) {
-          C.push_back(r.col[p]);
-          V.push_back(v);
-        }
+        if (v != 0.0) put(r.col[p], v);
         ++p;
         ++q;
       }
