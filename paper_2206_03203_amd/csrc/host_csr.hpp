@@ -158,21 +158,26 @@ HCsr build_rows_twice(int32_t nr, int32_t nc, Emit &&emit) {
 
 // Sort the column indices of every row (values follow); duplicate columns are
 // summed in their stored order.
+// Rows whose columns already increase strictly are kept as they are.
 inline void sort_rows(HCsr &a) {
-  std::vector<std::vector<std::pair<int32_t, double>>> tmp(static_cast<size_t>(setup_workers()));
-  a = build_rows(a.nr, a.nc, [&](int32_t i, int t, std::vector<int32_t> &C, std::vector<double> &V) {
-    auto &row = tmp[t];
+  a = build_rows_twice(a.nr, a.nc, [&](int32_t i, auto &&put) {
+    const int32_t p0 = a.ptr[i], p1 = a.ptr[i + 1];
+    bool sorted = true;
+    for (int32_t p = p0 + 1; p < p1 && sorted; ++p) sorted = a.col[p - 1] < a.col[p];
+    if (sorted) {
+      for (int32_t p = p0; p < p1; ++p) put(a.col[p], a.val[p]);
+      return;
+    }
+    static thread_local std::vector<std::pair<int32_t, double>> row;
     row.clear();
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) row.emplace_back(a.col[p], a.val[p]);
+    for (int32_t p = p0; p < p1; ++p) row.emplace_back(a.col[p], a.val[p]);
     std::stable_sort(row.begin(), row.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
-    const size_t start = C.size();
-    for (const auto &e : row) {
-      if (C.size() > start && C.back() == e.first) {
-        V.back() += e.second;
-      } else {
-        C.push_back(e.first);
-        V.push_back(e.second);
-      }
+    for (size_t k = 0; k < row.size();) {
+      double v = row[k].second;
+      size_t m = k + 1;
+      for (; m < row.size() && row[m].first == row[k].first; ++m) v += row[m].second;
+      put(row[k].first, v);
+      k = m;
     }
   });
 }
@@ -353,17 +358,13 @@ inline std::vector<double> l1_row_norms(const HCsr &a) {
 // old -> new via colmap; colmap[c] = -1 drops the column).
 inline HCsr extract(const HCsr &a, const std::vector<int32_t> &rows,
                     const std::vector<int32_t> &colmap, int32_t ncols) {
-  return build_rows(static_cast<int32_t>(rows.size()), ncols,
-                    [&](int32_t r, int, std::vector<int32_t> &C, std::vector<double> &V) {
-                      const int32_t i = rows[r];
-                      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
-                        const int32_t c = colmap[a.col[p]];
-                        if (c >= 0) {
-                          C.push_back(c);
-                          V.push_back(a.val[p]);
-                        }
-                      }
-                    });
+  return build_rows_twice(static_cast<int32_t>(rows.size()), ncols, [&](int32_t r, auto &&put) {
+    const int32_t i = rows[r];
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+      const int32_t c = colmap[a.col[p]];
+      if (c >= 0) put(c, a.val[p]);
+    }
+  });
 }
 
 }  // namespace mdp

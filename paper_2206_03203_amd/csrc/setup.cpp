@@ -73,16 +73,30 @@ void check_diag(const HCsr &a, const char *what) {
 void strength(const HCsr &a, double theta, const int32_t *labels, std::vector<int32_t> &sp,
               std::vector<int32_t> &sc) {
   const std::vector<double> d = diagonal(a);
+  // two parallel passes over the rows: count the strong neighbours, then
+  // write them at their row offsets
+  auto strong = [&](int32_t i, int32_t p) {
+    const int32_t j = a.col[p];
+    if (j == i || (labels && labels[j] != labels[i])) return false;
+    return std::fabs(a.val[p]) >= theta * std::sqrt(std::fabs(d[i] * d[j]));
+  };
   sp.assign(static_cast<size_t>(a.nr) + 1, 0);
-  sc.clear();
-  for (int32_t i = 0; i < a.nr; ++i) {
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
-      const int32_t j = a.col[p];
-      if (j == i || (labels && labels[j] != labels[i])) continue;
-      if (std::fabs(a.val[p]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) sc.push_back(j);
+  parallel_chunks(a.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t c = 0;
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) c += strong(static_cast<int32_t>(i), p);
+      sp[i + 1] = c;
     }
-    sp[i + 1] = static_cast<int32_t>(sc.size());
-  }
+  });
+  for (int32_t i = 0; i < a.nr; ++i) sp[i + 1] += sp[i];
+  sc.resize(static_cast<size_t>(sp[a.nr]));
+  parallel_chunks(a.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t q = sp[i];
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p)
+        if (strong(static_cast<int32_t>(i), p)) sc[q++] = a.col[p];
+    }
+  });
 }
 
 int32_t aggregate(int32_t n, const std::vector<int32_t> &sp, const std::vector<int32_t> &sc,
@@ -140,8 +154,10 @@ HCsr smooth_prolongator(const HCsr &a, const HCsr &pt) {
   for (int32_t i = 0; i < a.nr; ++i) rho = std::max(rho, l1[i] / std::fabs(d[i]));
   const double omega = (4.0 / 3.0) / rho;
   HCsr ap = spgemm(a, pt);
-  for (int32_t i = 0; i < ap.nr; ++i)
-    for (int32_t p = ap.ptr[i]; p < ap.ptr[i + 1]; ++p) ap.val[p] = omega * ((1.0 / d[i]) * ap.val[p]);
+  parallel_chunks(ap.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i)
+      for (int32_t p = ap.ptr[i]; p < ap.ptr[i + 1]; ++p) ap.val[p] = omega * ((1.0 / d[i]) * ap.val[p]);
+  });
   return subtract(pt, ap);
 }
 
@@ -449,17 +465,10 @@ void build_host_system(const mdp_csr *Ain, const int32_t *part, const mdp_option
     if (s.perm[r] != r) s.identity = false;
   }
 
-  HCsr A = HCsr::empty(n, n);
-  A.col.reserve(static_cast<size_t>(Ain->nnz));
-  A.val.reserve(static_cast<size_t>(Ain->nnz));
-  for (int32_t r = 0; r < n; ++r) {
+  HCsr A = build_rows_twice(n, n, [&](int32_t r, auto &&put) {
     const int32_t i = s.perm[r];
-    for (int32_t p = Ain->row_ptr[i]; p < Ain->row_ptr[i + 1]; ++p) {
-      A.col.push_back(inv[Ain->col[p]]);
-      A.val.push_back(Ain->val[p]);
-    }
-    A.ptr[r + 1] = static_cast<int32_t>(A.col.size());
-  }
+    for (int32_t p = Ain->row_ptr[i]; p < Ain->row_ptr[i + 1]; ++p) put(inv[Ain->col[p]], Ain->val[p]);
+  });
   sort_rows(A);
   clk.lap("permute");
 
