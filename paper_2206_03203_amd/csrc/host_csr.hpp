@@ -338,19 +338,23 @@ inline bool is_symmetric(const HCsr &a) {
 
 inline std::vector<double> diagonal(const HCsr &a) {
   std::vector<double> d(static_cast<size_t>(std::min(a.nr, a.nc)), 0.0);
-  for (int32_t i = 0; i < a.nr && i < a.nc; ++i)
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p)
-      if (a.col[p] == i) d[i] += a.val[p];
+  parallel_chunks(std::min(a.nr, a.nc), [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i)
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p)
+        if (a.col[p] == i) d[i] += a.val[p];
+  });
   return d;
 }
 
 inline std::vector<double> l1_row_norms(const HCsr &a) {
   std::vector<double> d(static_cast<size_t>(a.nr), 0.0);
-  for (int32_t i = 0; i < a.nr; ++i) {
-    double s = 0.0;
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) s += std::fabs(a.val[p]);
-    d[i] = s;
-  }
+  parallel_chunks(a.nr, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      double s = 0.0;
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) s += std::fabs(a.val[p]);
+      d[i] = s;
+    }
+  });
   return d;
 }
 

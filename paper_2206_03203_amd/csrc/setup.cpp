@@ -221,12 +221,20 @@ std::vector<double> dense_inverse(const HCsr &a) {
 void check_grounded(const HCsr &a, bool symmetric) {
   const int32_t n = a.nr;
   std::vector<double> rs(static_cast<size_t>(n), 0.0), dg(static_cast<size_t>(n), 0.0);
-  for (int32_t i = 0; i < n; ++i)
-    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
-      if (a.col[p] != i && a.val[p] > 0.0) return;  // not an M-matrix pattern: no claim
-      rs[i] += a.val[p];
-      if (a.col[p] == i) dg[i] = a.val[p];
-    }
+  std::vector<char> positive(static_cast<size_t>(setup_workers()), 0);
+  parallel_chunks(n, [&](int64_t b, int64_t e, int t) {
+    for (int64_t i = b; i < e && !positive[t]; ++i)
+      for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+        if (a.col[p] != i && a.val[p] > 0.0) {
+          positive[t] = 1;
+          break;
+        }
+        rs[i] += a.val[p];
+        if (a.col[p] == i) dg[i] = a.val[p];
+      }
+  });
+  for (char c : positive)
+    if (c) return;  // not an M-matrix pattern: no claim
   // walk the transpose from the grounded rows: row j reaches ground when
   // a_ji != 0 for a row i that does
   const HCsr tt = symmetric ? HCsr::empty(0, 0) : transpose(a);
