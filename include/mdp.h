@@ -92,8 +92,9 @@ extern "C" {
                               device (expansion, stable radix sort by
                               row and column, in-order sums): the same
                               matrices bit for bit, so the same hierarchy; a
-                              product that does not fit in free device memory
-                              is formed on the host. */
+                              product of more than 2^29 terms, or one that does
+                              not fit in free device memory, is formed on the
+                              host. */
 #define MDP_NO_AUTOTUNE 4u /* mdp_setup: keep the fixed rule for each matrix's
                               device format instead of timing the candidates
                               (diagonal storage for stencil matrices,
